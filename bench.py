@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused D3Q27 FPC-LBM stream-and-collide step on one MI355X.
+
+Workload (the channel case): 256 x 128 x 128 nodes, walls half a link outside
+y = 0 and y = 127 (halfway bounce-back), periodic in x and z, nu = 0.01,
+constant body force F_x = 8 nu u_max / H^2 with u_max = 0.05 and H = 128,
+starting from rest.  A step is one fused stream + collide launch over all
+nodes.  Inputs are synthetic (no dataset) and already resident in HBM when the
+timed region starts.
+
+Printed (one JSON line): MLUPS of the FP32-storage form as ``value``, the HBM
+roofline of the stream-collide kernel measured with HIP events on the stream
+the kernel runs on, every storage form's MLUPS / roofline fraction / error
+against the analytic start-up profile and against the FP64 run, and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_channel_256x128x128.json")
+KERNEL_SOURCES = ["paper_2410_09739_amd/csrc/lbm.hip", "paper_2410_09739_amd/csrc/fpc_collide.hpp",
+                  "paper_2410_09739_amd/csrc/d3q27.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def analytic_startup(ny: int, nu: float, F: float, t: float, nterms: int = 400) -> np.ndarray:
+    """Start-up of plane Poiseuille flow from rest between walls at y = 0 and H
+    (here the half-link wall positions), u(y, t) for the node centres."""
+    H = float(ny)
+    y = np.arange(ny) + 0.5
+    u = F / (2 * nu) * y * (H - y)
+    for n in range(1, 2 * nterms, 2):
+        u -= 4 * F * H * H / (nu * n ** 3 * np.pi ** 3) * np.sin(n * np.pi * y / H) * np.exp(-n * n * np.pi ** 2 * nu * t / (H * H))
+    return u
+
+
+def run_form(L, torch, storage, shape, nu, F, steps, warmup):
+    nx, ny, nz = shape
+    stream = torch.cuda.Stream()
+    cfg = L.Config(nx, ny, nz, storage=storage, walls_y=True, nu=nu, force=(F, 0.0, 0.0),
+                   hip_stream=stream.cuda_stream)
+    with L.Lattice(cfg) as lat:
+        lat.init()  # rest: rho = 1, u = 0
+        lat.step(warmup)
+        lat.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        lat.step(steps)
+        end.record(stream)
+        end.synchronize()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        _, u = lat.moments()
+        diag = lat.diagnostics()
+    return ms, u, diag
+
+
+def cpu_baseline(shape, nu, F, steps):
+    import oracle as O
+    nx, ny, nz = shape
+    g = O.init(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
+    om = O.omega_table(nu)
+    t0 = time.perf_counter()
+    O.run(g, om, (F, 0.0, 0.0), walls_y=True, steps=steps)
+    dt = time.perf_counter() - t0
+    return nx * ny * nz * steps / dt / 1e6, dt, O.num_threads()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--forms", default="f32,f64,f16dev,bf16dev")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is designed, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2410_09739_amd import lbm as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    shape = (256, 128, 128)
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    nu, umax = 0.01, 0.05
+    F = 8 * nu * umax / ny ** 2
+
+    forms = [s for s in args.forms.split(",") if s]
+    if "f32" not in forms:
+        forms.insert(0, "f32")
+    results, profiles = {}, {}
+    for st in forms:
+        ms, u, diag = run_form(L, torch, st, shape, nu, F, args.steps, args.warmup)
+        sb = L.STORAGE_BYTES[L.STORAGE[st]]
+        ms_step = ms / args.steps
+        bytes_launch = N * 54 * sb
+        gbs = bytes_launch / (ms_step * 1e-3) / 1e9
+        prof = u[0].mean(axis=(0, 2))  # x-z average of u_x(y)
+        t = args.warmup + args.steps - 0.5
+        ua = analytic_startup(ny, nu, F, t)
+        profiles[st] = (u, prof)
+        results[st] = {
+            "mlups": N / (ms_step * 1e-3) / 1e6,
+            "ms_per_step": ms_step,
+            "bytes_per_node": 54 * sb,
+            "achieved_GBs": gbs,
+            "frac_hbm": gbs / HBM_PEAK_GBS,
+            "profile_rel_l2_vs_analytic": float(np.sqrt(np.sum((prof - ua) ** 2) / np.sum(ua ** 2))),
+            "mass_drift": diag["mass"] / N - 1.0,
+        }
+        print(f"# {st}: {results[st]['mlups']:.0f} MLUPS, {gbs:.0f} GB/s, "
+              f"profile err {results[st]['profile_rel_l2_vs_analytic']:.2e}", file=sys.stderr, flush=True)
+    if "f64" in profiles:
+        u64 = profiles["f64"][0]
+        for st in results:
+            results[st]["max_abs_u_err_vs_f64_over_umax"] = float(np.abs(profiles[st][0] - u64).max() / umax)
+
+    main_form = results["f32"]
+    roof = {"bound": "hbm", "achieved": round(main_form["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(main_form["frac_hbm"], 4), "traffic": None}
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_source_sha") == kernel_source_hash() and "f32" in tr.get("forms", {}):
+            roof["traffic"] = tr["forms"]["f32"]["hbm_bytes_per_launch"]
+
+    line = {
+        "metric": "D3Q27 FPC-LBM MLUPS & % HBM peak, FP32 vs FP16-storage at stated error",
+        "value": round(main_form["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_form["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "channel 256x128x128, halfway bounce-back walls in y, body force, nu=0.01, "
+                               "u_max=0.05, from rest; FP32 storage of f - w",
+                   "nx": nx, "ny": ny, "nz": nz, "parallelism": "single GPU"},
+        "roofline": roof,
+        "forms": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                  for k, v in results.items()},
+    }
+    if not args.no_cpu_baseline:
+        cshape = (256, 128, 16)
+        mlups, dt, cores = cpu_baseline(cshape, nu, F, args.cpu_steps)
+        line["cpu_baseline"] = {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+                                "sample": f"{args.cpu_steps} steps of a 256x128x16 slab of the same channel "
+                                          f"(periodic z), FP64, {dt:.1f} s"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D3Q27 Fokker-Planck central-moment
+ * lattice Boltzmann library (FPC-LBM, Schupbach & Premnath, arXiv 2410.09739).
+ *
+ * The library advances a periodic box (optionally bounded by two walls normal
+ * to y) with the fused stream-and-collide update of the paper:
+ *   - collision of Appendix D Steps 1-5: raw moments (Step 1), central moments
+ *     (Step 2, Eq. rmcm), relaxation of each central moment towards its
+ *     Markovian attractor (Step 3, Eqs. Mvcmattractor3D and
+ *     diffusion-tensor-parameter-3D, attractor list of Sec. 3.5) with the
+ *     body-force sources of Eq. (cmupdatesourceD3Q27), and the maps back
+ *     (Steps 4 and 5);
+ *   - streaming, Eq. (LBMsteps-stream) / Appendix D Step 6, with halfway
+ *     bounce-back at the walls (Sec. 4, 3D cavity: stationary walls only);
+ *   - macroscopic fields of Appendix D Step 7: rho = sum f,
+ *     rho u = sum f e + F/2, P = rho c_s^2, c_s^2 = 1/3.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid: nx * ny * nz nodes, node index i = x + nx * (y + ny * z), x fastest.
+ * Populations: 27 per node in the order of the paper's velocity list (Sec. 3.5),
+ *   host arrays are structure-of-arrays f[alpha * N + i], N = nx ny nz.
+ * Time levels: the library stores the post-collision populations f~(t) of the
+ *   last completed step.  lbm_init stores f^eq(rho, u) as f~(0).  One call of
+ *   lbm_step(c, 1) streams f~(t) (Step 6), takes rho and u (Step 7) and collides
+ *   (Steps 1-5) to f~(t+1).  lbm_moments reports the Step 7 fields of the
+ *   pre-collision state at t: rho = sum f~, rho u = sum f~ e - F/2 (the
+ *   collision adds exactly F to sum f e).
+ * Walls: walls_y = 1 puts stationary no-slip walls half a link below y = 0 and
+ *   half a link above y = ny - 1; x and z stay periodic.
+ * Storage forms: the distributions are held as deviations f - w_alpha from the
+ *   D3Q27 lattice weights (8/27, 2/27, 1/54, 1/216), in FP64, FP32, FP16 or
+ *   BF16.  FP16 and BF16 values carry an exact power-of-two scale per weight
+ *   class; arithmetic is FP64 for LBM_F64 and FP32 otherwise.
+ * Streams: every device operation is enqueued on the configured HIP stream.
+ * Errors: functions return LBM_OK (0) or a negative code; lbm_last_error gives
+ *   a text.  No entry point throws, aborts or exits.
+ * Ownership: the library owns the device memory it allocates (two state
+ *   buffers of 27 * N values plus small scratch); every pointer the caller
+ *   passes stays the caller's and is never retained past the call.
+ * Threads: one context must not be used by two host threads at once.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_EINVAL (-1)    /* invalid argument or configuration            */
+#define LBM_ENOMEM (-2)    /* device or host allocation failed             */
+#define LBM_EHIP (-3)      /* HIP runtime error (text in lbm_last_error)   */
+#define LBM_EUNSTABLE (-4) /* diagnostics found non-finite values or rho<=0 */
+#define LBM_ESTATE (-5)    /* call out of order (e.g. step before init)    */
+
+#define LBM_Q 27
+#define LBM_CLOSURE_NIN 27
+#define LBM_CLOSURE_NHID 64
+#define LBM_CLOSURE_NOUT 6
+/* W1[64][27] b1[64] W2[64][64] b2[64] W3[6][64] b3[6] */
+#define LBM_CLOSURE_NPARAM 6342
+
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2, LBM_BF16DEV = 3 } lbm_storage;
+
+/* How the 27 relaxation rates omega_0..omega_26 (Appendix D numbering) are set.
+ * In all modes omega_4,5,6,8,9 come from the shear viscosity through
+ * Eq. (transportcoeff3DFPCLBM), 1/omega = nu / c_s^2 + 1/2, and omega_7 is
+ * omega_bulk (bulk viscosity zeta = (2/3) c_s^2 (1/omega_7 - 1/2)), except in
+ * LBM_OMEGA_EXPLICIT.
+ *   LBM_OMEGA_PAPER        omega_0..3 = 1 (no effect), omega_10..26 = omega_higher
+ *                          (the paper's runs use 1 for these and for omega_7).
+ *   LBM_OMEGA_ORDER_SCALED moments of order n >= 3 take the order-scaled rate of
+ *                          Eq. (FPcoll3d), omega_n = (n/2) omega_2, through the
+ *                          Henon correction: 1/omega_n - 1/2 = (2/n)(1/omega_2 - 1/2).
+ *   LBM_OMEGA_EXPLICIT     omega[] is used as given.
+ * Every rate must lie in (0, 2). */
+typedef enum { LBM_OMEGA_PAPER = 0, LBM_OMEGA_ORDER_SCALED = 1, LBM_OMEGA_EXPLICIT = 2 } lbm_omega_mode;
+
+typedef struct {
+  int32_t nx, ny, nz;   /* >= 1 each; N = nx*ny*nz must be < 2^31              */
+  int32_t storage;      /* lbm_storage                                          */
+  int32_t walls_y;      /* 0: periodic in y; 1: halfway bounce-back walls in y  */
+  int32_t omega_mode;   /* lbm_omega_mode                                       */
+  double nu;            /* shear viscosity, lattice units (> 0 unless EXPLICIT) */
+  double omega_bulk;    /* omega_7                                              */
+  double omega_higher;  /* omega_10..26 in LBM_OMEGA_PAPER                      */
+  double omega[LBM_Q];  /* LBM_OMEGA_EXPLICIT only                              */
+  double force[3];      /* body force per unit volume, lattice units, dt = 1    */
+  void* hip_stream;     /* hipStream_t to run on; NULL: the library makes one   */
+} lbm_config;
+
+typedef struct {
+  double mass;            /* sum rho                                              */
+  double momentum[3];     /* sum rho u (Step 7 definition)                        */
+  double kinetic_energy;  /* 1/2 sum rho |u|^2                                    */
+  double enstrophy;       /* 1/2 sum |curl u|^2, centred differences (periodic;   */
+                          /* antisymmetric ghost layer at the half-link walls)    */
+  double wall_force[3];   /* force of the fluid on the walls: sum over bounce-back */
+                          /* links of 2 f~_alpha e_alpha (zero without walls)     */
+  double max_speed;       /* max |u|                                              */
+  double min_rho;         /* min rho                                              */
+  int64_t n_nonfinite;    /* nodes with a non-finite population                   */
+  int64_t step;           /* completed time steps                                 */
+} lbm_diag;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Fills cfg with defaults: 0 sizes, LBM_F32, periodic, LBM_OMEGA_PAPER,
+ * nu = 1/6, omega_bulk = omega_higher = 1, zero force, NULL stream. */
+void lbm_config_default(lbm_config* cfg);
+
+/* Host-only: the 27 rates the configuration implies (no GPU needed).
+ * Returns LBM_EINVAL (with no output written) if any rate falls outside (0,2). */
+int lbm_omega_table(const lbm_config* cfg, double omega_out[LBM_Q]);
+
+/* Validates cfg, allocates the two device state buffers and scratch on the
+ * current HIP device.  *out receives the context (NULL on error; the error text
+ * is then available from lbm_last_error(NULL)). */
+int lbm_create(const lbm_config* cfg, lbm_ctx** out);
+
+/* Stores f~(0) = f^eq(rho, u) at every node, where f^eq has the equilibrium
+ * central moments rho c_a c_b c_c (c_0 = 1, c_1 = 0, c_2 = c_s^2) of the
+ * attractor list of Sec. 3.5 about velocity u.  rho: host array [N] or NULL
+ * (rho = 1); u: host array [3][N] (SoA) or NULL (u = 0).  Resets the step count.
+ * Synchronous. */
+int lbm_init(lbm_ctx* c, const double* rho, const double* u);
+
+/* Enqueues n >= 0 fused stream-and-collide steps; returns once they are queued. */
+int lbm_step(lbm_ctx* c, int64_t n);
+
+/* Blocks until all work queued on the context's stream has finished. */
+int lbm_synchronize(lbm_ctx* c);
+
+/* Step 7 fields of the current time level to host arrays rho [N] and u [3][N]
+ * (either may be NULL).  Synchronous. */
+int lbm_moments(lbm_ctx* c, double* rho, double* u);
+
+/* Same fields into caller-owned device memory, enqueued on the stream:
+ * rho_dev [N], u_dev [3][N]; element type double if f64 != 0, else float. */
+int lbm_moments_device(lbm_ctx* c, void* rho_dev, void* u_dev, int32_t f64);
+
+/* FP64 reductions over the current state (deterministic order).  Synchronous.
+ * Returns LBM_EUNSTABLE (after filling *out) if a population is non-finite or
+ * some rho <= 0. */
+int lbm_diagnostics(lbm_ctx* c, lbm_diag* out);
+
+/* Checkpoint / parity access to the stored post-collision populations f~ as
+ * host FP64 [27][N].  lbm_set_f rounds to the storage form (round to nearest
+ * even) and marks the context initialised.  Synchronous. */
+int lbm_get_f(lbm_ctx* c, double* f);
+int lbm_set_f(lbm_ctx* c, const double* f);
+
+/* Bit-exact checkpoint of the raw storage (27 * N values of the storage type,
+ * deviations, SoA).  nbytes must equal lbm_state_bytes(c).  Synchronous. */
+int64_t lbm_state_bytes(const lbm_ctx* c);
+int lbm_get_raw(lbm_ctx* c, void* host, int64_t nbytes);
+int lbm_set_raw(lbm_ctx* c, const void* host, int64_t nbytes);
+
+/* The HIP stream the context runs on (a hipStream_t). */
+void* lbm_stream(const lbm_ctx* c);
+
+/* Completed time steps since lbm_init / lbm_set_f / lbm_set_raw. */
+int64_t lbm_step_count(const lbm_ctx* c);
+
+/* Releases every resource of c (NULL is ignored).  Synchronizes first. */
+void lbm_destroy(lbm_ctx* c);
+
+/* Last error text of c, or of the last failed lbm_create when c is NULL.
+ * Valid until the next call on the same context. */
+const char* lbm_last_error(const lbm_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

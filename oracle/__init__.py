@@ -63,6 +63,7 @@ def _load():
         lib.orc_stream.argtypes = [ctypes.c_int] * 4 + [_dp, _dp]
         lib.orc_run.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, ctypes.c_int]
         lib.orc_run.restype = ctypes.c_int
+        lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_step_nodes.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, _i64p, ctypes.c_int64, _dp]
         _lib = lib
     return _lib
@@ -201,6 +202,11 @@ def step_nodes(g: np.ndarray, sel, omega, force=(0.0, 0.0, 0.0), walls_y: bool =
     lib.orc_step_nodes(nx, ny, nz, int(bool(walls_y)), _d(_f64(omega)), _d(_f64(force)), _d(g),
                        sel.ctypes.data_as(_i64p), sel.size, _d(out))
     return out
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's lattice loops use."""
+    return int(_load().orc_num_threads())
 
 
 def macroscopic(state: np.ndarray, force=(0.0, 0.0, 0.0), post_collision: bool = True):

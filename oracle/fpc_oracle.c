@@ -42,6 +42,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 27
 
@@ -459,4 +462,13 @@ void orc_step_nodes(int nx, int ny, int nz, int walls_y, const double* omega, co
     orc_collide_node(fi, omega, F, fo, NULL, NULL);
     for (int a = 0; a < Q; ++a) out[a * nsel + s] = fo[a];
   }
+}
+
+/* threads the OpenMP loops above will use (for reporting the baseline) */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -1,0 +1,288 @@
+// fpc_collide.hpp -- per-node FPC-LBM collision in registers (device code).
+//
+// The state of one node is a 3x3x3 register cube v[iz][iy][ix] indexed by the
+// velocity (ix = e_x + 1, ...).  It holds deviations delta = f - w_alpha from
+// the lattice weights, never f itself, so that FP32 arithmetic keeps the small
+// non-equilibrium and force contributions (the weights would otherwise take
+// most of the mantissa).
+//
+// Raw and central moments of the paper (Appendix D Steps 1 and 2: m = P f,
+// kappa = F(u) m) are both tensor products over the three axes, because the
+// D3Q27 moment set is {0,1,2}^3.  So kappa = F(u) P f is computed as three
+// sweeps of a 3-point transform, one per axis, that map the values at
+// e = -1, 0, +1 straight to the central moments of order 0, 1, 2 about u_d.
+// Each sweep also carries the rest state's contribution as a compile-time
+// constant W, so that the cube ends up holding kappa' = kappa - E with
+// E_abc = C1[a] C1[b] C1[c] the rest-state central moments (C1 = 1, 0, c_s^2).
+// Steps 4 and 5 (m~ = F^-1 kappa~, f~ = P^-1 m~) are the inverse sweeps.
+//
+// The collision (Step 3) relaxes the primed moments in the paper's order:
+// orders 0-2 (grouped 2s1/2d1/2d2), decomposition, order 3 (3s*/3m*, 111),
+// decomposition, order 4 with attractors from post-collision order 2
+// (4s1/4d1/4d2, 211/121/112), decomposition, order 5 from post-collision
+// orders 2 and 3, order 6 from post-collision orders 2 and 4.  Attractors are
+// those of Sec. 3.5 (Eq. Mvcmattractor3D with the diffusion tensor of
+// Eq. diffusion-tensor-parameter-3D), rewritten exactly for primed moments;
+// sources follow Eq. (cmupdatesourceD3Q27) with the pre-collision moments,
+// kappa_000 = rho and first-order moments taken as zero.  kappa^Mv_122 uses the
+// product kappa~_110 kappa~_012 that the general attractor formula gives.
+#pragma once
+
+#include "d3q27.hpp"
+
+namespace fpc {
+
+template <typename T>
+struct Rates {
+  T w[Q];   // omega_0 .. omega_26 (Appendix D numbering)
+  T h[Q];   // 1 - omega_j / 2
+};
+
+// ---------------------------------------------------------------------------
+// 3-point sweeps.  Forward: values (dm, d0, dp) at e = -1, 0, +1, deviations
+// from W * (1/6, 2/3, 1/6)  ->  central moments (r0, r1, r2) about u, minus
+// W * (1, 0, 1/3).
+template <typename T, int WNUM_IS_ZERO>
+__device__ __forceinline__ void fwd3(T& a0, T& a1, T& a2, T u, T W) {
+  const T s0 = a0 + a1 + a2;
+  const T d1 = a2 - a0;
+  const T sp = a2 + a0;
+  const T S = WNUM_IS_ZERO ? s0 : s0 + W;
+  a0 = s0;
+  a1 = d1 - u * S;
+  a2 = sp - T(2) * u * d1 + u * u * S;
+}
+
+// Inverse: (r0, r1, r2) as produced by fwd3 -> deviations at e = -1, 0, +1.
+template <typename T, int WNUM_IS_ZERO>
+__device__ __forceinline__ void inv3(T& a0, T& a1, T& a2, T u, T W) {
+  const T r0 = a0, r1 = a1, r2 = a2;
+  const T R0 = WNUM_IS_ZERO ? r0 : r0 + W;
+  const T u2 = u * u;
+  a1 = r0 - R0 * u2 - T(2) * u * r1 - r2;
+  a2 = T(0.5) * (R0 * (u2 + u) + r1 * (T(2) * u + T(1)) + r2);
+  a0 = T(0.5) * (R0 * (u2 - u) + r1 * (T(2) * u - T(1)) + r2);
+}
+
+#define FPC_FWD(T, ZERO, a, b, c, u, W) fwd3<T, ZERO>(a, b, c, u, T(W))
+#define FPC_INV(T, ZERO, a, b, c, u, W) inv3<T, ZERO>(a, b, c, u, T(W))
+
+// Forward sweeps over the cube (x, then y, then z).  On return v[c][b][a] holds
+// kappa'_abc.  The x sweep is split so that rho and j come out of its line sums.
+template <typename T>
+__device__ __forceinline__ void forward_x(T (&v)[3][3][3], T ux) {
+#pragma unroll
+  for (int iz = 0; iz < 3; ++iz)
+#pragma unroll
+    for (int iy = 0; iy < 3; ++iy)
+      fwd3<T, 0>(v[iz][iy][0], v[iz][iy][1], v[iz][iy][2], ux, T(W1[iy] * W1[iz]));
+}
+
+template <typename T>
+__device__ __forceinline__ void forward_yz(T (&v)[3][3][3], T uy, T uz) {
+#pragma unroll
+  for (int iz = 0; iz < 3; ++iz) {
+    fwd3<T, 0>(v[iz][0][0], v[iz][1][0], v[iz][2][0], uy, T(C1[0] * W1[iz]));
+    fwd3<T, 1>(v[iz][0][1], v[iz][1][1], v[iz][2][1], uy, T(0));
+    fwd3<T, 0>(v[iz][0][2], v[iz][1][2], v[iz][2][2], uy, T(C1[2] * W1[iz]));
+  }
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a == 1 || b == 1)
+        fwd3<T, 1>(v[0][b][a], v[1][b][a], v[2][b][a], uz, T(0));
+      else
+        fwd3<T, 0>(v[0][b][a], v[1][b][a], v[2][b][a], uz, T(C1[a] * C1[b]));
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void inverse_all(T (&v)[3][3][3], T ux, T uy, T uz) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a == 1 || b == 1)
+        inv3<T, 1>(v[0][b][a], v[1][b][a], v[2][b][a], uz, T(0));
+      else
+        inv3<T, 0>(v[0][b][a], v[1][b][a], v[2][b][a], uz, T(C1[a] * C1[b]));
+    }
+#pragma unroll
+  for (int iz = 0; iz < 3; ++iz) {
+    inv3<T, 0>(v[iz][0][0], v[iz][1][0], v[iz][2][0], uy, T(C1[0] * W1[iz]));
+    inv3<T, 1>(v[iz][0][1], v[iz][1][1], v[iz][2][1], uy, T(0));
+    inv3<T, 0>(v[iz][0][2], v[iz][1][2], v[iz][2][2], uy, T(C1[2] * W1[iz]));
+  }
+#pragma unroll
+  for (int iz = 0; iz < 3; ++iz)
+#pragma unroll
+    for (int iy = 0; iy < 3; ++iy)
+      inv3<T, 0>(v[iz][iy][0], v[iz][iy][1], v[iz][iy][2], ux, T(W1[iy] * W1[iz]));
+}
+
+// Macroscopic fields from the deviation cube: rho' = sum delta, j = sum delta e.
+template <typename T>
+__device__ __forceinline__ void density_momentum(const T (&v)[3][3][3], T& rhop, T& jx, T& jy, T& jz) {
+  T s[3][3];
+  jx = T(0);
+#pragma unroll
+  for (int iz = 0; iz < 3; ++iz)
+#pragma unroll
+    for (int iy = 0; iy < 3; ++iy) {
+      s[iz][iy] = v[iz][iy][0] + v[iz][iy][1] + v[iz][iy][2];
+      jx += v[iz][iy][2] - v[iz][iy][0];
+    }
+  jy = (s[0][2] - s[0][0]) + (s[1][2] - s[1][0]) + (s[2][2] - s[2][0]);
+  jz = (s[2][0] - s[0][0]) + (s[2][1] - s[0][1]) + (s[2][2] - s[0][2]);
+  rhop = (s[0][0] + s[0][1] + s[0][2]) + (s[1][0] + s[1][1] + s[1][2]) + (s[2][0] + s[2][1] + s[2][2]);
+}
+
+// ---------------------------------------------------------------------------
+// Collision of one node.  v: deviation cube in, post-collision deviations out.
+// F: body force.  ws[6]: the second-order rates omega_4..omega_9 to use at this
+// node (the rates table, or a per-node closure).  Returns rho and u (Step 7).
+template <typename T, bool FORCE>
+__device__ __forceinline__ void collide(T (&v)[3][3][3], const Rates<T>& R, const T (&ws)[6],
+                                        T Fx, T Fy, T Fz, T& rho_out, T& ux, T& uy, T& uz) {
+  const T third = T(1.0 / 3.0), ninth = T(1.0 / 9.0);
+  T rhop, jx, jy, jz;
+  density_momentum(v, rhop, jx, jy, jz);
+  const T rho = T(1) + rhop;
+  const T ir = T(1) / rho;
+  if (FORCE) {
+    jx += T(0.5) * Fx;
+    jy += T(0.5) * Fy;
+    jz += T(0.5) * Fz;
+  }
+  ux = jx * ir;
+  uy = jy * ir;
+  uz = jz * ir;
+  rho_out = rho;
+
+  forward_x(v, ux);
+  forward_yz(v, uy, uz);
+
+  // pre-collision primed central moments (v[c][b][a] = kappa'_abc)
+  const T k100 = v[0][0][1], k010 = v[0][1][0], k001 = v[1][0][0];
+  const T k110 = v[0][1][1], k101 = v[1][0][1], k011 = v[1][1][0];
+  const T k200 = v[0][0][2], k020 = v[0][2][0], k002 = v[2][0][0];
+  const T k120 = v[0][2][1], k102 = v[2][0][1], k210 = v[0][1][2];
+  const T k012 = v[2][1][0], k201 = v[1][0][2], k021 = v[1][2][0];
+  const T k111 = v[1][1][1];
+  const T k220 = v[0][2][2], k202 = v[2][0][2], k022 = v[2][2][0];
+  const T k211 = v[1][1][2], k121 = v[1][2][1], k112 = v[2][1][1];
+  const T k122 = v[2][2][1], k212 = v[2][1][2], k221 = v[1][2][2];
+  const T k222 = v[2][2][2];
+
+  // sources sigma_abc = a gx K_(a-1)bc + b gy K_a(b-1)c + c gz K_ab(c-1), full K = E + kappa'
+  T s100 = 0, s010 = 0, s001 = 0;
+  T s120 = 0, s102 = 0, s210 = 0, s012 = 0, s201 = 0, s021 = 0, s111 = 0;
+  T s220 = 0, s202 = 0, s022 = 0, s211 = 0, s121 = 0, s112 = 0;
+  T s122 = 0, s212 = 0, s221 = 0, s222 = 0;
+  if (FORCE) {
+    const T gx = Fx * ir, gy = Fy * ir, gz = Fz * ir;
+    const T K200 = third + k200, K020 = third + k020, K002 = third + k002;
+    const T K220 = ninth + k220, K202 = ninth + k202, K022 = ninth + k022;
+    s100 = Fx;
+    s010 = Fy;
+    s001 = Fz;
+    s120 = gx * K020 + T(2) * gy * k110;
+    s102 = gx * K002 + T(2) * gz * k101;
+    s210 = T(2) * gx * k110 + gy * K200;
+    s012 = gy * K002 + T(2) * gz * k011;
+    s201 = T(2) * gx * k101 + gz * K200;
+    s021 = T(2) * gy * k011 + gz * K020;
+    s111 = gx * k011 + gy * k101 + gz * k110;
+    s220 = T(2) * (gx * k120 + gy * k210);
+    s202 = T(2) * (gx * k102 + gz * k201);
+    s022 = T(2) * (gy * k012 + gz * k021);
+    s211 = T(2) * gx * k111 + gy * k201 + gz * k210;
+    s121 = gx * k021 + T(2) * gy * k111 + gz * k120;
+    s112 = gx * k012 + gy * k102 + T(2) * gz * k111;
+    s122 = gx * K022 + T(2) * (gy * k112 + gz * k121);
+    s212 = gy * K202 + T(2) * (gx * k112 + gz * k211);
+    s221 = gz * K220 + T(2) * (gx * k121 + gy * k211);
+    s222 = T(2) * (gx * k122 + gy * k212 + gz * k221);
+  }
+
+  // ---- orders 0-2.  kappa~_000 = rho' (conserved); first order: attractor 0.
+  const T t100 = k100 - R.w[1] * k100 + R.h[1] * s100;
+  const T t010 = k010 - R.w[2] * k010 + R.h[2] * s010;
+  const T t001 = k001 - R.w[3] * k001 + R.h[3] * s001;
+  const T t110 = (T(1) - ws[0]) * k110;  // sigma_110 = 0
+  const T t101 = (T(1) - ws[1]) * k101;
+  const T t011 = (T(1) - ws[2]) * k011;
+  const T c2s1 = k200 + k020 + k002;      // primed: attractor rho c_s^2 * 3 -> rho'
+  const T c2d1 = k200 - k020, c2d2 = k200 - k002;
+  const T t2s1 = c2s1 + ws[3] * (rhop - c2s1);  // sigma_200 = sigma_020 = sigma_002 = 0
+  const T t2d1 = (T(1) - ws[4]) * c2d1;
+  const T t2d2 = (T(1) - ws[5]) * c2d2;
+  const T t200 = third * (t2s1 + t2d1 + t2d2);
+  const T t020 = third * (t2s1 - T(2) * t2d1 + t2d2);
+  const T t002 = third * (t2s1 + t2d1 - T(2) * t2d2);
+
+  // ---- order 3: attractors 0.
+  const T t3s1 = (T(1) - R.w[10]) * (k120 + k102) + R.h[10] * (s120 + s102);
+  const T t3m1 = (T(1) - R.w[11]) * (k120 - k102) + R.h[11] * (s120 - s102);
+  const T t3s2 = (T(1) - R.w[12]) * (k210 + k012) + R.h[12] * (s210 + s012);
+  const T t3m2 = (T(1) - R.w[13]) * (k210 - k012) + R.h[13] * (s210 - s012);
+  const T t3s3 = (T(1) - R.w[14]) * (k201 + k021) + R.h[14] * (s201 + s021);
+  const T t3m3 = (T(1) - R.w[15]) * (k201 - k021) + R.h[15] * (s201 - s021);
+  const T t111 = (T(1) - R.w[16]) * k111 + R.h[16] * s111;
+  const T t120 = T(0.5) * (t3s1 + t3m1), t102 = T(0.5) * (t3s1 - t3m1);
+  const T t210 = T(0.5) * (t3s2 + t3m2), t012 = T(0.5) * (t3s2 - t3m2);
+  const T t201 = T(0.5) * (t3s3 + t3m3), t021 = T(0.5) * (t3s3 - t3m3);
+
+  // ---- order 4: attractors from post-collision order 2 (primed form of
+  // (K200 K020 + 2 K110^2)/rho - 1/9 etc.).
+  const T m220 = ((t200 + t020) * third + t200 * t020 + T(2) * t110 * t110 - ninth * rhop) * ir;
+  const T m202 = ((t200 + t002) * third + t200 * t002 + T(2) * t101 * t101 - ninth * rhop) * ir;
+  const T m022 = ((t020 + t002) * third + t020 * t002 + T(2) * t011 * t011 - ninth * rhop) * ir;
+  const T A2 = third + t200, B2 = third + t020, C2 = third + t002;  // full post-collision order 2
+  const T m211 = (A2 * t011 + T(2) * t110 * t101) * ir;
+  const T m121 = (B2 * t101 + T(2) * t110 * t011) * ir;
+  const T m112 = (C2 * t110 + T(2) * t011 * t101) * ir;
+  const T c4s1 = k220 + k202 + k022, c4d1 = k220 + k202 - k022, c4d2 = k220 - k202;
+  const T t4s1 = c4s1 + R.w[17] * ((m220 + m202 + m022) - c4s1) + R.h[17] * (s220 + s202 + s022);
+  const T t4d1 = c4d1 + R.w[18] * ((m220 + m202 - m022) - c4d1) + R.h[18] * (s220 + s202 - s022);
+  const T t4d2 = c4d2 + R.w[19] * ((m220 - m202) - c4d2) + R.h[19] * (s220 - s202);
+  const T t211 = k211 + R.w[20] * (m211 - k211) + R.h[20] * s211;
+  const T t121 = k121 + R.w[21] * (m121 - k121) + R.h[21] * s121;
+  const T t112 = k112 + R.w[22] * (m112 - k112) + R.h[22] * s112;
+  const T t220 = T(0.25) * (t4s1 + t4d1 + T(2) * t4d2);
+  const T t202 = T(0.25) * (t4s1 + t4d1 - T(2) * t4d2);
+  const T t022 = T(0.5) * (t4s1 - t4d1);
+
+  // ---- order 5: attractors from post-collision orders 2 and 3.
+  const T f5 = T(0.4) * ir;  // 2 / (5 rho)
+  const T m122 = f5 * (B2 * t102 + C2 * t120 + T(4) * t011 * t111 + T(2) * (t101 * t021 + t110 * t012));
+  const T m212 = f5 * (A2 * t012 + C2 * t210 + T(4) * t101 * t111 + T(2) * (t110 * t102 + t011 * t201));
+  const T m221 = f5 * (A2 * t021 + B2 * t201 + T(4) * t110 * t111 + T(2) * (t011 * t210 + t101 * t120));
+  const T t122 = k122 + R.w[23] * (m122 - k122) + R.h[23] * s122;
+  const T t212 = k212 + R.w[24] * (m212 - k212) + R.h[24] * s212;
+  const T t221 = k221 + R.w[25] * (m221 - k221) + R.h[25] * s221;
+
+  // ---- order 6: attractor from post-collision orders 2 and 4 (primed form).
+  const T m222 = ((t200 + t020 + t002) * ninth + (t022 + t202 + t220) * third + t200 * t022 + t020 * t202 +
+                  t002 * t220 + T(4) * (t110 * t112 + t101 * t121 + t011 * t211)) *
+                     (third * ir) -
+                 rhop * (T(1.0 / 27.0) * ir);
+  const T t222 = k222 + R.w[26] * (m222 - k222) + R.h[26] * s222;
+
+  v[0][0][0] = rhop;
+  v[0][0][1] = t100; v[0][1][0] = t010; v[1][0][0] = t001;
+  v[0][1][1] = t110; v[1][0][1] = t101; v[1][1][0] = t011;
+  v[0][0][2] = t200; v[0][2][0] = t020; v[2][0][0] = t002;
+  v[0][2][1] = t120; v[2][0][1] = t102; v[0][1][2] = t210;
+  v[2][1][0] = t012; v[1][0][2] = t201; v[1][2][0] = t021;
+  v[1][1][1] = t111;
+  v[0][2][2] = t220; v[2][0][2] = t202; v[2][2][0] = t022;
+  v[1][1][2] = t211; v[1][2][1] = t121; v[2][1][1] = t112;
+  v[2][2][1] = t122; v[2][1][2] = t212; v[1][2][2] = t221;
+  v[2][2][2] = t222;
+
+  inverse_all(v, ux, uy, uz);
+}
+
+}  // namespace fpc

@@ -1,0 +1,743 @@
+// lbm.hip -- gfx950 kernels and the C ABI of include/lbm.h.
+//
+// Data layout in HBM: two state buffers (A/B, ping-pong), each 27 direction
+// arrays of `stride` values (stride = N rounded up to 256 values), node index
+// i = x + nx (y + ny z).  A step reads the previous post-collision state from
+// one buffer with a pull gather (f_alpha(x) = f~_alpha(x - e_alpha), Appendix D
+// Step 6; halfway bounce-back takes the node's own opposite population) and
+// writes the new post-collision state to the other: 27 reads and 27 writes per
+// node, each direction array read exactly once, no atomics, no LDS.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "../../include/lbm.h"
+#include "d3q27.hpp"
+#include "fpc_collide.hpp"
+
+using namespace fpc;
+
+// ===========================================================================
+// storage forms
+template <int ST>
+struct Stor;
+
+template <>
+struct Stor<LBM_F64> {
+  using S = double;
+  using R = double;
+  static __device__ __forceinline__ R dec(S s, int) { return s; }
+  static __device__ __forceinline__ S enc(R r, int) { return r; }
+};
+
+template <>
+struct Stor<LBM_F32> {
+  using S = float;
+  using R = float;
+  static __device__ __forceinline__ R dec(S s, int) { return s; }
+  static __device__ __forceinline__ S enc(R r, int) { return r; }
+};
+
+template <>
+struct Stor<LBM_F16DEV> {
+  using S = _Float16;
+  using R = float;
+  static __device__ __forceinline__ R dec(S s, int a) { return (float)s * (1.0f / dev_scale(a)); }
+  // float -> half conversion rounds to nearest even (default rounding mode)
+  static __device__ __forceinline__ S enc(R r, int a) { return (_Float16)(r * dev_scale(a)); }
+};
+
+template <>
+struct Stor<LBM_BF16DEV> {
+  using S = uint16_t;
+  using R = float;
+  static __device__ __forceinline__ R dec(S s, int a) {
+    return __uint_as_float((uint32_t)s << 16) * (1.0f / dev_scale(a));
+  }
+  // round to nearest even on the 16 dropped bits; NaN stays NaN
+  static __device__ __forceinline__ S enc(R r, int a) {
+    const uint32_t u = __float_as_uint(r * dev_scale(a));
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (S)((u >> 16) | 0x40u);
+    return (S)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  }
+};
+
+struct Geom {
+  int nx, ny, nz;
+  int64_t stride;  // values between direction arrays
+};
+
+template <typename T>
+struct StepArgs {
+  Geom g;
+  Rates<T> r;
+  T F[3];
+};
+
+// ===========================================================================
+// fused stream + collide
+//
+// One thread per node; a block covers BX x BY nodes of one z plane.
+template <int ST, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>::S* __restrict__ src,
+                                                        typename Stor<ST>::S* __restrict__ dst,
+                                                        StepArgs<typename Stor<ST>::R> A) {
+  using T = typename Stor<ST>::R;
+  using SS = Stor<ST>;
+  const int nx = A.g.nx, ny = A.g.ny, nz = A.g.nz;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= nx || y >= ny) return;
+  const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};  // source x for e_x = -1, 0, +1
+  const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
+  const int zs[3] = {z == nz - 1 ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
+  const int i = (z * ny + y) * nx + x;
+  const int64_t st = A.g.stride;
+
+  T v[3][3][3];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const int ex = EX[a], ey = EY[a], ez = EZ[a];
+    T val;
+    if (WALLS && ((ey == 1 && y == 0) || (ey == -1 && y == ny - 1))) {
+      val = SS::dec(src[opposite(a) * st + i], opposite(a));  // halfway bounce-back
+      // the stored value is a deviation from w_opp = w_alpha
+    } else {
+      const int j = (zs[ez + 1] * ny + ys[ey + 1]) * nx + xs[ex + 1];
+      val = SS::dec(src[a * st + j], a);
+    }
+    v[ez + 1][ey + 1][ex + 1] = val;
+  }
+
+  const T ws[6] = {A.r.w[4], A.r.w[5], A.r.w[6], A.r.w[7], A.r.w[8], A.r.w[9]};
+  T rho, ux, uy, uz;
+  collide<T, FORCE>(v, A.r, ws, A.F[0], A.F[1], A.F[2], rho, ux, uy, uz);
+
+#pragma unroll
+  for (int a = 0; a < Q; ++a) dst[a * st + i] = SS::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a);
+}
+
+// ===========================================================================
+// initialisation: f~(0) = f^eq(rho, u); kappa' = rho' E, mapped back by the
+// inverse sweeps (the same ones the collision uses).
+template <int ST>
+__global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, const double* __restrict__ u,
+                                              typename Stor<ST>::S* __restrict__ dst, int64_t n, int64_t st) {
+  using T = typename Stor<ST>::R;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T rp = rho ? (T)(rho[i] - 1.0) : T(0);
+  const T ux = u ? (T)u[i] : T(0), uy = u ? (T)u[n + i] : T(0), uz = u ? (T)u[2 * n + i] : T(0);
+  T v[3][3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v[c][b][a] = rp * T(C1[a] * C1[b] * C1[c]);
+  inverse_all(v, ux, uy, uz);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) dst[a * st + i] = Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_set_f(const double* __restrict__ f, typename Stor<ST>::S* __restrict__ dst,
+                                               int64_t n, int64_t st) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+    dst[a * st + i] = Stor<ST>::enc((typename Stor<ST>::R)(f[a * n + i] - weight(a)), a);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_get_f(const typename Stor<ST>::S* __restrict__ src, double* __restrict__ f,
+                                               int64_t n, int64_t st) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) f[a * n + i] = weight(a) + (double)Stor<ST>::dec(src[a * st + i], a);
+}
+
+// Step 7 fields from the stored post-collision state: rho = 1 + sum delta,
+// rho u = sum delta e - F/2.
+template <int ST, typename OUT>
+__global__ __launch_bounds__(256) void k_moments(const typename Stor<ST>::S* __restrict__ src, OUT* __restrict__ rho,
+                                                 OUT* __restrict__ u, int64_t n, int64_t st, double Fx, double Fy,
+                                                 double Fz) {
+  using T = typename Stor<ST>::R;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T v[3][3][3];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] = Stor<ST>::dec(src[a * st + i], a);
+  T rp, jx, jy, jz;
+  density_momentum(v, rp, jx, jy, jz);
+  const double r = 1.0 + (double)rp;
+  if (rho) rho[i] = (OUT)r;
+  if (u) {
+    u[i] = (OUT)(((double)jx - 0.5 * Fx) / r);
+    u[n + i] = (OUT)(((double)jy - 0.5 * Fy) / r);
+    u[2 * n + i] = (OUT)(((double)jz - 0.5 * Fz) / r);
+  }
+}
+
+// ===========================================================================
+// FP64 diagnostics with a deterministic reduction order:
+// fixed grid of DIAG_BLOCKS blocks, grid-stride loops, wave64 shuffles, LDS
+// across the 4 waves, then one block over the per-block partials.
+constexpr int DIAG_BLOCKS = 1024;
+constexpr int DIAG_THREADS = 256;
+constexpr int NP = 12;  // partial slots per block
+
+enum { P_MASS, P_MX, P_MY, P_MZ, P_KE, P_WX, P_WY, P_WZ, P_NONFIN, P_ENS, P_MAXU, P_MINRHO };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// sums partial values over the block; kind 0 = sum, 1 = max, 2 = min
+template <int NV>
+__device__ void block_reduce(double (&val)[NV], const int (&kind)[NV], double* out) {
+  __shared__ double sh[DIAG_THREADS / 64][NV];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double t = kind[k] == 0 ? wave_sum(val[k]) : kind[k] == 1 ? wave_max(val[k]) : wave_min(val[k]);
+    if (lane == 0) sh[wid][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double t = sh[0][k];
+      for (int w = 1; w < DIAG_THREADS / 64; ++w)
+        t = kind[k] == 0 ? t + sh[w][k] : kind[k] == 1 ? fmax(t, sh[w][k]) : fmin(t, sh[w][k]);
+      out[k] = t;
+    }
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(DIAG_THREADS) void k_diag_nodes(const typename Stor<ST>::S* __restrict__ src,
+                                                             double* __restrict__ uscr, double* __restrict__ part,
+                                                             Geom g, int walls, double Fx, double Fy, double Fz) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t st = g.stride;
+  double acc[NP];
+  const int kind[NP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 2};
+#pragma unroll
+  for (int k = 0; k < NP; ++k) acc[k] = 0.0;
+  acc[P_MINRHO] = INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x; i < n; i += (int64_t)DIAG_BLOCKS * DIAG_THREADS) {
+    double d[Q];
+    bool finite = true;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      d[a] = (double)Stor<ST>::dec(src[a * st + i], a);
+      finite = finite && isfinite(d[a]);
+    }
+    double rp = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      rp += d[a];
+      jx += EX[a] * d[a];
+      jy += EY[a] * d[a];
+      jz += EZ[a] * d[a];
+    }
+    const double r = 1.0 + rp;
+    jx -= 0.5 * Fx;
+    jy -= 0.5 * Fy;
+    jz -= 0.5 * Fz;
+    const double ux = jx / r, uy = jy / r, uz = jz / r;
+    uscr[i] = ux;
+    uscr[n + i] = uy;
+    uscr[2 * n + i] = uz;
+    acc[P_MASS] += r;
+    acc[P_MX] += jx;
+    acc[P_MY] += jy;
+    acc[P_MZ] += jz;
+    const double s2 = ux * ux + uy * uy + uz * uz;
+    acc[P_KE] += 0.5 * r * s2;
+    acc[P_NONFIN] += finite ? 0.0 : 1.0;
+    acc[P_MAXU] = fmax(acc[P_MAXU], sqrt(s2));
+    acc[P_MINRHO] = fmin(acc[P_MINRHO], r);
+    if (walls) {
+      const int y = (int)((i / g.nx) % g.ny);
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        if ((EY[a] == -1 && y == 0) || (EY[a] == 1 && y == g.ny - 1)) {
+          const double fa = weight(a) + d[a];
+          acc[P_WX] += 2.0 * fa * EX[a];
+          acc[P_WY] += 2.0 * fa * EY[a];
+          acc[P_WZ] += 2.0 * fa * EZ[a];
+        }
+      }
+    }
+  }
+  block_reduce<NP>(acc, kind, part + (int64_t)blockIdx.x * NP);
+}
+
+// 1/2 |curl u|^2 with centred differences; periodic, or an antisymmetric
+// ghost layer across the half-link walls (u = 0 at the wall).
+__global__ __launch_bounds__(DIAG_THREADS) void k_diag_enstrophy(const double* __restrict__ u, double* __restrict__ part,
+                                                                 Geom g, int walls) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  double acc[1] = {0.0};
+  const int kind[1] = {0};
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  for (int64_t i = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x; i < n; i += (int64_t)DIAG_BLOCKS * DIAG_THREADS) {
+    const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+    const int xp = x == nx - 1 ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+    const int zp = z == nz - 1 ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
+    int yp = y == ny - 1 ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+    double sgp = 1.0, sgm = 1.0;
+    if (walls) {
+      if (y == ny - 1) { yp = y; sgp = -1.0; }
+      if (y == 0) { ym = y; sgm = -1.0; }
+    }
+    auto at = [&](int c, int xx, int yy, int zz) { return u[(int64_t)c * n + ((int64_t)zz * ny + yy) * nx + xx]; };
+    const double dwy_dx = 0.5 * (at(2, xp, y, z) - at(2, xm, y, z));  // d uz / dx
+    const double dvy_dz = 0.5 * (at(1, x, y, zp) - at(1, x, y, zm));  // d uy / dz
+    const double duz_dy = 0.5 * (sgp * at(2, x, yp, z) - sgm * at(2, x, ym, z));
+    const double dux_dy = 0.5 * (sgp * at(0, x, yp, z) - sgm * at(0, x, ym, z));
+    const double dux_dz = 0.5 * (at(0, x, y, zp) - at(0, x, y, zm));
+    const double duy_dx = 0.5 * (at(1, xp, y, z) - at(1, xm, y, z));
+    const double wx = duz_dy - dvy_dz, wy = dux_dz - dwy_dx, wz = duy_dx - dux_dy;
+    acc[0] += 0.5 * (wx * wx + wy * wy + wz * wz);
+  }
+  block_reduce<1>(acc, kind, part + (int64_t)blockIdx.x);
+}
+
+__global__ __launch_bounds__(DIAG_THREADS) void k_diag_final(const double* __restrict__ part,
+                                                             const double* __restrict__ part_ens,
+                                                             double* __restrict__ out) {
+  double acc[NP];
+  const int kind[NP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 2};
+#pragma unroll
+  for (int k = 0; k < NP; ++k) acc[k] = 0.0;
+  acc[P_MINRHO] = INFINITY;
+  for (int b = threadIdx.x; b < DIAG_BLOCKS; b += DIAG_THREADS) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const double p = k == P_ENS ? part_ens[b] : part[b * NP + k];
+      acc[k] = kind[k] == 0 ? acc[k] + p : kind[k] == 1 ? fmax(acc[k], p) : fmin(acc[k], p);
+    }
+  }
+  block_reduce<NP>(acc, kind, out);
+}
+
+// ===========================================================================
+// host side
+struct lbm_ctx {
+  lbm_config cfg;
+  int device = 0;
+  int64_t n = 0, stride = 0;
+  size_t elem = 0;
+  void* buf[2] = {nullptr, nullptr};
+  int cur = 0;  // buffer holding the current post-collision state
+  bool initialised = false;
+  int64_t steps = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  double omega[LBM_Q];
+  double* scratch = nullptr;  // 4 N doubles for moments / diagnostics
+  double* part = nullptr;     // DIAG_BLOCKS * (NP + 1) + NP doubles
+  double* host_out = nullptr; // pinned NP doubles
+  char err[512] = {0};
+};
+
+static char g_create_err[512] = "";
+
+// 256-thread blocks: a row segment of up to 256 nodes along x, and as many rows
+// along y as fill the block when nx is small.
+static void step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid) {
+  const int bx = nx >= 256 ? 256 : (nx + 31) / 32 * 32;
+  const int by = 256 / bx;
+  block = dim3(bx, by, 1);
+  grid = dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nz);
+}
+
+static int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
+  char* dst = c ? c->err : g_create_err;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(dst, 512, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return set_err(ctx, LBM_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCHCHK(ctx)                                                                     \
+  do {                                                                                     \
+    hipError_t e_ = hipGetLastError();                                                     \
+    if (e_ != hipSuccess) return set_err(ctx, LBM_EHIP, "kernel launch: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" void lbm_config_default(lbm_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->storage = LBM_F32;
+  cfg->omega_mode = LBM_OMEGA_PAPER;
+  cfg->nu = 1.0 / 6.0;
+  cfg->omega_bulk = 1.0;
+  cfg->omega_higher = 1.0;
+}
+
+// Eq. (transportcoeff3DFPCLBM): nu = c_s^2 (1/omega - 1/2), c_s^2 = 1/3.
+extern "C" int lbm_omega_table(const lbm_config* cfg, double out[LBM_Q]) {
+  if (!cfg || !out) return LBM_EINVAL;
+  double w[LBM_Q];
+  if (cfg->omega_mode == LBM_OMEGA_EXPLICIT) {
+    for (int j = 0; j < LBM_Q; ++j) w[j] = cfg->omega[j];
+  } else if (cfg->omega_mode == LBM_OMEGA_PAPER || cfg->omega_mode == LBM_OMEGA_ORDER_SCALED) {
+    if (!(cfg->nu > 0.0) || !std::isfinite(cfg->nu)) return LBM_EINVAL;
+    const double w2 = 1.0 / (3.0 * cfg->nu + 0.5);
+    for (int j = 0; j < LBM_Q; ++j) w[j] = cfg->omega_higher;
+    w[0] = w[1] = w[2] = w[3] = 1.0;
+    w[4] = w[5] = w[6] = w[8] = w[9] = w2;
+    w[7] = cfg->omega_bulk;
+    if (cfg->omega_mode == LBM_OMEGA_ORDER_SCALED) {
+      // order of the moments relaxed with omega_10..omega_26
+      static const int order[LBM_Q] = {0, 1, 1, 1, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3,
+                                       4, 4, 4, 4, 4, 4, 5, 5, 5, 6};
+      for (int j = 10; j < LBM_Q; ++j) w[j] = 1.0 / ((2.0 / order[j]) * (1.0 / w2 - 0.5) + 0.5);
+    }
+  } else {
+    return LBM_EINVAL;
+  }
+  for (int j = 0; j < LBM_Q; ++j)
+    if (!(w[j] > 0.0 && w[j] < 2.0)) return LBM_EINVAL;
+  for (int j = 0; j < LBM_Q; ++j) out[j] = w[j];
+  return LBM_OK;
+}
+
+static size_t elem_size(int st) {
+  switch (st) {
+    case LBM_F64: return 8;
+    case LBM_F32: return 4;
+    case LBM_F16DEV:
+    case LBM_BF16DEV: return 2;
+    default: return 0;
+  }
+}
+
+extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
+  if (!out) return set_err(nullptr, LBM_EINVAL, "lbm_create: out is NULL");
+  *out = nullptr;
+  if (!cfg) return set_err(nullptr, LBM_EINVAL, "lbm_create: cfg is NULL");
+  if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)
+    return set_err(nullptr, LBM_EINVAL, "lbm_create: grid %d x %d x %d must be positive", cfg->nx, cfg->ny, cfg->nz);
+  const int64_t n = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+  if (n >= (int64_t)1 << 31) return set_err(nullptr, LBM_EINVAL, "lbm_create: %lld nodes exceed 2^31 - 1", (long long)n);
+  {
+    dim3 blk, grd;
+    step_launch_shape(cfg->nx, cfg->ny, cfg->nz, blk, grd);
+    if (cfg->nz > 65535 || (cfg->ny + (int)blk.y - 1) / (int)blk.y > 65535)
+      return set_err(nullptr, LBM_EINVAL, "lbm_create: nz and the y extent of the launch grid must be <= 65535");
+  }
+  const size_t es = elem_size(cfg->storage);
+  if (!es) return set_err(nullptr, LBM_EINVAL, "lbm_create: unknown storage %d", cfg->storage);
+  if (cfg->walls_y != 0 && cfg->walls_y != 1) return set_err(nullptr, LBM_EINVAL, "lbm_create: walls_y must be 0 or 1");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(cfg->force[d])) return set_err(nullptr, LBM_EINVAL, "lbm_create: non-finite force");
+  double w[LBM_Q];
+  if (lbm_omega_table(cfg, w) != LBM_OK)
+    return set_err(nullptr, LBM_EINVAL, "lbm_create: relaxation rates must lie in (0,2) (check nu, omega_bulk, omega_higher, omega[])");
+
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return set_err(nullptr, LBM_ENOMEM, "lbm_create: host allocation failed");
+  c->cfg = *cfg;
+  std::memcpy(c->omega, w, sizeof w);
+  c->n = n;
+  c->stride = (n + 255) / 256 * 256;
+  c->elem = es;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) {
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&c->buf[b], (size_t)LBM_Q * c->stride * es);
+  }
+  if (e == hipSuccess) e = hipMalloc((void**)&c->part, sizeof(double) * (DIAG_BLOCKS * (NP + 1) + NP));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_out, sizeof(double) * NP, hipHostMallocDefault);
+  if (e == hipSuccess) {
+    if (cfg->hip_stream) {
+      c->stream = (hipStream_t)cfg->hip_stream;
+    } else {
+      e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+      c->own_stream = (e == hipSuccess);
+    }
+  }
+  if (e != hipSuccess) {
+    int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? LBM_ENOMEM : LBM_EHIP;
+    set_err(nullptr, code, "lbm_create: %s", hipGetErrorString(e));
+    lbm_destroy(c);
+    return code;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+extern "C" void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (int b = 0; b < 2; ++b)
+    if (c->buf[b]) (void)hipFree(c->buf[b]);
+  if (c->scratch) (void)hipFree(c->scratch);
+  if (c->part) (void)hipFree(c->part);
+  if (c->host_out) (void)hipHostFree(c->host_out);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+extern "C" const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err : g_create_err; }
+extern "C" void* lbm_stream(const lbm_ctx* c) { return c ? (void*)c->stream : nullptr; }
+extern "C" int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->steps : -1; }
+extern "C" int64_t lbm_state_bytes(const lbm_ctx* c) { return c ? (int64_t)(LBM_Q * c->n * c->elem) : -1; }
+
+static unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// dispatch a functor over the four storage forms
+#define DISPATCH_ST(st, ...)                                   \
+  switch (st) {                                                \
+    case LBM_F64: { constexpr int ST = LBM_F64; __VA_ARGS__; } break;         \
+    case LBM_F32: { constexpr int ST = LBM_F32; __VA_ARGS__; } break;         \
+    case LBM_F16DEV: { constexpr int ST = LBM_F16DEV; __VA_ARGS__; } break;   \
+    case LBM_BF16DEV: { constexpr int ST = LBM_BF16DEV; __VA_ARGS__; } break; \
+  }
+
+static int alloc_scratch(lbm_ctx* c) {
+  if (!c->scratch) HIPCHK(c, hipMalloc((void**)&c->scratch, sizeof(double) * 4 * c->n));
+  return LBM_OK;
+}
+
+extern "C" int lbm_init(lbm_ctx* c, const double* rho, const double* u) {
+  if (!c) return LBM_EINVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = alloc_scratch(c);
+  if (rc) return rc;
+  const int64_t n = c->n;
+  double* drho = nullptr;
+  double* du = nullptr;
+  if (rho) {
+    drho = c->scratch;
+    HIPCHK(c, hipMemcpyAsync(drho, rho, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  }
+  if (u) {
+    du = c->scratch + n;
+    HIPCHK(c, hipMemcpyAsync(du, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+  }
+  c->cur = 0;
+  DISPATCH_ST(c->cfg.storage,
+              k_init<ST><<<nblocks(n, 256), 256, 0, c->stream>>>(drho, du, (typename Stor<ST>::S*)c->buf[0], n, c->stride));
+  LAUNCHCHK(c);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->initialised = true;
+  c->steps = 0;
+  return LBM_OK;
+}
+
+template <int ST>
+static int launch_steps(lbm_ctx* c, int64_t nsteps) {
+  using T = typename Stor<ST>::R;
+  using S = typename Stor<ST>::S;
+  StepArgs<T> A;
+  A.g = Geom{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->stride};
+  for (int j = 0; j < LBM_Q; ++j) {
+    A.r.w[j] = (T)c->omega[j];
+    A.r.h[j] = (T)(1.0 - 0.5 * c->omega[j]);
+  }
+  for (int d = 0; d < 3; ++d) A.F[d] = (T)c->cfg.force[d];
+  const bool force = c->cfg.force[0] != 0.0 || c->cfg.force[1] != 0.0 || c->cfg.force[2] != 0.0;
+  const bool walls = c->cfg.walls_y != 0;
+  dim3 block, grid;
+  step_launch_shape(c->cfg.nx, c->cfg.ny, c->cfg.nz, block, grid);
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const S* src = (const S*)c->buf[c->cur];
+    S* dst = (S*)c->buf[c->cur ^ 1];
+    if (walls) {
+      if (force) k_stream_collide<ST, true, true><<<grid, block, 0, c->stream>>>(src, dst, A);
+      else k_stream_collide<ST, true, false><<<grid, block, 0, c->stream>>>(src, dst, A);
+    } else {
+      if (force) k_stream_collide<ST, false, true><<<grid, block, 0, c->stream>>>(src, dst, A);
+      else k_stream_collide<ST, false, false><<<grid, block, 0, c->stream>>>(src, dst, A);
+    }
+    LAUNCHCHK(c);
+    c->cur ^= 1;
+    c->steps++;
+  }
+  return LBM_OK;
+}
+
+extern "C" int lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c || n < 0) return LBM_EINVAL;
+  if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_step: state not initialised (call lbm_init or lbm_set_f)");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = LBM_OK;
+  DISPATCH_ST(c->cfg.storage, rc = launch_steps<ST>(c, n));
+  return rc;
+}
+
+extern "C" int lbm_synchronize(lbm_ctx* c) {
+  if (!c) return LBM_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_moments_device(lbm_ctx* c, void* rho_dev, void* u_dev, int32_t f64) {
+  if (!c) return LBM_EINVAL;
+  if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_moments: state not initialised");
+  HIPCHK(c, hipSetDevice(c->device));
+  const double* F = c->cfg.force;
+  const int64_t n = c->n;
+  if (f64) {
+    DISPATCH_ST(c->cfg.storage,
+                k_moments<ST, double><<<nblocks(n, 256), 256, 0, c->stream>>>(
+                    (const typename Stor<ST>::S*)c->buf[c->cur], (double*)rho_dev, (double*)u_dev, n, c->stride, F[0], F[1], F[2]));
+  } else {
+    DISPATCH_ST(c->cfg.storage,
+                k_moments<ST, float><<<nblocks(n, 256), 256, 0, c->stream>>>(
+                    (const typename Stor<ST>::S*)c->buf[c->cur], (float*)rho_dev, (float*)u_dev, n, c->stride, F[0], F[1], F[2]));
+  }
+  LAUNCHCHK(c);
+  return LBM_OK;
+}
+
+extern "C" int lbm_moments(lbm_ctx* c, double* rho, double* u) {
+  if (!c) return LBM_EINVAL;
+  if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_moments: state not initialised");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = alloc_scratch(c);
+  if (rc) return rc;
+  rc = lbm_moments_device(c, c->scratch, c->scratch + c->n, 1);
+  if (rc) return rc;
+  if (rho) HIPCHK(c, hipMemcpyAsync(rho, c->scratch, sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
+  if (u) HIPCHK(c, hipMemcpyAsync(u, c->scratch + c->n, sizeof(double) * 3 * c->n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_f(lbm_ctx* c, double* f) {
+  if (!c || !f) return LBM_EINVAL;
+  if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_get_f: state not initialised");
+  HIPCHK(c, hipSetDevice(c->device));
+  double* tmp = nullptr;
+  HIPCHK(c, hipMalloc((void**)&tmp, sizeof(double) * LBM_Q * c->n));
+  DISPATCH_ST(c->cfg.storage,
+              k_get_f<ST><<<nblocks(c->n, 256), 256, 0, c->stream>>>((const typename Stor<ST>::S*)c->buf[c->cur], tmp, c->n, c->stride));
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(f, tmp, sizeof(double) * LBM_Q * c->n, hipMemcpyDeviceToHost, c->stream);
+  hipError_t e3 = hipStreamSynchronize(c->stream);
+  hipError_t e2 = hipFree(tmp);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = e3;
+  if (e != hipSuccess) return set_err(c, LBM_EHIP, "lbm_get_f: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+extern "C" int lbm_set_f(lbm_ctx* c, const double* f) {
+  if (!c || !f) return LBM_EINVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  double* tmp = nullptr;
+  HIPCHK(c, hipMalloc((void**)&tmp, sizeof(double) * LBM_Q * c->n));
+  hipError_t e = hipMemcpyAsync(tmp, f, sizeof(double) * LBM_Q * c->n, hipMemcpyHostToDevice, c->stream);
+  c->cur = 0;
+  if (e == hipSuccess) {
+    DISPATCH_ST(c->cfg.storage,
+                k_set_f<ST><<<nblocks(c->n, 256), 256, 0, c->stream>>>(tmp, (typename Stor<ST>::S*)c->buf[0], c->n, c->stride));
+    e = hipGetLastError();
+  }
+  hipError_t e3 = hipStreamSynchronize(c->stream);
+  hipError_t e2 = hipFree(tmp);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = e3;
+  if (e != hipSuccess) return set_err(c, LBM_EHIP, "lbm_set_f: %s", hipGetErrorString(e));
+  c->initialised = true;
+  c->steps = 0;
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_raw(lbm_ctx* c, void* host, int64_t nbytes) {
+  if (!c || !host || nbytes != lbm_state_bytes(c)) return LBM_EINVAL;
+  if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_get_raw: state not initialised");
+  HIPCHK(c, hipSetDevice(c->device));
+  const size_t row = (size_t)c->n * c->elem;
+  HIPCHK(c, hipMemcpy2DAsync(host, row, c->buf[c->cur], (size_t)c->stride * c->elem, row, LBM_Q, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_set_raw(lbm_ctx* c, const void* host, int64_t nbytes) {
+  if (!c || !host || nbytes != lbm_state_bytes(c)) return LBM_EINVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  const size_t row = (size_t)c->n * c->elem;
+  c->cur = 0;
+  HIPCHK(c, hipMemcpy2DAsync(c->buf[0], (size_t)c->stride * c->elem, host, row, row, LBM_Q, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->initialised = true;
+  c->steps = 0;
+  return LBM_OK;
+}
+
+extern "C" int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
+  if (!c || !out) return LBM_EINVAL;
+  if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_diagnostics: state not initialised");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = alloc_scratch(c);
+  if (rc) return rc;
+  const Geom g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->stride};
+  const double* F = c->cfg.force;
+  double* part = c->part;
+  double* part_ens = c->part + DIAG_BLOCKS * NP;
+  double* dout = part_ens + DIAG_BLOCKS;
+  DISPATCH_ST(c->cfg.storage,
+              k_diag_nodes<ST><<<DIAG_BLOCKS, DIAG_THREADS, 0, c->stream>>>(
+                  (const typename Stor<ST>::S*)c->buf[c->cur], c->scratch, part, g, c->cfg.walls_y, F[0], F[1], F[2]));
+  LAUNCHCHK(c);
+  k_diag_enstrophy<<<DIAG_BLOCKS, DIAG_THREADS, 0, c->stream>>>(c->scratch, part_ens, g, c->cfg.walls_y);
+  LAUNCHCHK(c);
+  k_diag_final<<<1, DIAG_THREADS, 0, c->stream>>>(part, part_ens, dout);
+  LAUNCHCHK(c);
+  HIPCHK(c, hipMemcpyAsync(c->host_out, dout, sizeof(double) * NP, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double* h = c->host_out;
+  out->mass = h[P_MASS];
+  out->momentum[0] = h[P_MX];
+  out->momentum[1] = h[P_MY];
+  out->momentum[2] = h[P_MZ];
+  out->kinetic_energy = h[P_KE];
+  out->enstrophy = h[P_ENS];
+  out->wall_force[0] = h[P_WX];
+  out->wall_force[1] = h[P_WY];
+  out->wall_force[2] = h[P_WZ];
+  out->max_speed = h[P_MAXU];
+  out->min_rho = h[P_MINRHO];
+  out->n_nonfinite = (int64_t)h[P_NONFIN];
+  out->step = c->steps;
+  if (out->n_nonfinite > 0 || !(out->min_rho > 0.0) || !std::isfinite(out->mass))
+    return set_err(c, LBM_EUNSTABLE, "lbm_diagnostics: %lld non-finite nodes, min rho %g", (long long)out->n_nonfinite, out->min_rho);
+  return LBM_OK;
+}

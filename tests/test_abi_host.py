@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+function include/lbm.h declares, validates configurations before touching the
+device, and maps viscosities to relaxation rates as Eq. (transportcoeff3DFPCLBM)
+prescribes (compared with the oracle's independent mapping)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2410_09739_amd import lbm as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = L.load()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (lbm_\w+)", out))
+    assert set(names) <= exported
+    assert set(names) == set(L.SIGNATURES), "binding and header disagree"
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Compile the header with the host C compiler and compare every field offset
+    with the ctypes mirror used by the binding."""
+    fields = {"lbm_config": [f[0] for f in L.lbm_config._fields_], "lbm_diag": [f[0] for f in L.lbm_diag._fields_]}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', "int main(void){"]
+    for st, names in fields.items():
+        src.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for n in names:
+            src.append(f'printf("{st} {n} %zu\\n", offsetof({st}, {n}));')
+    src.append("return 0;}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(c)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    for line in filter(None, out):
+        st, name, val = line.split()
+        cls = getattr(L, st)
+        expect = ctypes.sizeof(cls) if name == "size" else getattr(cls, name).offset
+        assert int(val) == expect, (st, name)
+
+
+@pytest.mark.parametrize("nu", [1e-6, 0.0025465, 0.01, 1.0 / 6.0, 0.5])
+@pytest.mark.parametrize("mode", ["paper", "order_scaled"])
+def test_omega_table_matches_oracle_mapping(nu, mode):
+    cfg = L.Config(4, 4, 4, nu=nu, omega_mode=mode, omega_bulk=1.2, omega_higher=1.1).to_c()
+    got = L.lbm_omega_table(cfg)
+    ref = O.omega_table(nu, omega_bulk=1.2, omega_higher=1.1, mode=mode)
+    np.testing.assert_allclose(got, ref, rtol=1e-15)
+    # shear rates reproduce nu = c_s^2 (1/omega - 1/2)
+    for j in (4, 5, 6, 8, 9):
+        assert (1 / got[j] - 0.5) / 3 == pytest.approx(nu, rel=1e-12)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(ny=-1), dict(nu=0.0), dict(nu=-0.1), dict(omega_bulk=2.0), dict(omega_higher=0.0),
+    dict(storage=7), dict(walls_y=2), dict(nx=2048, ny=2048, nz=1024),
+])
+def test_create_rejects_invalid_configs_before_touching_the_device(bad):
+    c = L.Config(8, 8, 8, nu=0.01).to_c()
+    for k, v in bad.items():
+        setattr(c, k, v)
+    h = ctypes.c_void_p()
+    rc = L.load().lbm_create(ctypes.byref(c), ctypes.byref(h))
+    assert rc == L.LBM_EINVAL
+    assert h.value is None
+    assert L.lbm_last_error(None)
+
+
+def test_explicit_rates_are_checked():
+    c = L.Config(4, 4, 4, omega_mode="explicit", omega=[1.0] * 27).to_c()
+    np.testing.assert_array_equal(L.lbm_omega_table(c), np.ones(27))
+    c.omega[12] = 2.0
+    with pytest.raises(L.LBMError):
+        L.lbm_omega_table(c)
+
+
+def test_null_arguments_are_rejected():
+    lib = L.load()
+    assert lib.lbm_step(None, 1) == L.LBM_EINVAL
+    assert lib.lbm_moments(None, None, None) == L.LBM_EINVAL
+    assert lib.lbm_state_bytes(None) == -1
+    lib.lbm_destroy(None)  # no-op

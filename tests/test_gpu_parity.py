@@ -1,0 +1,259 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Inputs are seeded; every expected value comes from ``oracle/``.  Tolerances:
+
+* FP64 storage: 1e-12 relative to max(|f_ref|, w_alpha), element by element (both sides FP64; they differ
+  only in rounding order: factorised sweeps on deviations vs explicit matrices).
+* FP32 storage (deviations f - w in FP32, FP32 arithmetic): the error of one step
+  is a few FP32 ulps of the moment magnitudes; the bound is stated per step as
+  |f_gpu - f_ref| <= 4e-7 * w_alpha * steps, where w_alpha is the lattice weight
+  (f is of the order of w_alpha), plus the rounding of the initial state.
+* FP16 / BF16 deviation storage: one rounding of the stored deviation per step,
+  relative 2^-11 (FP16) / 2^-8 (BF16) of |f - w|, plus the FP32 bound; stated as
+  |f_gpu - f_ref| <= c * (max |f_ref - w|) * steps with c = 2^-10 / 2^-7.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2410_09739_amd import lbm as L
+from paper_2410_09739_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+W_ALPHA = O.feq(1.0, [0, 0, 0])[:, None, None, None]
+SHAPES = [(13, 10, 9), (32, 8, 5), (1, 16, 1), (65, 3, 7), (7, 1, 4)]
+
+
+def _state(shape, seed, amp=0.05, u_amp=0.05):
+    nx, ny, nz = shape
+    rho, u = W.random_fields(nx, ny, nz, seed=seed, u_amp=u_amp)
+    return O.init(rho, u) * W.random_factors((27, nz, ny, nx), seed=seed + 1, amplitude=amp)
+
+
+def _run_gpu(shape, storage, g0, steps, nu=0.02, walls=False, force=(0, 0, 0), mode="paper", **kw):
+    nx, ny, nz = shape
+    with L.Lattice(L.Config(nx, ny, nz, storage=storage, walls_y=walls, nu=nu, force=force,
+                            omega_mode=mode, **kw)) as lat:
+        lat.set_f(g0)
+        lat.step(steps)
+        return lat.get_f()
+
+
+def _rel(got, ref):
+    """max |got - ref| / max(|ref|, w_alpha): relative error on the scale of each population."""
+    return float((np.abs(got - ref) / np.maximum(np.abs(ref), W_ALPHA)).max())
+
+
+def _tol(storage, steps, ref):
+    dev = np.abs(ref - W_ALPHA).max()
+    if storage == "f32":
+        return 4e-7 * W_ALPHA * (steps + 1)
+    if storage == "f16dev":
+        return 2.0 ** -10 * dev * (steps + 1) + 4e-7 * W_ALPHA * (steps + 1)
+    if storage == "bf16dev":
+        return 2.0 ** -7 * dev * (steps + 1) + 4e-7 * W_ALPHA * (steps + 1)
+    raise ValueError(storage)
+
+
+# ------------------------------------------------------------------ FP64
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("walls,force", [(False, (0, 0, 0)), (True, (3e-5, -2e-5, 1e-5)), (False, (1e-4, 2e-5, -5e-5))])
+def test_f64_matches_oracle(shape, walls, force):
+    g0 = _state(shape, seed=sum(shape))
+    om = O.omega_table(0.02)
+    for steps in (1, 6):
+        ref = O.run(g0, om, force, walls_y=walls, steps=steps)
+        got = _run_gpu(shape, "f64", g0, steps, walls=walls, force=force)
+        err = _rel(got, ref)
+        assert err <= 1e-12, (steps, err)
+
+
+@pytest.mark.parametrize("mode", ["order_scaled", "explicit"])
+def test_f64_matches_oracle_other_rate_sets(mode):
+    shape = (11, 9, 6)
+    g0 = _state(shape, seed=3, amp=0.1)
+    rng = np.random.default_rng(4)
+    expl = rng.uniform(0.3, 1.9, 27)
+    om = O.omega_table(0.004, mode=mode, explicit=expl)
+    ref = O.run(g0, om, (1e-5, 0, 2e-5), walls_y=True, steps=4)
+    kw = {"omega": list(expl)} if mode == "explicit" else {}
+    got = _run_gpu(shape, "f64", g0, 4, nu=0.004, walls=True, force=(1e-5, 0, 2e-5), mode=mode, **kw)
+    err = _rel(got, ref)
+    assert err <= 1e-12, err
+
+
+def test_taylor_green_32_cube_f64_200_steps():
+    """The 32^3 periodic Taylor-Green case (u0 = 0.05, Re = 100 with L = N/2pi)
+    for 200 steps from f^eq: populations and Step 7 fields match the oracle."""
+    n, u0 = 32, 0.05
+    nu = u0 * (n / (2 * np.pi)) / 100.0
+    rho, u = W.taylor_green(n, u0=u0)
+    om = O.omega_table(nu)
+    ref = O.run(O.init(rho, u), om, steps=200)
+    with L.Lattice(L.Config(n, n, n, storage="f64", nu=nu)) as lat:
+        lat.init(rho, u)
+        err0 = _rel(lat.get_f(), O.init(rho, u))
+        assert err0 <= 1e-14, err0
+        lat.step(200)
+        got = lat.get_f()
+        r_gpu, u_gpu = lat.moments()
+        d = lat.diagnostics()
+    err = _rel(got, ref)
+    assert err <= 1e-12, err
+    r_ref, u_ref = O.macroscopic(ref)
+    assert np.abs(r_gpu - r_ref).max() <= 1e-12
+    assert np.abs(u_gpu - u_ref).max() <= 1e-12 * u0
+    assert d["mass"] == pytest.approx(r_ref.sum(), rel=1e-13)
+    assert d["kinetic_energy"] == pytest.approx(0.5 * np.sum(r_ref * (u_ref ** 2).sum(0)), rel=1e-12)
+    assert d["max_speed"] == pytest.approx(np.sqrt((u_ref ** 2).sum(0)).max(), rel=1e-12)
+    assert d["step"] == 200
+
+
+# ------------------------------------------------------------------ reduced precision
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "bf16dev"])
+@pytest.mark.parametrize("walls,force", [(False, (0, 0, 0)), (True, (2e-6, 0, 1e-6))])
+def test_reduced_precision_within_stated_bound(storage, walls, force):
+    shape = (37, 12, 9)
+    g0 = _state(shape, seed=21)
+    om = O.omega_table(0.01)
+    for steps in (1, 10):
+        ref = O.run(g0, om, force, walls_y=walls, steps=steps)
+        got = _run_gpu(shape, storage, g0, steps, nu=0.01, walls=walls, force=force)
+        err = np.abs(got - ref)
+        tol = _tol(storage, steps, ref)
+        ratio = float((err / tol).max())
+        assert ratio <= 1.0, (storage, steps, ratio)
+
+
+# ------------------------------------------------------------------ invariants on the GPU
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_mass_conserved_and_momentum_gains_force(storage):
+    shape = (24, 16, 8)
+    g0 = _state(shape, seed=9)
+    F = (1e-5, -2e-5, 3e-5)
+    with L.Lattice(L.Config(*shape, storage=storage, nu=0.01, force=F)) as lat:
+        lat.set_f(g0)
+        d0 = lat.diagnostics()
+        lat.step(50)
+        d1 = lat.diagnostics()
+    n = np.prod(shape)
+    tol = 1e-13 if storage == "f64" else 2e-6
+    assert d1["mass"] == pytest.approx(d0["mass"], rel=tol)
+    for k in range(3):
+        assert d1["momentum"][k] - d0["momentum"][k] == pytest.approx(50 * n * F[k], rel=1e-9 if storage == "f64" else 1e-3)
+
+
+def test_uniform_equilibrium_is_a_fixed_point_on_gpu():
+    shape = (16, 8, 4)
+    rho = np.full(shape[::-1], 1.01)
+    u = np.zeros((3,) + shape[::-1])
+    u[0] += 0.04
+    u[1] -= 0.02
+    with L.Lattice(L.Config(*shape, storage="f64", nu=0.003)) as lat:
+        lat.init(rho, u)
+        f0 = lat.get_f()
+        lat.step(20)
+        np.testing.assert_allclose(lat.get_f(), f0, rtol=1e-14)
+
+
+def test_moments_and_device_moments_match_oracle_definition():
+    import torch
+    shape = (19, 6, 5)
+    g0 = _state(shape, seed=31)
+    F = (2e-5, 0.0, -1e-5)
+    with L.Lattice(L.Config(*shape, storage="f64", walls_y=True, nu=0.05, force=F)) as lat:
+        lat.set_f(g0)
+        lat.step(3)
+        g = lat.get_f()
+        r, u = lat.moments()
+        rd = torch.empty(np.prod(shape), dtype=torch.float64, device="cuda")
+        ud = torch.empty(3 * np.prod(shape), dtype=torch.float64, device="cuda")
+        L.lbm_moments_device(lat.ctx, rd.data_ptr(), ud.data_ptr(), True)
+        lat.synchronize()
+    r_ref, u_ref = O.macroscopic(g, F)
+    np.testing.assert_allclose(r, r_ref, rtol=1e-14)
+    np.testing.assert_allclose(u, u_ref, rtol=1e-12, atol=1e-16)
+    np.testing.assert_allclose(rd.cpu().numpy().reshape(r.shape), r_ref, rtol=1e-14)
+    np.testing.assert_allclose(ud.cpu().numpy().reshape(u.shape), u_ref, rtol=1e-12, atol=1e-16)
+
+
+def test_wall_force_diagnostic_matches_momentum_exchange():
+    shape = (8, 12, 6)
+    e, _, _ = O.lattice()
+    g0 = _state(shape, seed=41)
+    with L.Lattice(L.Config(*shape, storage="f64", walls_y=True, nu=0.05, force=(1e-5, 0, 0))) as lat:
+        lat.set_f(g0)
+        lat.step(2)
+        g = lat.get_f()
+        d = lat.diagnostics()
+    ny = shape[1]
+    wall = np.zeros(3)
+    for a in range(27):
+        if e[a, 1] == -1:
+            wall += 2 * g[a, :, 0, :].sum() * e[a]
+        if e[a, 1] == 1:
+            wall += 2 * g[a, :, ny - 1, :].sum() * e[a]
+    np.testing.assert_allclose(d["wall_force"], wall, rtol=1e-12, atol=1e-15)
+
+
+# ------------------------------------------------------------------ checkpoint / state handling
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
+def test_raw_checkpoint_resume_is_bitwise(storage):
+    shape = (33, 7, 5)
+    g0 = _state(shape, seed=51)
+    cfg = L.Config(*shape, storage=storage, walls_y=True, nu=0.01, force=(1e-5, 0, 0))
+    with L.Lattice(cfg) as a:
+        a.set_f(g0)
+        a.step(7)
+        ck = a.get_raw()
+        a.step(5)
+        straight = a.get_raw()
+    with L.Lattice(cfg) as b:
+        b.set_raw(ck)
+        b.step(5)
+        resumed = b.get_raw()
+    assert np.array_equal(straight, resumed)
+
+
+def test_errors_are_reported_not_raised_on_device():
+    with L.Lattice(L.Config(4, 4, 4, nu=0.1)) as lat:
+        with pytest.raises(L.LBMError) as ei:
+            lat.step(1)
+        assert ei.value.code == L.LBM_ESTATE
+        f = np.full((27, 4, 4, 4), np.nan)
+        lat.set_f(f)
+        d = L.lbm_diagnostics(lat.ctx, check=False)
+        assert d.n_nonfinite == 64
+        with pytest.raises(L.LBMError) as ei:
+            lat.diagnostics()
+        assert ei.value.code == L.LBM_EUNSTABLE
+
+
+# ------------------------------------------------------------------ full size, sampled
+def test_channel_256x128x128_sampled_nodes_f32():
+    """The 256 x 128 x 128 body-force channel in FP32 storage, in the launch
+    configuration the benchmark times: after a few steps from a perturbed state,
+    the update at sampled nodes (walls, corners, interior) matches the oracle's
+    single-node evaluation of the same step from the GPU's own previous state."""
+    nx, ny, nz = 256, 128, 128
+    nu = 0.01
+    F = (8 * nu * 0.05 / ny ** 2, 0.0, 0.0)
+    rho, u = W.channel_turbulent_start(nx, ny, nz, u_bulk=0.03, amp=0.1, seed=1234, kmax=2)
+    rng = np.random.default_rng(77)
+    sel = np.unique(np.concatenate([
+        rng.integers(0, nx * ny * nz, 3000),
+        # wall rows and periodic seams
+        np.array([(z * ny + y) * nx + x for x in (0, 1, nx - 1) for y in (0, ny - 1) for z in (0, nz - 1)]),
+    ]))
+    om = O.omega_table(nu)
+    with L.Lattice(L.Config(nx, ny, nz, storage="f32", walls_y=True, nu=nu, force=F)) as lat:
+        lat.init(rho, u)
+        lat.step(5)
+        g_prev = lat.get_f()
+        lat.step(1)
+        g_next = lat.get_f().reshape(27, -1)[:, sel]
+    ref = O.step_nodes(g_prev, sel, om, F, walls_y=True)
+    tol = 4e-7 * W_ALPHA.reshape(27, 1) * 2
+    ratio = float((np.abs(g_next - ref) / tol).max())
+    assert ratio <= 1.0, ratio
