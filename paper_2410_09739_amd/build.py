@@ -22,6 +22,23 @@ FLAGS = [
 ]
 
 
+HOST_CHECK_SRC = os.path.join(os.path.dirname(HERE), "tests", "native", "collide_host.hip")
+HOST_CHECK_OUT = os.path.join(os.path.dirname(HERE), "tests", "native", "libcollide_host.so")
+
+
+def build_host_check() -> str:
+    """Host-only build of the kernels' per-node arithmetic, used by CPU tests."""
+    tmp = HOST_CHECK_OUT + ".tmp"
+    cmd = [HIPCC, "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+           "-Wno-unused-command-line-argument", "-o", tmp, HOST_CHECK_SRC]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed for " + HOST_CHECK_SRC)
+    os.replace(tmp, HOST_CHECK_OUT)
+    return HOST_CHECK_OUT
+
+
 def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     cmd = [HIPCC, *FLAGS, "-o", tmp, SRC]
@@ -37,3 +54,5 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    if os.path.exists(HOST_CHECK_SRC):
+        print(build_host_check())

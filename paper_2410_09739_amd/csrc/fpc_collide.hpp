@@ -14,7 +14,9 @@
 // Each sweep also carries the rest state's contribution as a compile-time
 // constant W, so that the cube ends up holding kappa' = kappa - E with
 // E_abc = C1[a] C1[b] C1[c] the rest-state central moments (C1 = 1, 0, c_s^2).
-// Steps 4 and 5 (m~ = F^-1 kappa~, f~ = P^-1 m~) are the inverse sweeps.
+// Steps 4 and 5 (m~ = F^-1 kappa~, f~ = P^-1 m~) are the inverse sweeps; they
+// return each deviation times an exact power of two (inv_shift), which the
+// caller removes when it stores the value.
 //
 // The collision (Step 3) relaxes the primed moments in the paper's order:
 // orders 0-2 (grouped 2s1/2d1/2d2), decomposition, order 3 (3s*/3m*, 111),
@@ -28,6 +30,8 @@
 // product kappa~_110 kappa~_012 that the general attractor formula gives.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include "d3q27.hpp"
 
 namespace fpc {
@@ -35,6 +39,7 @@ namespace fpc {
 template <typename T>
 struct Rates {
   T w[Q];   // omega_0 .. omega_26 (Appendix D numbering)
+  T c[Q];   // 1 - omega_j
   T h[Q];   // 1 - omega_j / 2
 };
 
@@ -43,7 +48,7 @@ struct Rates {
 // from W * (1/6, 2/3, 1/6)  ->  central moments (r0, r1, r2) about u, minus
 // W * (1, 0, 1/3).
 template <typename T, int WNUM_IS_ZERO>
-__device__ __forceinline__ void fwd3(T& a0, T& a1, T& a2, T u, T W) {
+__host__ __device__ __forceinline__ void fwd3(T& a0, T& a1, T& a2, T u, T W) {
   const T s0 = a0 + a1 + a2;
   const T d1 = a2 - a0;
   const T sp = a2 + a0;
@@ -53,24 +58,31 @@ __device__ __forceinline__ void fwd3(T& a0, T& a1, T& a2, T u, T W) {
   a2 = sp - T(2) * u * d1 + u * u * S;
 }
 
-// Inverse: (r0, r1, r2) as produced by fwd3 -> deviations at e = -1, 0, +1.
+// Inverse: (r0, r1, r2) as produced by fwd3 -> deviations at e = -1, 0, +1,
+// with the two outer values returned doubled: with the raw moments
+// m1 = R0 u + r1 and m2 = R0 u^2 + 2 u r1 + r2 (R0 = r0 + W) of the line,
+// the values are d(0) = r0 - m2 and d(+-1) = (m2 +- m1) / 2; the halving is
+// left to the caller (an exact power of two folded into the store).
 template <typename T, int WNUM_IS_ZERO>
-__device__ __forceinline__ void inv3(T& a0, T& a1, T& a2, T u, T W) {
+__host__ __device__ __forceinline__ void inv3(T& a0, T& a1, T& a2, T u, T u2, T two_u, T W) {
   const T r0 = a0, r1 = a1, r2 = a2;
   const T R0 = WNUM_IS_ZERO ? r0 : r0 + W;
-  const T u2 = u * u;
-  a1 = r0 - R0 * u2 - T(2) * u * r1 - r2;
-  a2 = T(0.5) * (R0 * (u2 + u) + r1 * (T(2) * u + T(1)) + r2);
-  a0 = T(0.5) * (R0 * (u2 - u) + r1 * (T(2) * u - T(1)) + r2);
+  const T m1 = R0 * u + r1;
+  const T m2 = R0 * u2 + (two_u * r1 + r2);
+  a1 = r0 - m2;
+  a2 = m2 + m1;
+  a0 = m2 - m1;
 }
 
-#define FPC_FWD(T, ZERO, a, b, c, u, W) fwd3<T, ZERO>(a, b, c, u, T(W))
-#define FPC_INV(T, ZERO, a, b, c, u, W) inv3<T, ZERO>(a, b, c, u, T(W))
+// log2 of the factor inverse_all leaves on the value of direction alpha:
+// one doubling per non-zero velocity component.
+constexpr int inv_shift(int a) { return (EX[a] != 0) + (EY[a] != 0) + (EZ[a] != 0); }
+constexpr double inv_factor(int a) { return 1.0 / double(1 << inv_shift(a)); }
 
 // Forward sweeps over the cube (x, then y, then z).  On return v[c][b][a] holds
 // kappa'_abc.  The x sweep is split so that rho and j come out of its line sums.
 template <typename T>
-__device__ __forceinline__ void forward_x(T (&v)[3][3][3], T ux) {
+__host__ __device__ __forceinline__ void forward_x(T (&v)[3][3][3], T ux) {
 #pragma unroll
   for (int iz = 0; iz < 3; ++iz)
 #pragma unroll
@@ -79,7 +91,7 @@ __device__ __forceinline__ void forward_x(T (&v)[3][3][3], T ux) {
 }
 
 template <typename T>
-__device__ __forceinline__ void forward_yz(T (&v)[3][3][3], T uy, T uz) {
+__host__ __device__ __forceinline__ void forward_yz(T (&v)[3][3][3], T uy, T uz) {
 #pragma unroll
   for (int iz = 0; iz < 3; ++iz) {
     fwd3<T, 0>(v[iz][0][0], v[iz][1][0], v[iz][2][0], uy, T(C1[0] * W1[iz]));
@@ -97,33 +109,42 @@ __device__ __forceinline__ void forward_yz(T (&v)[3][3][3], T uy, T uz) {
     }
 }
 
+// Inverse sweeps (z, then y, then x).  Each sweep doubles the values it writes
+// at e = +-1, so the line constants W of a later sweep are scaled by the
+// doublings its inputs already carry; on return the cube holds
+// delta_alpha * 2^inv_shift(alpha).
 template <typename T>
-__device__ __forceinline__ void inverse_all(T (&v)[3][3][3], T ux, T uy, T uz) {
+__host__ __device__ __forceinline__ void inverse_all(T (&v)[3][3][3], T ux, T uy, T uz) {
+  const T uz2 = uz * uz, uy2 = uy * uy, ux2 = ux * ux;
+  const T tz = uz + uz, ty = uy + uy, tx = ux + ux;
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (a == 1 || b == 1)
-        inv3<T, 1>(v[0][b][a], v[1][b][a], v[2][b][a], uz, T(0));
+        inv3<T, 1>(v[0][b][a], v[1][b][a], v[2][b][a], uz, uz2, tz, T(0));
       else
-        inv3<T, 0>(v[0][b][a], v[1][b][a], v[2][b][a], uz, T(C1[a] * C1[b]));
+        inv3<T, 0>(v[0][b][a], v[1][b][a], v[2][b][a], uz, uz2, tz, T(C1[a] * C1[b]));
     }
 #pragma unroll
   for (int iz = 0; iz < 3; ++iz) {
-    inv3<T, 0>(v[iz][0][0], v[iz][1][0], v[iz][2][0], uy, T(C1[0] * W1[iz]));
-    inv3<T, 1>(v[iz][0][1], v[iz][1][1], v[iz][2][1], uy, T(0));
-    inv3<T, 0>(v[iz][0][2], v[iz][1][2], v[iz][2][2], uy, T(C1[2] * W1[iz]));
+    const double sz = iz == 1 ? 1.0 : 2.0;
+    inv3<T, 0>(v[iz][0][0], v[iz][1][0], v[iz][2][0], uy, uy2, ty, T(C1[0] * W1[iz] * sz));
+    inv3<T, 1>(v[iz][0][1], v[iz][1][1], v[iz][2][1], uy, uy2, ty, T(0));
+    inv3<T, 0>(v[iz][0][2], v[iz][1][2], v[iz][2][2], uy, uy2, ty, T(C1[2] * W1[iz] * sz));
   }
 #pragma unroll
   for (int iz = 0; iz < 3; ++iz)
 #pragma unroll
-    for (int iy = 0; iy < 3; ++iy)
-      inv3<T, 0>(v[iz][iy][0], v[iz][iy][1], v[iz][iy][2], ux, T(W1[iy] * W1[iz]));
+    for (int iy = 0; iy < 3; ++iy) {
+      const double syz = (iz == 1 ? 1.0 : 2.0) * (iy == 1 ? 1.0 : 2.0);
+      inv3<T, 0>(v[iz][iy][0], v[iz][iy][1], v[iz][iy][2], ux, ux2, tx, T(W1[iy] * W1[iz] * syz));
+    }
 }
 
 // Macroscopic fields from the deviation cube: rho' = sum delta, j = sum delta e.
 template <typename T>
-__device__ __forceinline__ void density_momentum(const T (&v)[3][3][3], T& rhop, T& jx, T& jy, T& jz) {
+__host__ __device__ __forceinline__ void density_momentum(const T (&v)[3][3][3], T& rhop, T& jx, T& jy, T& jz) {
   T s[3][3];
   jx = T(0);
 #pragma unroll
@@ -140,11 +161,13 @@ __device__ __forceinline__ void density_momentum(const T (&v)[3][3][3], T& rhop,
 
 // ---------------------------------------------------------------------------
 // Collision of one node.  v: deviation cube in, post-collision deviations out.
-// F: body force.  ws[6]: the second-order rates omega_4..omega_9 to use at this
-// node (the rates table, or a per-node closure).  Returns rho and u (Step 7).
+// F: body force.  ws[6], cs[6]: the second-order rates omega_4..omega_9 to use
+// at this node (the rates table, or a per-node closure) and 1 - ws.  Returns
+// rho and u (Step 7).
 template <typename T, bool FORCE>
-__device__ __forceinline__ void collide(T (&v)[3][3][3], const Rates<T>& R, const T (&ws)[6],
-                                        T Fx, T Fy, T Fz, T& rho_out, T& ux, T& uy, T& uz) {
+__host__ __device__ __forceinline__ void collide(T (&v)[3][3][3], const Rates<T>& R, const T (&ws)[6],
+                                                 const T (&cs)[6], T Fx, T Fy, T Fz, T& rho_out, T& ux,
+                                                 T& uy, T& uz) {
   const T third = T(1.0 / 3.0), ninth = T(1.0 / 9.0);
   T rhop, jx, jy, jz;
   density_momentum(v, rhop, jx, jy, jz);
@@ -207,29 +230,30 @@ __device__ __forceinline__ void collide(T (&v)[3][3][3], const Rates<T>& R, cons
   }
 
   // ---- orders 0-2.  kappa~_000 = rho' (conserved); first order: attractor 0.
-  const T t100 = k100 - R.w[1] * k100 + R.h[1] * s100;
-  const T t010 = k010 - R.w[2] * k010 + R.h[2] * s010;
-  const T t001 = k001 - R.w[3] * k001 + R.h[3] * s001;
-  const T t110 = (T(1) - ws[0]) * k110;  // sigma_110 = 0
-  const T t101 = (T(1) - ws[1]) * k101;
-  const T t011 = (T(1) - ws[2]) * k011;
+  // First order: kappa = -F/2 before collision (u carries the F/2 shift), so
+  // kappa + omega (0 - kappa) + (1 - omega/2) F = F/2 for every omega_1..3.
+  const T t100 = T(0.5) * s100, t010 = T(0.5) * s010, t001 = T(0.5) * s001;
+  (void)k100; (void)k010; (void)k001;
+  const T t110 = cs[0] * k110;  // sigma_110 = 0
+  const T t101 = cs[1] * k101;
+  const T t011 = cs[2] * k011;
   const T c2s1 = k200 + k020 + k002;      // primed: attractor rho c_s^2 * 3 -> rho'
   const T c2d1 = k200 - k020, c2d2 = k200 - k002;
   const T t2s1 = c2s1 + ws[3] * (rhop - c2s1);  // sigma_200 = sigma_020 = sigma_002 = 0
-  const T t2d1 = (T(1) - ws[4]) * c2d1;
-  const T t2d2 = (T(1) - ws[5]) * c2d2;
+  const T t2d1 = cs[4] * c2d1;
+  const T t2d2 = cs[5] * c2d2;
   const T t200 = third * (t2s1 + t2d1 + t2d2);
   const T t020 = third * (t2s1 - T(2) * t2d1 + t2d2);
   const T t002 = third * (t2s1 + t2d1 - T(2) * t2d2);
 
   // ---- order 3: attractors 0.
-  const T t3s1 = (T(1) - R.w[10]) * (k120 + k102) + R.h[10] * (s120 + s102);
-  const T t3m1 = (T(1) - R.w[11]) * (k120 - k102) + R.h[11] * (s120 - s102);
-  const T t3s2 = (T(1) - R.w[12]) * (k210 + k012) + R.h[12] * (s210 + s012);
-  const T t3m2 = (T(1) - R.w[13]) * (k210 - k012) + R.h[13] * (s210 - s012);
-  const T t3s3 = (T(1) - R.w[14]) * (k201 + k021) + R.h[14] * (s201 + s021);
-  const T t3m3 = (T(1) - R.w[15]) * (k201 - k021) + R.h[15] * (s201 - s021);
-  const T t111 = (T(1) - R.w[16]) * k111 + R.h[16] * s111;
+  const T t3s1 = R.c[10] * (k120 + k102) + R.h[10] * (s120 + s102);
+  const T t3m1 = R.c[11] * (k120 - k102) + R.h[11] * (s120 - s102);
+  const T t3s2 = R.c[12] * (k210 + k012) + R.h[12] * (s210 + s012);
+  const T t3m2 = R.c[13] * (k210 - k012) + R.h[13] * (s210 - s012);
+  const T t3s3 = R.c[14] * (k201 + k021) + R.h[14] * (s201 + s021);
+  const T t3m3 = R.c[15] * (k201 - k021) + R.h[15] * (s201 - s021);
+  const T t111 = R.c[16] * k111 + R.h[16] * s111;
   const T t120 = T(0.5) * (t3s1 + t3m1), t102 = T(0.5) * (t3s1 - t3m1);
   const T t210 = T(0.5) * (t3s2 + t3m2), t012 = T(0.5) * (t3s2 - t3m2);
   const T t201 = T(0.5) * (t3s3 + t3m3), t021 = T(0.5) * (t3s3 - t3m3);

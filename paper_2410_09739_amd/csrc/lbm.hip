@@ -1,7 +1,7 @@
 // lbm.hip -- gfx950 kernels and the C ABI of include/lbm.h.
 //
 // Data layout in HBM: two state buffers (A/B, ping-pong), each 27 direction
-// arrays of `stride` values (stride = N rounded up to 256 values), node index
+// arrays of `stride` values (N rounded up to 256, plus kStridePad), node index
 // i = x + nx (y + ny z).  A step reads the previous post-collision state from
 // one buffer with a pull gather (f_alpha(x) = f~_alpha(x - e_alpha), Appendix D
 // Step 6; halfway bounce-back takes the node's own opposite population) and
@@ -33,7 +33,8 @@ struct Stor<LBM_F64> {
   using S = double;
   using R = double;
   static __device__ __forceinline__ R dec(S s, int) { return s; }
-  static __device__ __forceinline__ S enc(R r, int) { return r; }
+  // f: exact power of two still carried by r (see inverse_all)
+  static __device__ __forceinline__ S enc(R r, int, double f = 1.0) { return r * f; }
 };
 
 template <>
@@ -41,7 +42,7 @@ struct Stor<LBM_F32> {
   using S = float;
   using R = float;
   static __device__ __forceinline__ R dec(S s, int) { return s; }
-  static __device__ __forceinline__ S enc(R r, int) { return r; }
+  static __device__ __forceinline__ S enc(R r, int, double f = 1.0) { return r * (float)f; }
 };
 
 template <>
@@ -50,7 +51,7 @@ struct Stor<LBM_F16DEV> {
   using R = float;
   static __device__ __forceinline__ R dec(S s, int a) { return (float)s * (1.0f / dev_scale(a)); }
   // float -> half conversion rounds to nearest even (default rounding mode)
-  static __device__ __forceinline__ S enc(R r, int a) { return (_Float16)(r * dev_scale(a)); }
+  static __device__ __forceinline__ S enc(R r, int a, double f = 1.0) { return (_Float16)(r * (float)(dev_scale(a) * f)); }
 };
 
 template <>
@@ -60,11 +61,10 @@ struct Stor<LBM_BF16DEV> {
   static __device__ __forceinline__ R dec(S s, int a) {
     return __uint_as_float((uint32_t)s << 16) * (1.0f / dev_scale(a));
   }
-  // round to nearest even on the 16 dropped bits; NaN stays NaN
-  static __device__ __forceinline__ S enc(R r, int a) {
-    const uint32_t u = __float_as_uint(r * dev_scale(a));
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (S)((u >> 16) | 0x40u);
-    return (S)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  // hardware conversion (v_cvt_pk_bf16_f32): round to nearest even, NaN stays NaN
+  static __device__ __forceinline__ S enc(R r, int a, double f = 1.0) {
+    const __bf16 h = (__bf16)(r * (float)(dev_scale(a) * f));
+    return __builtin_bit_cast(uint16_t, h);
   }
 };
 
@@ -83,45 +83,70 @@ struct StepArgs {
 // ===========================================================================
 // fused stream + collide
 //
-// One thread per node; a block covers BX x BY nodes of one z plane.
-template <int ST, bool WALLS, bool FORCE>
+// One thread per node.  ROW = true: a block is one segment of an x row, so y
+// and z are uniform across the wavefront and every row/plane offset lives in
+// scalar registers; the only per-lane address terms are the three x offsets.
+// ROW = false: 2D blocks (small nx), y per lane.  All addresses are a uniform
+// 64-bit base per direction plus a 32-bit per-lane byte offset (the state of
+// one direction is < 4 GiB, checked at creation).
+template <int ST, bool WALLS, bool FORCE, bool ROW>
 __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>::S* __restrict__ src,
                                                         typename Stor<ST>::S* __restrict__ dst,
                                                         StepArgs<typename Stor<ST>::R> A) {
   using T = typename Stor<ST>::R;
+  using S = typename Stor<ST>::S;
   using SS = Stor<ST>;
+  constexpr uint32_t SZ = sizeof(S);
   const int nx = A.g.nx, ny = A.g.ny, nz = A.g.nz;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int y = ROW ? (int)blockIdx.y : (int)(blockIdx.y * blockDim.y + threadIdx.y);
   const int z = blockIdx.z;
-  if (x >= nx || y >= ny) return;
-  const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};  // source x for e_x = -1, 0, +1
-  const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
-  const int zs[3] = {z == nz - 1 ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
-  const int i = (z * ny + y) * nx + x;
-  const int64_t st = A.g.stride;
+  if (x >= nx || (!ROW && y >= ny)) return;
+  const uint32_t rowb = (uint32_t)nx * SZ;
+  const uint32_t planeb = rowb * (uint32_t)ny;
+  // byte offsets of the source x, y, z for e = -1, 0, +1 (periodic wrap)
+  const uint32_t x0 = (uint32_t)x * SZ;
+  const uint32_t xb[3] = {x == nx - 1 ? 0u : x0 + SZ, x0, x == 0 ? rowb - SZ : x0 - SZ};
+  const uint32_t y0 = (uint32_t)y * rowb;
+  const uint32_t yb[3] = {y == ny - 1 ? 0u : y0 + rowb, y0, y == 0 ? planeb - rowb : y0 - rowb};
+  const uint32_t z0 = (uint32_t)z * planeb;
+  const uint32_t zb[3] = {z == nz - 1 ? 0u : z0 + planeb, z0, z == 0 ? (uint32_t)(nz - 1) * planeb : z0 - planeb};
+  const uint64_t stb = (uint64_t)A.g.stride * SZ;
+  const char* __restrict__ sb = (const char*)src;
+  char* __restrict__ db = (char*)dst;
 
   T v[3][3][3];
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     const int ex = EX[a], ey = EY[a], ez = EZ[a];
+    // halfway bounce-back: if x - e_alpha is a wall node, take the node's own
+    // opposite population (same weight, so the deviation carries over)
+    const bool bb = WALLS && ((ey == 1 && y == 0) || (ey == -1 && y == ny - 1));
+    const int o = opposite(a);
     T val;
-    if (WALLS && ((ey == 1 && y == 0) || (ey == -1 && y == ny - 1))) {
-      val = SS::dec(src[opposite(a) * st + i], opposite(a));  // halfway bounce-back
-      // the stored value is a deviation from w_opp = w_alpha
+    if (ROW) {
+      // bb is uniform here: the base is chosen in scalar registers
+      const char* base = bb ? sb + o * stb + (uint64_t)(z0 + y0) : sb + a * stb + (uint64_t)(zb[ez + 1] + yb[ey + 1]);
+      const uint32_t off = bb ? x0 : xb[ex + 1];
+      val = SS::dec(*(const S*)(base + off), a);  // w_opp = w_alpha, scales equal
+    } else if (bb) {
+      val = SS::dec(*(const S*)(sb + o * stb + (uint32_t)(z0 + y0 + x0)), o);
     } else {
-      const int j = (zs[ez + 1] * ny + ys[ey + 1]) * nx + xs[ex + 1];
-      val = SS::dec(src[a * st + j], a);
+      val = SS::dec(*(const S*)(sb + a * stb + (uint32_t)(zb[ez + 1] + yb[ey + 1] + xb[ex + 1])), a);
     }
     v[ez + 1][ey + 1][ex + 1] = val;
   }
 
   const T ws[6] = {A.r.w[4], A.r.w[5], A.r.w[6], A.r.w[7], A.r.w[8], A.r.w[9]};
+  const T cs[6] = {A.r.c[4], A.r.c[5], A.r.c[6], A.r.c[7], A.r.c[8], A.r.c[9]};
   T rho, ux, uy, uz;
-  collide<T, FORCE>(v, A.r, ws, A.F[0], A.F[1], A.F[2], rho, ux, uy, uz);
+  collide<T, FORCE>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rho, ux, uy, uz);
 
 #pragma unroll
-  for (int a = 0; a < Q; ++a) dst[a * st + i] = SS::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a);
+  for (int a = 0; a < Q; ++a) {
+    S* p = ROW ? (S*)(db + a * stb + (uint64_t)(z0 + y0) + x0) : (S*)(db + a * stb + (uint32_t)(z0 + y0 + x0));
+    *p = SS::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
+  }
 }
 
 // ===========================================================================
@@ -144,7 +169,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, co
       for (int a = 0; a < 3; ++a) v[c][b][a] = rp * T(C1[a] * C1[b] * C1[c]);
   inverse_all(v, ux, uy, uz);
 #pragma unroll
-  for (int a = 0; a < Q; ++a) dst[a * st + i] = Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a);
+  for (int a = 0; a < Q; ++a) dst[a * st + i] = Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
 }
 
 template <int ST>
@@ -368,13 +393,32 @@ struct lbm_ctx {
 
 static char g_create_err[512] = "";
 
-// 256-thread blocks: a row segment of up to 256 nodes along x, and as many rows
-// along y as fill the block when nx is small.
-static void step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid) {
-  const int bx = nx >= 256 ? 256 : (nx + 31) / 32 * 32;
+// Values between the starts of consecutive direction arrays beyond N (rounded
+// to 256): staggers the 27 arrays so that a power-of-two N does not put the
+// same element of every direction at the same HBM channel offset (measured:
+// a few per cent at 256x128x128 and 512^3).
+constexpr int64_t kStridePad = 4352;
+
+// Launch shape of the stream-collide kernel.  Row blocks (one x-row segment of
+// 256, 192 or 128 nodes, whichever divides nx; 256 with a ragged tail for other
+// nx >= 256) when nx >= 128, otherwise 2D blocks of 256 threads covering
+// several rows.  Returns true for row blocks.
+static bool step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid) {
+  if (nx >= 128) {
+    int bx = 256;
+    if (nx % 256 != 0) {
+      if (nx % 192 == 0) bx = 192;
+      else if (nx % 128 == 0) bx = 128;
+    }
+    block = dim3(bx, 1, 1);
+    grid = dim3((nx + bx - 1) / bx, ny, nz);
+    return true;
+  }
+  const int bx = (nx + 31) / 32 * 32;
   const int by = 256 / bx;
   block = dim3(bx, by, 1);
-  grid = dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nz);
+  grid = dim3(1, (ny + by - 1) / by, nz);
+  return false;
 }
 
 static int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
@@ -460,6 +504,8 @@ extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     if (cfg->nz > 65535 || (cfg->ny + (int)blk.y - 1) / (int)blk.y > 65535)
       return set_err(nullptr, LBM_EINVAL, "lbm_create: nz and the y extent of the launch grid must be <= 65535");
   }
+  if ((uint64_t)((n + 255) / 256 * 256 + kStridePad) * elem_size(cfg->storage) >= ((uint64_t)1 << 32))
+    return set_err(nullptr, LBM_EINVAL, "lbm_create: one direction array must stay below 4 GiB (N * bytes per value)");
   const size_t es = elem_size(cfg->storage);
   if (!es) return set_err(nullptr, LBM_EINVAL, "lbm_create: unknown storage %d", cfg->storage);
   if (cfg->walls_y != 0 && cfg->walls_y != 1) return set_err(nullptr, LBM_EINVAL, "lbm_create: walls_y must be 0 or 1");
@@ -474,7 +520,7 @@ extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   c->cfg = *cfg;
   std::memcpy(c->omega, w, sizeof w);
   c->n = n;
-  c->stride = (n + 255) / 256 * 256;
+  c->stride = (n + 255) / 256 * 256 + kStridePad;
   c->elem = es;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) {
@@ -568,23 +614,25 @@ static int launch_steps(lbm_ctx* c, int64_t nsteps) {
   A.g = Geom{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->stride};
   for (int j = 0; j < LBM_Q; ++j) {
     A.r.w[j] = (T)c->omega[j];
+    A.r.c[j] = (T)(1.0 - c->omega[j]);
     A.r.h[j] = (T)(1.0 - 0.5 * c->omega[j]);
   }
   for (int d = 0; d < 3; ++d) A.F[d] = (T)c->cfg.force[d];
   const bool force = c->cfg.force[0] != 0.0 || c->cfg.force[1] != 0.0 || c->cfg.force[2] != 0.0;
   const bool walls = c->cfg.walls_y != 0;
   dim3 block, grid;
-  step_launch_shape(c->cfg.nx, c->cfg.ny, c->cfg.nz, block, grid);
+  const bool row = step_launch_shape(c->cfg.nx, c->cfg.ny, c->cfg.nz, block, grid);
+  using KFn = void (*)(const S*, S*, StepArgs<T>);
+  static const KFn table[2][2][2] = {
+      {{k_stream_collide<ST, false, false, false>, k_stream_collide<ST, false, false, true>},
+       {k_stream_collide<ST, false, true, false>, k_stream_collide<ST, false, true, true>}},
+      {{k_stream_collide<ST, true, false, false>, k_stream_collide<ST, true, false, true>},
+       {k_stream_collide<ST, true, true, false>, k_stream_collide<ST, true, true, true>}}};
+  const KFn kern = table[walls][force][row];
   for (int64_t s = 0; s < nsteps; ++s) {
     const S* src = (const S*)c->buf[c->cur];
     S* dst = (S*)c->buf[c->cur ^ 1];
-    if (walls) {
-      if (force) k_stream_collide<ST, true, true><<<grid, block, 0, c->stream>>>(src, dst, A);
-      else k_stream_collide<ST, true, false><<<grid, block, 0, c->stream>>>(src, dst, A);
-    } else {
-      if (force) k_stream_collide<ST, false, true><<<grid, block, 0, c->stream>>>(src, dst, A);
-      else k_stream_collide<ST, false, false><<<grid, block, 0, c->stream>>>(src, dst, A);
-    }
+    kern<<<grid, block, 0, c->stream>>>(src, dst, A);
     LAUNCHCHK(c);
     c->cur ^= 1;
     c->steps++;

@@ -1,0 +1,45 @@
+// Host build of the kernels' per-node arithmetic (paper_2410_09739_amd/csrc/fpc_collide.hpp)
+// for CPU-side tests against the oracle.  It runs the same __host__ __device__
+// sweeps and collision the GPU runs, on one node given as 27 populations.
+#include <cstdint>
+
+#include "../../paper_2410_09739_amd/csrc/fpc_collide.hpp"
+
+using namespace fpc;
+
+template <typename T>
+static void run(const double* f, const double* omega, const double* F, double* out) {
+  T v[3][3][3];
+  for (int a = 0; a < Q; ++a) v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] = (T)(f[a] - weight(a));
+  Rates<T> R;
+  for (int j = 0; j < Q; ++j) {
+    R.w[j] = (T)omega[j];
+    R.c[j] = (T)(1.0 - omega[j]);
+    R.h[j] = (T)(1.0 - 0.5 * omega[j]);
+  }
+  const T ws[6] = {R.w[4], R.w[5], R.w[6], R.w[7], R.w[8], R.w[9]};
+  const T cs[6] = {R.c[4], R.c[5], R.c[6], R.c[7], R.c[8], R.c[9]};
+  T rho, ux, uy, uz;
+  const bool force = F[0] != 0.0 || F[1] != 0.0 || F[2] != 0.0;
+  if (force)
+    collide<T, true>(v, R, ws, cs, (T)F[0], (T)F[1], (T)F[2], rho, ux, uy, uz);
+  else
+    collide<T, false>(v, R, ws, cs, T(0), T(0), T(0), rho, ux, uy, uz);
+  for (int a = 0; a < Q; ++a) out[a] = weight(a) + (double)(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] * (T)inv_factor(a));
+}
+
+extern "C" void host_collide_f64(const double* f, const double* omega, const double* F, double* out) {
+  run<double>(f, omega, F, out);
+}
+extern "C" void host_collide_f32(const double* f, const double* omega, const double* F, double* out) {
+  run<float>(f, omega, F, out);
+}
+// f^eq(rho, u) through the kernels' inverse sweeps (what lbm_init stores)
+extern "C" void host_feq_f64(double rho, const double* u, double* out) {
+  double v[3][3][3];
+  for (int c = 0; c < 3; ++c)
+    for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < 3; ++a) v[c][b][a] = (rho - 1.0) * C1[a] * C1[b] * C1[c];
+  inverse_all(v, u[0], u[1], u[2]);
+  for (int a = 0; a < Q; ++a) out[a] = weight(a) + v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] * inv_factor(a);
+}

@@ -1,0 +1,62 @@
+"""The kernels' per-node arithmetic (fpc_collide.hpp), compiled for the host,
+against the FP64 oracle on the CPU: catches transform or collision mistakes in
+the HIP path before any GPU run.  FP64: 1e-13 relative to max(|f|, w_alpha);
+FP32: the per-step FP32 bound of the GPU parity tests (4e-7 w_alpha)."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2410_09739_amd import workloads as W
+
+LIB = os.path.join(os.path.dirname(__file__), "native", "libcollide_host.so")
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+@pytest.fixture(scope="module")
+def host():
+    if not os.path.exists(LIB):
+        from paper_2410_09739_amd import build
+        build.build_host_check()
+    lib = ctypes.CDLL(LIB)
+    for n in ("host_collide_f64", "host_collide_f32"):
+        getattr(lib, n).argtypes = [_dp, _dp, _dp, _dp]
+    lib.host_feq_f64.argtypes = [ctypes.c_double, _dp, _dp]
+    return lib
+
+
+def _call(fn, f, om, F):
+    out = np.zeros(27)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (f, om, F)]
+    fn(*(x.ctypes.data_as(_dp) for x in a), out.ctypes.data_as(_dp))
+    return out
+
+
+WA = O.feq(1.0, [0, 0, 0])
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_host_collision_matches_oracle(host, seed):
+    rng = np.random.default_rng(100 + seed)
+    u = 0.1 * rng.uniform(-1, 1, 3)
+    f = O.feq(1 + 0.05 * rng.uniform(-1, 1), u) * W.random_factors(27, seed, 0.2)
+    mode = ["paper", "order_scaled", "explicit"][seed % 3]
+    om = O.omega_table(10 ** rng.uniform(-5, -0.5), omega_bulk=rng.uniform(0.5, 1.9),
+                       omega_higher=rng.uniform(0.5, 1.9), mode=mode, explicit=rng.uniform(0.1, 1.99, 27))
+    F = 1e-4 * rng.uniform(-1, 1, 3) if seed % 2 else np.zeros(3)
+    ref = O.collide_node(f, om, F)
+    got = _call(host.host_collide_f64, f, om, F)
+    err = np.max(np.abs(got - ref) / np.maximum(np.abs(ref), WA))
+    assert err <= 1e-13, err
+    got32 = _call(host.host_collide_f32, f, om, F)
+    assert np.all(np.abs(got32 - ref) <= 4e-7 * WA), np.max(np.abs(got32 - ref) / WA)
+
+
+@pytest.mark.parametrize("rho,u", [(1.0, (0, 0, 0)), (1.04, (0.06, -0.02, 0.09)), (0.95, (-0.2, 0.15, 0.05))])
+def test_host_equilibrium_matches_oracle(host, rho, u):
+    out = np.zeros(27)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    host.host_feq_f64(rho, uu.ctypes.data_as(_dp), out.ctypes.data_as(_dp))
+    np.testing.assert_allclose(out, O.feq(rho, u), rtol=0, atol=4e-16)
