@@ -172,6 +172,80 @@ void lbm_destroy(lbm_ctx* c);
  * Valid until the next call on the same context. */
 const char* lbm_last_error(const lbm_ctx* c);
 
+/* ---------------------------------------------------------------------------
+ * Learned second-order closure (not part of the paper; see the design notes).
+ * A per-node network 27 -> 64 -> 64 -> 6 (ReLU hidden layers) maps features of
+ * the node's pre-collision central moments (Appendix D Step 2) to eddy
+ * viscosities nu_t,j of the six second-order groups relaxed with omega_4..9
+ * (110, 101, 011, 2s1, 2d1, 2d2), applied through Eq. (transportcoeff3DFPCLBM)
+ * as 1/omega_j,eff = 1/omega_j + 3 clamp(nu_t,j, 0, 1/3).
+ * Features: x_000 = rho - 1; for the other 26 moments, in the paper's order,
+ * (kappa_abc - rho c_a c_b c_c) / rho * 3^((a+b+c)/2).
+ * Parameters: LBM_CLOSURE_NPARAM floats W1[64][27] b1[64] W2[64][64] b2[64]
+ * W3[6][64] b3[6] (row-major, W[out][in]) acting on raw features.  The fused
+ * kernel rounds weights and activations to BF16 and accumulates in FP32 on
+ * the matrix cores.
+ */
+
+/* Enables the closure in lbm_step (params != NULL, copied) or disables it
+ * (NULL).  Requires nx % 64 == 0.  Synchronous. */
+int lbm_set_closure(lbm_ctx* c, const float* params);
+
+/* Features the next collision would see at every node, to caller device memory
+ * x_dev [N][27] (float).  Enqueued on the context's stream. */
+int lbm_closure_features(lbm_ctx* c, float* x_dev);
+
+/* The fused kernel's BF16 MFMA evaluation of the network on given features:
+ * x_dev [n][27] -> nu_dev [n][6] (device, float).  Synchronous on hip_stream
+ * (NULL: the null stream).  Errors: lbm_mlp_last_error(NULL). */
+int lbm_closure_eval(const float* params, const float* x_dev, float* nu_dev, int64_t n, void* hip_stream);
+
+/* 2x2x2 box filter of the current state of c (nx, ny, nz even) onto the
+ * coarse grid (nx/2, ny/2, nz/2), caller device memory, FP64:
+ * rho_dev [Nc] (mean density), u_dev [3][Nc] (Favre velocity avg(rho u)/avg(rho)),
+ * tau_dev [6][Nc] (sub-filter stress avg(rho u_i u_j) - rho u_i u_j; xx, yy, zz,
+ * xy, xz, yz).  Fine rho, u are the Step 7 fields.  Enqueued on the stream. */
+int lbm_coarsen(lbm_ctx* c, double* rho_dev, double* u_dev, double* tau_dev);
+
+/* lbm_init from device fields rho_dev [N], u_dev [3][N] (FP64).  Synchronous. */
+int lbm_init_device(lbm_ctx* c, const double* rho_dev, const double* u_dev);
+
+/* Eddy-viscosity targets on the grid of c from filtered fields (as written by
+ * lbm_coarsen): per node y_dev[i][6] (float) =
+ * max(0, -tau_j S_j / (2 rho (S_j^2 + eps^2))) for the groups 110, 101, 011,
+ * 2d1, 2d2 (tau_j, S_j: xy, xz, yz, xx-yy, xx-zz) and 0 for 2s1; S is the
+ * strain rate of u by centred differences (periodic, or an antisymmetric ghost
+ * across the walls); eps = eps_rel * rms(S), rms over the 3 N entries of
+ * S_ii^2 + 2 S_ij^2.  Synchronous. */
+int lbm_closure_targets(lbm_ctx* c, const double* rho_dev, const double* u_dev, const double* tau_dev,
+                        double eps_rel, float* y_dev);
+
+/* Training of the closure network on the GPU (FP32 forward and backward
+ * kernels, Adam).  Inputs are standardised, (x - mu) / sigma (sigma = 0 drops a
+ * feature), targets scaled by 1 / s_y; lbm_mlp_export folds both into
+ * parameters for lbm_set_closure.  Loss: mean over the batch and the 6 outputs
+ * of the squared error.  All data pointers are device memory, float,
+ * x [n][27], y [n][6]. */
+typedef struct lbm_mlp lbm_mlp;
+int lbm_mlp_create(uint64_t seed, void* hip_stream, lbm_mlp** out); /* He-uniform init from seed */
+int lbm_mlp_set_params(lbm_mlp* m, const float* p);                /* host, standardised space; resets Adam */
+int lbm_mlp_get_params(lbm_mlp* m, float* p);                      /* host */
+int lbm_mlp_set_normalisation(lbm_mlp* m, const float* mu, const float* sigma, float s_y); /* host */
+int lbm_mlp_get_normalisation(lbm_mlp* m, float* mu, float* sigma, float* s_y);             /* host */
+/* mu, sigma per feature (population std; sigma below 1e-7 of the largest -> 0)
+ * and s_y = rms of all targets, computed on the device. */
+int lbm_mlp_fit_normalisation(lbm_mlp* m, const float* x_dev, const float* y_dev, int64_t n);
+/* full-batch loss and gradient (host grad[LBM_CLOSURE_NPARAM], may be NULL) */
+int lbm_mlp_loss_grad(lbm_mlp* m, const float* x_dev, const float* y_dev, int64_t n, double* loss, float* grad);
+/* `steps` Adam steps (beta 0.9, 0.999, eps 1e-8) on minibatches of `batch`
+ * samples drawn with replacement by a counter-based generator of (seed, step,
+ * slot); loss_out (host, `steps` entries) may be NULL.  Synchronous. */
+int lbm_mlp_train(lbm_mlp* m, const float* x_dev, const float* y_dev, int64_t n, int32_t batch, int32_t steps,
+                  float lr, uint64_t seed, double* loss_out);
+int lbm_mlp_export(lbm_mlp* m, float* params_raw); /* host, for lbm_set_closure */
+void lbm_mlp_destroy(lbm_mlp* m);
+const char* lbm_mlp_last_error(const lbm_mlp* m);
+
 #ifdef __cplusplus
 }
 #endif

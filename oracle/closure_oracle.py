@@ -199,3 +199,52 @@ def targets(rho_t: np.ndarray, tau: np.ndarray, S: np.ndarray, eps_rel: float = 
     nu = np.maximum(nu, 0.0)
     nu[3] = 0.0
     return nu
+
+
+# ------------------------------------------------------------------ reduced-precision inference
+def round_bf16(x) -> np.ndarray:
+    """Round to the nearest bfloat16 (ties to even), returned as float64.
+    Values are first rounded to float32, as the GPU holds them."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    nan = (u & 0x7FFFFFFF) > 0x7F800000
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    r = np.where(nan, (u | 0x400000) & 0xFFFF0000, r).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def forward_bf16(p, X):
+    """The network with inputs, weights, biases of layers 1-2 used as given, and
+    the quantisation of the matrix-core path: inputs, weights and the ReLU'd
+    hidden activations rounded to bfloat16; biases and sums in full precision."""
+    W1, b1, W2, b2, W3, b3 = unpack(p)
+    Xq = round_bf16(X)
+    H1 = round_bf16(np.maximum(Xq @ round_bf16(W1).T + b1.astype(np.float32), 0.0))
+    H2 = round_bf16(np.maximum(H1 @ round_bf16(W2).T + b2.astype(np.float32), 0.0))
+    return H2 @ round_bf16(W3).T + b3.astype(np.float32)
+
+
+# ------------------------------------------------------------------ minibatch sampling
+_M64 = (1 << 64) - 1
+
+
+def _mix64(z: int) -> int:
+    """SplitMix64 output function (Steele, Lea & Flood 2014)."""
+    z &= _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def sample_indices(seed: int, step: int, batch: int, n: int) -> np.ndarray:
+    """Indices of minibatch `step` (0-based): slot j draws
+    mix64(seed xor mix64(step * 0x9E3779B97F4A7C15 + j)) mod n."""
+    return np.array([_mix64(seed ^ _mix64(step * 0x9E3779B97F4A7C15 + j)) % n for j in range(batch)],
+                    dtype=np.int64)
+
+
+def closure_rates(nu: np.ndarray, omega: np.ndarray) -> np.ndarray:
+    """Per-node omega_4..omega_9 from the network outputs:
+    1/omega_eff = 1/omega + 3 clamp(nu, 0, 1/3)."""
+    nt = np.clip(np.nan_to_num(nu, nan=0.0), 0.0, 1.0 / 3.0)
+    return 1.0 / (1.0 / np.asarray(omega)[4:10] + 3.0 * nt)

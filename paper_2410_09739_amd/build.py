@@ -1,6 +1,6 @@
 """Build step of the HIP library: ``python -m paper_2410_09739_amd.build``.
 
-Compiles ``csrc/lbm.hip`` for gfx950 into ``liblbm.so`` next to this file.
+Compiles ``csrc/lbm.hip`` and ``csrc/closure.hip`` for gfx950 into ``liblbm.so`` next to this file.
 Packed FP32 instructions are disabled for all device code
 (``-target-feature -packed-fp32-ops``).
 """
@@ -11,7 +11,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "lbm.hip")
+SRCS = [os.path.join(HERE, "csrc", "lbm.hip"), os.path.join(HERE, "csrc", "closure.hip")]
 OUT = os.path.join(HERE, "liblbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -41,11 +41,11 @@ def build_host_check() -> str:
 
 def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, SRC]
+    cmd = [HIPCC, *FLAGS, "-o", tmp, *SRCS]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed for " + SRC)
+        raise RuntimeError("hipcc failed for " + " ".join(SRCS))
     if verbose:
         sys.stderr.write(res.stderr)
     os.replace(tmp, OUT)

@@ -1,0 +1,938 @@
+// closure.hip -- learned second-order closure: fused BF16-MFMA inference in the
+// stream-collide kernel, feature extraction, the 2x2x2 filter of fine runs and
+// its eddy-viscosity targets, and FP32 training kernels (forward, backward,
+// Adam) with deterministic reductions.
+//
+// Reading of the (paper-less) closure, shared with the oracle: the network maps
+// the 27 features of a node's pre-collision central moments to six eddy
+// viscosities nu_t,j for the second-order groups relaxed with omega_4..omega_9,
+// applied through Eq. (transportcoeff3DFPCLBM) as
+// 1/omega_j,eff = 1/omega_j + 3 clamp(nu_t,j, 0, 1/3).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "closure.hpp"
+#include "lbm_internal.hpp"
+
+using namespace fpc::cl;
+
+// ===========================================================================
+// host-side packing of the parameters into MFMA fragments
+static uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// params: W1[64][27] b1[64] W2[64][64] b2[64] W3[6][64] b3[6]
+static void pack_params(const float* p, std::vector<char>& out) {
+  out.assign(PACKED_BYTES, 0);
+  uint16_t* af = (uint16_t*)out.data();
+  float* bias = (float*)(out.data() + AFRAG_BYTES);
+  auto W1 = [&](int m, int k) { return k < NIN ? p[OFF_W1 + m * NIN + k] : 0.0f; };
+  auto W2 = [&](int m, int k) { return p[OFF_W2 + m * NH + k]; };
+  auto W3 = [&](int m, int k) { return m < NOUT ? p[OFF_W3 + m * NH + k] : 0.0f; };
+  for (int l = 0; l < 64; ++l) {
+    const int r = l % 32, h = l / 32;
+    for (int i = 0; i < 8; ++i) {
+      for (int mb = 0; mb < 2; ++mb)
+        for (int kb = 0; kb < 2; ++kb) af[((mb * 2 + kb) * 64 + l) * 8 + i] = f32_to_bf16_rne(W1(mb * 32 + r, 16 * kb + 8 * h + i));
+      for (int mb = 0; mb < 2; ++mb)
+        for (int q = 0; q < 4; ++q) af[((4 + mb * 4 + q) * 64 + l) * 8 + i] = f32_to_bf16_rne(W2(mb * 32 + r, unit(q, h, i)));
+      for (int q = 0; q < 4; ++q) af[((12 + q) * 64 + l) * 8 + i] = f32_to_bf16_rne(W3(r, unit(q, h, i)));
+    }
+  }
+  for (int h = 0; h < 2; ++h)
+    for (int j = 0; j < 16; ++j) {
+      const int m = 8 * (j / 4) + 4 * h + (j % 4);
+      for (int mb = 0; mb < 2; ++mb) {
+        bias[((0 + mb) * 2 + h) * 16 + j] = p[OFF_B1 + mb * 32 + m];
+        bias[((2 + mb) * 2 + h) * 16 + j] = p[OFF_B2 + mb * 32 + m];
+      }
+      bias[(4 * 2 + h) * 16 + j] = m < NOUT ? p[OFF_B3 + m] : 0.0f;
+    }
+}
+
+// ===========================================================================
+// kernels
+template <typename T>
+__device__ __forceinline__ void closure_rates(const float (&nu)[NOUT], const float (&inv_w)[6], T (&ws)[6], T (&cs)[6]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float nt = fminf(fmaxf(nu[k], 0.0f), 1.0f / 3.0f);  // NaN -> 0
+    const T w = T(1) / (T(inv_w[k]) + T(3) * T(nt));
+    ws[k] = w;
+    cs[k] = T(1) - w;
+  }
+}
+
+struct ClosureArgs {
+  float inv_w[6];  // 1 / omega_4..omega_9
+  int nxs;         // 64-node segments per x row
+  int64_t nseg;    // segments in the grid
+};
+
+// Fused stream + collide with the closure.  Each wavefront takes one 64-node
+// segment of an x row per iteration (nx % 64 == 0), so y and z are uniform
+// within the wave; blocks stay resident and loop (the packed parameters are
+// loaded into LDS once per block).
+template <int ST, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(256) void k_stream_collide_closure(const typename Stor<ST>::S* __restrict__ src,
+                                                                typename Stor<ST>::S* __restrict__ dst,
+                                                                StepArgs<typename Stor<ST>::R> A, ClosureArgs C,
+                                                                const char* __restrict__ packed) {
+  using T = typename Stor<ST>::R;
+  __shared__ __attribute__((aligned(16))) char lw[PACKED_BYTES];
+  __shared__ __attribute__((aligned(16))) __bf16 lx[4 * XTILE];
+  for (int o = threadIdx.x * 16; o < PACKED_BYTES; o += blockDim.x * 16)
+    *(uint4*)(lw + o) = *(const uint4*)(packed + o);
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  __bf16* xs = lx + wave * XTILE;
+  for (int64_t s = (int64_t)blockIdx.x * 4 + wave; s < C.nseg; s += (int64_t)gridDim.x * 4) {
+    const int xseg = (int)(s % C.nxs);
+    const int64_t row = s / C.nxs;
+    const int y = (int)(row % A.g.ny), z = (int)(row / A.g.ny);
+    const int x = xseg * 64 + lane;
+    T v[3][3][3];
+    const uint32_t ib = pull<ST, WALLS, true>(src, A.g, x, y, z, v);
+    T rhop, rho, ux, uy, uz;
+    pre_collision<T, FORCE>(v, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
+    float feat[NIN], nu[NOUT];
+    features(v, rhop, rho, feat);
+    mlp_wave(feat, nu, lw, xs);
+    T ws[6], cs[6];
+    closure_rates(nu, C.inv_w, ws, cs);
+    relax<T, FORCE>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
+    push<ST, true>(dst, A.g, y, z, ib, v);
+  }
+}
+
+// Features of the next collision at every node (no collision, no store):
+// x[i][27], i = x + nx (y + ny z).
+template <int ST, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(256) void k_closure_features(const typename Stor<ST>::S* __restrict__ src,
+                                                          StepArgs<typename Stor<ST>::R> A, float* __restrict__ out) {
+  using T = typename Stor<ST>::R;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= A.g.nx || y >= A.g.ny) return;
+  T v[3][3][3];
+  pull<ST, WALLS, false>(src, A.g, x, y, z, v);
+  T rhop, rho, ux, uy, uz;
+  pre_collision<T, FORCE>(v, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
+  float feat[NIN];
+  features(v, rhop, rho, feat);
+  const int64_t i = ((int64_t)z * A.g.ny + y) * A.g.nx + x;
+#pragma unroll
+  for (int k = 0; k < NIN; ++k) out[i * NIN + k] = feat[k];
+}
+
+// The fused kernel's network on given features: x[n][27] -> nu[n][6].
+__global__ __launch_bounds__(256) void k_closure_eval(const float* __restrict__ x, float* __restrict__ nu, int64_t n,
+                                                      const char* __restrict__ packed) {
+  __shared__ __attribute__((aligned(16))) char lw[PACKED_BYTES];
+  __shared__ __attribute__((aligned(16))) __bf16 lx[4 * XTILE];
+  for (int o = threadIdx.x * 16; o < PACKED_BYTES; o += blockDim.x * 16)
+    *(uint4*)(lw + o) = *(const uint4*)(packed + o);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float f[NIN], o[NOUT];
+#pragma unroll
+  for (int k = 0; k < NIN; ++k) f[k] = i < n ? x[i * NIN + k] : 0.0f;
+  mlp_wave(f, o, lw, lx + (threadIdx.x >> 6) * XTILE);
+  if (i < n) {
+#pragma unroll
+    for (int k = 0; k < NOUT; ++k) nu[i * NOUT + k] = o[k];
+  }
+}
+
+// 2x2x2 box filter of the fine state: per coarse node, rho~ = avg rho,
+// u~ = avg(rho u) / rho~ (Favre), tau_ij = avg(rho u_i u_j) - rho~ u~_i u~_j,
+// order xx, yy, zz, xy, xz, yz.  Fine rho, u are the Step 7 fields of the stored
+// post-collision state (rho u = sum f~ e - F/2).  FP64 throughout.
+template <int ST>
+__global__ __launch_bounds__(256) void k_coarsen(const typename Stor<ST>::S* __restrict__ src, Geom g, double Fx,
+                                                 double Fy, double Fz, double* __restrict__ rc, double* __restrict__ uc,
+                                                 double* __restrict__ tc) {
+  const int cx = g.nx / 2, cy = g.ny / 2, cz = g.nz / 2;
+  const int64_t nc = (int64_t)cx * cy * cz;
+  const int64_t ic = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ic >= nc) return;
+  const int X = (int)(ic % cx), Y = (int)((ic / cx) % cy), Z = (int)(ic / ((int64_t)cx * cy));
+  double R = 0, M[3] = {0, 0, 0}, Tm[6] = {0, 0, 0, 0, 0, 0};
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int64_t i = ((int64_t)(2 * Z + dz) * g.ny + (2 * Y + dy)) * g.nx + (2 * X + dx);
+        double rp = 0, j[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+          const double d = (double)Stor<ST>::dec(src[a * g.stride + i], a);
+          rp += d;
+          j[0] += EX[a] * d;
+          j[1] += EY[a] * d;
+          j[2] += EZ[a] * d;
+        }
+        const double r = 1.0 + rp;
+        j[0] -= 0.5 * Fx;
+        j[1] -= 0.5 * Fy;
+        j[2] -= 0.5 * Fz;
+        R += r;
+        for (int d = 0; d < 3; ++d) M[d] += j[d];
+        Tm[0] += j[0] * j[0] / r;
+        Tm[1] += j[1] * j[1] / r;
+        Tm[2] += j[2] * j[2] / r;
+        Tm[3] += j[0] * j[1] / r;
+        Tm[4] += j[0] * j[2] / r;
+        Tm[5] += j[1] * j[2] / r;
+      }
+  const double rb = R / 8.0;
+  const double u[3] = {M[0] / R, M[1] / R, M[2] / R};
+  rc[ic] = rb;
+  for (int d = 0; d < 3; ++d) uc[d * nc + ic] = u[d];
+  const int pi[6] = {0, 1, 2, 0, 0, 1}, pj[6] = {0, 1, 2, 1, 2, 2};
+  for (int k = 0; k < 6; ++k) tc[k * nc + ic] = Tm[k] / 8.0 - rb * u[pi[k]] * u[pj[k]];
+}
+
+// strain rate S_ij = (d_i u_j + d_j u_i)/2 by centred differences (periodic x,
+// z; periodic y or an antisymmetric ghost across the half-link walls), order
+// xx, yy, zz, xy, xz, yz
+__device__ __forceinline__ void strain_at(const double* __restrict__ u, const Geom& g, int walls, int64_t i,
+                                          double (&S)[6]) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+  const int xp = x == nx - 1 ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+  const int zp = z == nz - 1 ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
+  int yp = y == ny - 1 ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+  double sp = 1.0, sm = 1.0;
+  if (walls) {
+    if (y == ny - 1) { yp = y; sp = -1.0; }
+    if (y == 0) { ym = y; sm = -1.0; }
+  }
+  auto at = [&](int c, int xx, int yy, int zz) { return u[(int64_t)c * n + ((int64_t)zz * ny + yy) * nx + xx]; };
+  double gr[3][3];  // gr[i][j] = d_i u_j
+  for (int c = 0; c < 3; ++c) {
+    gr[0][c] = 0.5 * (at(c, xp, y, z) - at(c, xm, y, z));
+    gr[1][c] = 0.5 * (sp * at(c, x, yp, z) - sm * at(c, x, ym, z));
+    gr[2][c] = 0.5 * (at(c, x, y, zp) - at(c, x, y, zm));
+  }
+  S[0] = gr[0][0];
+  S[1] = gr[1][1];
+  S[2] = gr[2][2];
+  S[3] = 0.5 * (gr[0][1] + gr[1][0]);
+  S[4] = 0.5 * (gr[0][2] + gr[2][0]);
+  S[5] = 0.5 * (gr[1][2] + gr[2][1]);
+}
+
+constexpr int RB = 1024;  // blocks of the fixed-order reductions
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// deterministic block sum of one double per thread (256 threads)
+__device__ double block_sum(double v) {
+  __shared__ double sh[4];
+  v = wave_sum_d(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_strain_sq(const double* __restrict__ u, Geom g, int walls,
+                                                   double* __restrict__ part) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)RB * 256) {
+    double S[6];
+    strain_at(u, g, walls, i, S);
+    acc += S[0] * S[0] + S[1] * S[1] + S[2] * S[2] + 2.0 * (S[3] * S[3] + S[4] * S[4] + S[5] * S[5]);
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, int np, double* __restrict__ out) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < np; b += 256) acc += part[b];
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) *out = t;
+}
+
+// nu*_j = max(0, -tau_j S_j / (2 rho (S_j^2 + eps^2))) for the groups
+// 110, 101, 011, (2s1: 0), 2d1, 2d2; eps^2 = eps_rel^2 * sum / (3 n).
+__global__ __launch_bounds__(256) void k_targets(const double* __restrict__ rho, const double* __restrict__ u,
+                                                 const double* __restrict__ tau, Geom g, int walls, double eps_rel,
+                                                 const double* __restrict__ ssum, float* __restrict__ y) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double eps2 = eps_rel * eps_rel * (*ssum) / (3.0 * (double)n);
+  double S[6];
+  strain_at(u, g, walls, i, S);
+  double t[6];
+  for (int k = 0; k < 6; ++k) t[k] = tau[k * n + i];
+  const double tg[6] = {t[3], t[4], t[5], t[0] + t[1] + t[2], t[0] - t[1], t[0] - t[2]};
+  const double sg[6] = {S[3], S[4], S[5], S[0] + S[1] + S[2], S[0] - S[1], S[0] - S[2]};
+  const double r = rho[i];
+  for (int k = 0; k < 6; ++k) {
+    double nu = -tg[k] * sg[k] / (2.0 * r * (sg[k] * sg[k] + eps2));
+    nu = nu > 0.0 ? nu : 0.0;
+    if (k == 3) nu = 0.0;
+    y[i * 6 + k] = (float)nu;
+  }
+}
+
+// f~(0) = f^eq(rho, u) from device fields (what lbm_init does from host fields)
+template <int ST>
+__global__ __launch_bounds__(256) void k_init_dev(const double* __restrict__ rho, const double* __restrict__ u,
+                                                  typename Stor<ST>::S* __restrict__ dst, int64_t n, int64_t st) {
+  using T = typename Stor<ST>::R;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T rp = (T)(rho[i] - 1.0);
+  const T ux = (T)u[i], uy = (T)u[n + i], uz = (T)u[2 * n + i];
+  T v[3][3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v[c][b][a] = rp * T(C1[a] * C1[b] * C1[c]);
+  inverse_all(v, ux, uy, uz);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) dst[a * st + i] = Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
+}
+
+// ---------------------------------------------------------------------------
+// training (FP32, VALU): per-chunk forward and backward in LDS, gradients
+// accumulated per thread over the chunks a block owns, then a fixed-order
+// reduction over blocks.  Loss: mean over the batch of the 6 squared errors
+// on standardised features and scaled targets.
+constexpr int TCH = 32;           // samples per chunk
+constexpr int GB = 256;           // gradient blocks (partials)
+constexpr int GPT = (NPARAM + 255) / 256;  // gradient entries per thread (p = tid + 256 q)
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {  // splitmix64 finaliser
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int64_t sample_index(uint64_t seed, int64_t step, int64_t j, int64_t n, int sampled) {
+  if (!sampled) return j;
+  return (int64_t)(mix64(seed ^ mix64((uint64_t)step * 0x9e3779b97f4a7c15ull + (uint64_t)j)) % (uint64_t)n);
+}
+
+__global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ X, const float* __restrict__ Y, int64_t n,
+                                                  int64_t nbatch, const float* __restrict__ P,
+                                                  const float* __restrict__ mu, const float* __restrict__ isig,
+                                                  float inv_sy, uint64_t seed, int64_t step, int sampled,
+                                                  float* __restrict__ gpart, double* __restrict__ lpart) {
+  __shared__ float sP[NPARAM];
+  __shared__ float sX[TCH * NIN], sH1[TCH * NH], sH2[TCH * NH], sD[TCH * NOUT], sZ1[TCH * NH], sZ2[TCH * NH];
+  const int tid = threadIdx.x;
+  // this block's row of partial gradients; entry p belongs to thread p % 256
+  float* __restrict__ gp = gpart + (int64_t)blockIdx.x * NPARAM;
+  for (int p = tid; p < NPARAM; p += 256) {
+    sP[p] = P[p];
+    gp[p] = 0.0f;
+  }
+  double lacc = 0.0;
+  const float scale = (float)(2.0 / ((double)nbatch * NOUT));
+  const int64_t nch = (nbatch + TCH - 1) / TCH;
+  __syncthreads();
+  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    for (int e = tid; e < TCH * NIN; e += 256) {
+      const int s = e / NIN, k = e % NIN;
+      const int64_t j = c * TCH + s;
+      float val = 0.0f;
+      if (j < nbatch) val = (X[sample_index(seed, step, j, n, sampled) * NIN + k] - mu[k]) * isig[k];
+      sX[e] = val;
+    }
+    __syncthreads();
+    for (int e = tid; e < TCH * NH; e += 256) {
+      const int s = e / NH, m = e % NH;
+      float a = sP[OFF_B1 + m];
+#pragma unroll 9
+      for (int k = 0; k < NIN; ++k) a += sP[OFF_W1 + m * NIN + k] * sX[s * NIN + k];
+      sH1[e] = fmaxf(a, 0.0f);
+    }
+    __syncthreads();
+    for (int e = tid; e < TCH * NH; e += 256) {
+      const int s = e / NH, m = e % NH;
+      float a = sP[OFF_B2 + m];
+      for (int k = 0; k < NH; ++k) a += sP[OFF_W2 + m * NH + k] * sH1[s * NH + k];
+      sH2[e] = fmaxf(a, 0.0f);
+    }
+    __syncthreads();
+    for (int e = tid; e < TCH * NOUT; e += 256) {
+      const int s = e / NOUT, m = e % NOUT;
+      const int64_t j = c * TCH + s;
+      float d = 0.0f;
+      if (j < nbatch) {
+        float o = sP[OFF_B3 + m];
+        for (int k = 0; k < NH; ++k) o += sP[OFF_W3 + m * NH + k] * sH2[s * NH + k];
+        const float err = o - Y[sample_index(seed, step, j, n, sampled) * NOUT + m] * inv_sy;
+        lacc += (double)err * err;
+        d = scale * err;
+      }
+      sD[e] = d;
+    }
+    __syncthreads();
+    for (int e = tid; e < TCH * NH; e += 256) {  // dZ2 = (dO W3) . [H2 > 0]
+      const int s = e / NH, k = e % NH;
+      float a = 0.0f;
+      for (int m = 0; m < NOUT; ++m) a += sD[s * NOUT + m] * sP[OFF_W3 + m * NH + k];
+      sZ2[e] = sH2[e] > 0.0f ? a : 0.0f;
+    }
+    __syncthreads();
+    for (int e = tid; e < TCH * NH; e += 256) {  // dZ1 = (dZ2 W2) . [H1 > 0]
+      const int s = e / NH, k = e % NH;
+      float a = 0.0f;
+      for (int m = 0; m < NH; ++m) a += sZ2[s * NH + m] * sP[OFF_W2 + m * NH + k];
+      sZ1[e] = sH1[e] > 0.0f ? a : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int q = 0; q < GPT; ++q) {
+      const int p = tid + 256 * q;
+      if (p >= NPARAM) break;
+      float a = 0.0f;
+      if (p < OFF_B1) {
+        const int m = p / NIN, k = p % NIN;
+        for (int s = 0; s < TCH; ++s) a += sZ1[s * NH + m] * sX[s * NIN + k];
+      } else if (p < OFF_W2) {
+        const int m = p - OFF_B1;
+        for (int s = 0; s < TCH; ++s) a += sZ1[s * NH + m];
+      } else if (p < OFF_B2) {
+        const int m = (p - OFF_W2) / NH, k = (p - OFF_W2) % NH;
+        for (int s = 0; s < TCH; ++s) a += sZ2[s * NH + m] * sH1[s * NH + k];
+      } else if (p < OFF_W3) {
+        const int m = p - OFF_B2;
+        for (int s = 0; s < TCH; ++s) a += sZ2[s * NH + m];
+      } else if (p < OFF_B3) {
+        const int m = (p - OFF_W3) / NH, k = (p - OFF_W3) % NH;
+        for (int s = 0; s < TCH; ++s) a += sD[s * NOUT + m] * sH2[s * NH + k];
+      } else {
+        const int m = p - OFF_B3;
+        for (int s = 0; s < TCH; ++s) a += sD[s * NOUT + m];
+      }
+      gp[p] += a;
+    }
+    __syncthreads();
+  }
+  const double t = block_sum(lacc);
+  if (tid == 0) lpart[blockIdx.x] = t;
+}
+
+// sum the per-block partials in block order; optionally one Adam step
+// (bias corrections bc1 = 1 - beta1^t, bc2 = 1 - beta2^t from the host)
+__global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ gpart, const double* __restrict__ lpart,
+                                                    int nb, float* __restrict__ grad, double* __restrict__ loss,
+                                                    double loss_div, int adam, float* __restrict__ P,
+                                                    float* __restrict__ M, float* __restrict__ V, float lr, float b1,
+                                                    float b2, float eps, float bc1, float bc2) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p == 0) {
+    double l = 0.0;
+    for (int b = 0; b < nb; ++b) l += lpart[b];
+    *loss = l / loss_div;
+  }
+  if (p >= NPARAM) return;
+  double a = 0.0;
+  for (int b = 0; b < nb; ++b) a += gpart[(int64_t)b * NPARAM + p];
+  const float gp = (float)a;
+  grad[p] = gp;
+  if (adam) {
+    const float m = b1 * M[p] + (1.0f - b1) * gp;
+    const float v = b2 * V[p] + (1.0f - b2) * gp * gp;
+    M[p] = m;
+    V[p] = v;
+    P[p] -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+  }
+}
+
+// column means and squared deviations (two passes) for standardisation
+__global__ __launch_bounds__(256) void k_colstats(const float* __restrict__ X, int64_t n, int ncol,
+                                                  const double* __restrict__ mean, double* __restrict__ part) {
+  for (int k = 0; k < ncol; ++k) {
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)RB * 256) {
+      const double x = X[i * ncol + k];
+      acc += mean ? (x - mean[k]) * (x - mean[k]) : x;
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) part[(int64_t)k * RB + blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ part, int ncol, double div,
+                                                   double* __restrict__ out) {
+  for (int k = 0; k < ncol; ++k) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < RB; b += 256) acc += part[(int64_t)k * RB + b];
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) out[k] = t / div;
+  }
+}
+
+// ===========================================================================
+// host side
+template <int ST, bool WALLS, bool FORCE>
+static void launch_closure_kernel(lbm_ctx* c, int grid, const StepArgs<typename Stor<ST>::R>& A, const ClosureArgs& C) {
+  using S = typename Stor<ST>::S;
+  const S* src = (const S*)c->buf[c->cur];
+  S* dst = (S*)c->buf[c->cur ^ 1];
+  k_stream_collide_closure<ST, WALLS, FORCE><<<grid, 256, 0, c->stream>>>(src, dst, A, C, c->closure);
+}
+
+template <typename T>
+static StepArgs<T> step_args(const lbm_ctx* c) {
+  StepArgs<T> A;
+  A.g = Geom{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->stride};
+  for (int j = 0; j < LBM_Q; ++j) {
+    A.r.w[j] = (T)c->omega[j];
+    A.r.c[j] = (T)(1.0 - c->omega[j]);
+    A.r.h[j] = (T)(1.0 - 0.5 * c->omega[j]);
+  }
+  for (int d = 0; d < 3; ++d) A.F[d] = (T)c->cfg.force[d];
+  return A;
+}
+
+template <int ST>
+static int closure_steps(lbm_ctx* c, int64_t nsteps) {
+  using T = typename Stor<ST>::R;
+  const StepArgs<T> A = step_args<T>(c);
+  ClosureArgs C;
+  for (int k = 0; k < 6; ++k) C.inv_w[k] = c->closure_inv_w[k];
+  C.nxs = c->cfg.nx / 64;
+  C.nseg = (int64_t)C.nxs * c->cfg.ny * c->cfg.nz;
+  const int64_t want = (C.nseg + 3) / 4;
+  const int grid = (int)(want < 2048 ? want : 2048);
+  const bool walls = c->cfg.walls_y != 0;
+  const bool force = c->cfg.force[0] != 0.0 || c->cfg.force[1] != 0.0 || c->cfg.force[2] != 0.0;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    if (walls) {
+      if (force) launch_closure_kernel<ST, true, true>(c, grid, A, C);
+      else launch_closure_kernel<ST, true, false>(c, grid, A, C);
+    } else {
+      if (force) launch_closure_kernel<ST, false, true>(c, grid, A, C);
+      else launch_closure_kernel<ST, false, false>(c, grid, A, C);
+    }
+    LAUNCHCHK(c);
+    c->cur ^= 1;
+    c->steps++;
+  }
+  return LBM_OK;
+}
+
+int launch_closure_steps(lbm_ctx* c, int64_t nsteps) {
+  int rc = LBM_OK;
+  DISPATCH_ST(c->cfg.storage, rc = closure_steps<ST>(c, nsteps));
+  return rc;
+}
+
+extern "C" int lbm_set_closure(lbm_ctx* c, const float* params) {
+  if (!c) return LBM_EINVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  if (!params) {
+    if (c->closure) {
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      HIPCHK(c, hipFree(c->closure));
+    }
+    c->closure = nullptr;
+    return LBM_OK;
+  }
+  if (c->cfg.nx % 64 != 0)
+    return set_err(c, LBM_EINVAL, "lbm_set_closure: nx must be a multiple of 64 (one wavefront per row segment)");
+  for (int p = 0; p < NPARAM; ++p)
+    if (!std::isfinite(params[p])) return set_err(c, LBM_EINVAL, "lbm_set_closure: parameter %d is not finite", p);
+  std::vector<char> packed;
+  pack_params(params, packed);
+  if (!c->closure) HIPCHK(c, hipMalloc((void**)&c->closure, PACKED_BYTES));
+  HIPCHK(c, hipMemcpyAsync(c->closure, packed.data(), PACKED_BYTES, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 6; ++k) c->closure_inv_w[k] = (float)(1.0 / c->omega[4 + k]);
+  return LBM_OK;
+}
+
+extern "C" int lbm_closure_features(lbm_ctx* c, float* x_dev) {
+  if (!c || !x_dev) return LBM_EINVAL;
+  if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_closure_features: state not initialised");
+  HIPCHK(c, hipSetDevice(c->device));
+  const bool walls = c->cfg.walls_y != 0;
+  const bool force = c->cfg.force[0] != 0.0 || c->cfg.force[1] != 0.0 || c->cfg.force[2] != 0.0;
+  const int nx = c->cfg.nx;
+  const int bx = nx >= 256 ? 256 : (nx + 31) / 32 * 32, by = 256 / bx;
+  const dim3 block(bx, by, 1), grid((nx + bx - 1) / bx, (c->cfg.ny + by - 1) / by, c->cfg.nz);
+  DISPATCH_ST(c->cfg.storage, {
+    using T = typename Stor<ST>::R;
+    using S = typename Stor<ST>::S;
+    const StepArgs<T> A = step_args<T>(c);
+    const S* src = (const S*)c->buf[c->cur];
+    if (walls) {
+      if (force) k_closure_features<ST, true, true><<<grid, block, 0, c->stream>>>(src, A, x_dev);
+      else k_closure_features<ST, true, false><<<grid, block, 0, c->stream>>>(src, A, x_dev);
+    } else {
+      if (force) k_closure_features<ST, false, true><<<grid, block, 0, c->stream>>>(src, A, x_dev);
+      else k_closure_features<ST, false, false><<<grid, block, 0, c->stream>>>(src, A, x_dev);
+    }
+  });
+  LAUNCHCHK(c);
+  return LBM_OK;
+}
+
+static char g_closure_err[512] = "";
+
+extern "C" int lbm_closure_eval(const float* params, const float* x_dev, float* nu_dev, int64_t n, void* hip_stream) {
+  if (!params || !x_dev || !nu_dev || n < 0) {
+    snprintf(g_closure_err, sizeof g_closure_err, "lbm_closure_eval: invalid argument");
+    return LBM_EINVAL;
+  }
+  std::vector<char> packed;
+  pack_params(params, packed);
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* d = nullptr;
+  hipError_t e = hipMalloc((void**)&d, PACKED_BYTES);
+  if (e == hipSuccess) e = hipMemcpyAsync(d, packed.data(), PACKED_BYTES, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && n > 0) {
+    k_closure_eval<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(x_dev, nu_dev, n, d);
+    e = hipGetLastError();
+  }
+  hipError_t e2 = hipStreamSynchronize(st);
+  if (d) (void)hipFree(d);
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) {
+    snprintf(g_closure_err, sizeof g_closure_err, "lbm_closure_eval: %s", hipGetErrorString(e));
+    return LBM_EHIP;
+  }
+  return LBM_OK;
+}
+
+extern "C" int lbm_init_device(lbm_ctx* c, const double* rho_dev, const double* u_dev) {
+  if (!c || !rho_dev || !u_dev) return LBM_EINVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  c->cur = 0;
+  DISPATCH_ST(c->cfg.storage,
+              k_init_dev<ST><<<nblocks(c->n, 256), 256, 0, c->stream>>>(rho_dev, u_dev, (typename Stor<ST>::S*)c->buf[0],
+                                                                         c->n, c->stride));
+  LAUNCHCHK(c);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->initialised = true;
+  c->steps = 0;
+  return LBM_OK;
+}
+
+extern "C" int lbm_coarsen(lbm_ctx* c, double* rho_dev, double* u_dev, double* tau_dev) {
+  if (!c || !rho_dev || !u_dev || !tau_dev) return LBM_EINVAL;
+  if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_coarsen: state not initialised");
+  if (c->cfg.nx % 2 || c->cfg.ny % 2 || c->cfg.nz % 2)
+    return set_err(c, LBM_EINVAL, "lbm_coarsen: nx, ny, nz must be even");
+  HIPCHK(c, hipSetDevice(c->device));
+  const Geom g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->stride};
+  const int64_t nc = c->n / 8;
+  const double* F = c->cfg.force;
+  DISPATCH_ST(c->cfg.storage,
+              k_coarsen<ST><<<nblocks(nc, 256), 256, 0, c->stream>>>((const typename Stor<ST>::S*)c->buf[c->cur], g,
+                                                                      F[0], F[1], F[2], rho_dev, u_dev, tau_dev));
+  LAUNCHCHK(c);
+  return LBM_OK;
+}
+
+extern "C" int lbm_closure_targets(lbm_ctx* c, const double* rho_dev, const double* u_dev, const double* tau_dev,
+                                   double eps_rel, float* y_dev) {
+  if (!c || !rho_dev || !u_dev || !tau_dev || !y_dev || !(eps_rel >= 0.0)) return LBM_EINVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  const Geom g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->stride};
+  double* part = nullptr;
+  HIPCHK(c, hipMalloc((void**)&part, sizeof(double) * (RB + 1)));
+  k_strain_sq<<<RB, 256, 0, c->stream>>>(u_dev, g, c->cfg.walls_y, part);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    k_sum_partials<<<1, 256, 0, c->stream>>>(part, RB, part + RB);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    k_targets<<<nblocks(c->n, 256), 256, 0, c->stream>>>(rho_dev, u_dev, tau_dev, g, c->cfg.walls_y, eps_rel, part + RB, y_dev);
+    e = hipGetLastError();
+  }
+  hipError_t e2 = hipStreamSynchronize(c->stream);
+  (void)hipFree(part);
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) return set_err(c, LBM_EHIP, "lbm_closure_targets: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// training object
+struct lbm_mlp {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  float* P = nullptr;       // parameters (standardised space), FP32 master copy
+  float* M = nullptr;       // Adam first moments
+  float* V = nullptr;       // Adam second moments
+  float* G = nullptr;       // last gradient
+  float* gpart = nullptr;   // GB x NPARAM partial gradients
+  double* lpart = nullptr;  // GB partial losses
+  double* loss = nullptr;   // device loss history
+  float* mu = nullptr;      // feature means
+  float* isig = nullptr;    // 1 / feature std (0: dropped feature)
+  float s_y = 1.0f;         // target scale
+  int64_t t = 0;            // Adam step count
+  int64_t loss_cap = 0;
+  char err[512] = {0};
+};
+
+static int mlp_err(lbm_mlp* m, int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(m ? m->err : g_closure_err, 512, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define MLPCHK(m, call)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return mlp_err(m, LBM_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" void lbm_mlp_destroy(lbm_mlp* m) {
+  if (!m) return;
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  for (void* p : {(void*)m->P, (void*)m->M, (void*)m->V, (void*)m->G, (void*)m->gpart, (void*)m->lpart, (void*)m->loss,
+                  (void*)m->mu, (void*)m->isig})
+    if (p) (void)hipFree(p);
+  if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
+  delete m;
+}
+
+extern "C" const char* lbm_mlp_last_error(const lbm_mlp* m) { return m ? m->err : g_closure_err; }
+
+extern "C" int lbm_mlp_create(uint64_t seed, void* hip_stream, lbm_mlp** out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  lbm_mlp* m = new (std::nothrow) lbm_mlp();
+  if (!m) return LBM_ENOMEM;
+  hipError_t e = hipSuccess;
+  if (hip_stream) {
+    m->stream = (hipStream_t)hip_stream;
+  } else {
+    e = hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking);
+    m->own_stream = e == hipSuccess;
+  }
+  for (float** p : {&m->P, &m->M, &m->V, &m->G})
+    if (e == hipSuccess) e = hipMalloc((void**)p, sizeof(float) * NPARAM);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->gpart, sizeof(float) * NPARAM * GB);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->lpart, sizeof(double) * GB);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->mu, sizeof(float) * NIN);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->isig, sizeof(float) * NIN);
+  if (e != hipSuccess) {
+    mlp_err(nullptr, LBM_EHIP, "lbm_mlp_create: %s", hipGetErrorString(e));
+    lbm_mlp_destroy(m);
+    return LBM_EHIP;
+  }
+  // He-uniform initialisation from a counter-based generator (splitmix64)
+  std::vector<float> p(NPARAM, 0.0f);
+  auto uni = [&](uint64_t i) {
+    uint64_t z = seed + 0x9e3779b97f4a7c15ull * (i + 1);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+  };
+  for (int i = 0; i < NH * NIN; ++i) p[OFF_W1 + i] = (float)(uni(OFF_W1 + i) * std::sqrt(6.0 / NIN));
+  for (int i = 0; i < NH * NH; ++i) p[OFF_W2 + i] = (float)(uni(OFF_W2 + i) * std::sqrt(6.0 / NH));
+  for (int i = 0; i < NOUT * NH; ++i) p[OFF_W3 + i] = (float)(uni(OFF_W3 + i) * std::sqrt(6.0 / NH));
+  std::vector<float> zeros(NIN, 0.0f), ones(NIN, 1.0f);
+  e = hipMemcpy(m->P, p.data(), sizeof(float) * NPARAM, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->M, 0, sizeof(float) * NPARAM);
+  if (e == hipSuccess) e = hipMemset(m->V, 0, sizeof(float) * NPARAM);
+  if (e == hipSuccess) e = hipMemcpy(m->mu, zeros.data(), sizeof(float) * NIN, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->isig, ones.data(), sizeof(float) * NIN, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    mlp_err(nullptr, LBM_EHIP, "lbm_mlp_create: %s", hipGetErrorString(e));
+    lbm_mlp_destroy(m);
+    return LBM_EHIP;
+  }
+  *out = m;
+  return LBM_OK;
+}
+
+extern "C" int lbm_mlp_set_params(lbm_mlp* m, const float* p) {
+  if (!m || !p) return LBM_EINVAL;
+  MLPCHK(m, hipMemcpyAsync(m->P, p, sizeof(float) * NPARAM, hipMemcpyHostToDevice, m->stream));
+  MLPCHK(m, hipMemsetAsync(m->M, 0, sizeof(float) * NPARAM, m->stream));
+  MLPCHK(m, hipMemsetAsync(m->V, 0, sizeof(float) * NPARAM, m->stream));
+  MLPCHK(m, hipStreamSynchronize(m->stream));
+  m->t = 0;
+  return LBM_OK;
+}
+
+extern "C" int lbm_mlp_get_params(lbm_mlp* m, float* p) {
+  if (!m || !p) return LBM_EINVAL;
+  MLPCHK(m, hipMemcpyAsync(p, m->P, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, m->stream));
+  MLPCHK(m, hipStreamSynchronize(m->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_mlp_set_normalisation(lbm_mlp* m, const float* mu, const float* sigma, float s_y) {
+  if (!m || !mu || !sigma || !(s_y > 0.0f)) return LBM_EINVAL;
+  float is[NIN];
+  for (int k = 0; k < NIN; ++k) is[k] = sigma[k] > 0.0f ? 1.0f / sigma[k] : 0.0f;
+  MLPCHK(m, hipMemcpyAsync(m->mu, mu, sizeof(float) * NIN, hipMemcpyHostToDevice, m->stream));
+  MLPCHK(m, hipMemcpyAsync(m->isig, is, sizeof(float) * NIN, hipMemcpyHostToDevice, m->stream));
+  MLPCHK(m, hipStreamSynchronize(m->stream));
+  m->s_y = s_y;
+  return LBM_OK;
+}
+
+extern "C" int lbm_mlp_get_normalisation(lbm_mlp* m, float* mu, float* sigma, float* s_y) {
+  if (!m || !mu || !sigma || !s_y) return LBM_EINVAL;
+  float is[NIN];
+  MLPCHK(m, hipMemcpyAsync(mu, m->mu, sizeof(float) * NIN, hipMemcpyDeviceToHost, m->stream));
+  MLPCHK(m, hipMemcpyAsync(is, m->isig, sizeof(float) * NIN, hipMemcpyDeviceToHost, m->stream));
+  MLPCHK(m, hipStreamSynchronize(m->stream));
+  for (int k = 0; k < NIN; ++k) sigma[k] = is[k] > 0.0f ? 1.0f / is[k] : 0.0f;
+  *s_y = m->s_y;
+  return LBM_OK;
+}
+
+// mean and population std of each feature; features whose std is below
+// 1e-7 of the largest are dropped (sigma = 0); s_y = rms of all targets.
+extern "C" int lbm_mlp_fit_normalisation(lbm_mlp* m, const float* x_dev, const float* y_dev, int64_t n) {
+  if (!m || !x_dev || !y_dev || n < 1) return LBM_EINVAL;
+  double *part = nullptr, *res = nullptr;
+  MLPCHK(m, hipMalloc((void**)&part, sizeof(double) * RB * NIN));
+  hipError_t e = hipMalloc((void**)&res, sizeof(double) * (2 * NIN + 1));
+  double h[2 * NIN + 1];
+  if (e == hipSuccess) {
+    k_colstats<<<RB, 256, 0, m->stream>>>(x_dev, n, NIN, nullptr, part);
+    k_colreduce<<<1, 256, 0, m->stream>>>(part, NIN, (double)n, res);
+    k_colstats<<<RB, 256, 0, m->stream>>>(x_dev, n, NIN, res, part);
+    k_colreduce<<<1, 256, 0, m->stream>>>(part, NIN, (double)n, res + NIN);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h, res, sizeof(double) * 2 * NIN, hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  // sum of squares of the targets: mean about zero of one 6n-long column
+  double zero = 0.0;
+  if (e == hipSuccess) e = hipMemcpy(res + 2 * NIN, &zero, sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    k_colstats<<<RB, 256, 0, m->stream>>>(y_dev, 6 * n, 1, res + 2 * NIN, part);
+    k_colreduce<<<1, 256, 0, m->stream>>>(part, 1, (double)(6 * n), res);
+    e = hipGetLastError();
+  }
+  double ms = 0.0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&ms, res, sizeof(double), hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  (void)hipFree(part);
+  (void)hipFree(res);
+  if (e != hipSuccess) return mlp_err(m, LBM_EHIP, "lbm_mlp_fit_normalisation: %s", hipGetErrorString(e));
+  float mu[NIN], sig[NIN];
+  double smax = 0.0;
+  for (int k = 0; k < NIN; ++k) smax = std::fmax(smax, std::sqrt(h[NIN + k]));
+  for (int k = 0; k < NIN; ++k) {
+    mu[k] = (float)h[k];
+    const double s = std::sqrt(h[NIN + k]);
+    sig[k] = (s > 1e-7 * smax && s > 0.0) ? (float)s : 0.0f;
+  }
+  const float sy = ms > 0.0 ? (float)std::sqrt(ms) : 1.0f;
+  return lbm_mlp_set_normalisation(m, mu, sig, sy);
+}
+
+static int mlp_pass(lbm_mlp* m, const float* x, const float* y, int64_t n, int64_t nbatch, int sampled, uint64_t seed,
+                    int adam, float lr, double* loss_dev) {
+  const int64_t nch = (nbatch + TCH - 1) / TCH;
+  const int nb = (int)(nch < GB ? nch : GB);
+  k_mlp_grad<<<nb, 256, 0, m->stream>>>(x, y, n, nbatch, m->P, m->mu, m->isig, 1.0f / m->s_y, seed, m->t, sampled,
+                                         m->gpart, m->lpart);
+  MLPCHK(m, hipGetLastError());
+  float bc1 = 1.0f, bc2 = 1.0f;
+  const float b1 = 0.9f, b2 = 0.999f;
+  if (adam) {
+    m->t++;
+    bc1 = (float)(1.0 - std::pow((double)b1, (double)m->t));
+    bc2 = (float)(1.0 - std::pow((double)b2, (double)m->t));
+  }
+  k_mlp_reduce<<<(NPARAM + 255) / 256, 256, 0, m->stream>>>(m->gpart, m->lpart, nb, m->G, loss_dev,
+                                                            (double)nbatch * NOUT, adam, m->P, m->M, m->V, lr, b1, b2,
+                                                            1e-8f, bc1, bc2);
+  MLPCHK(m, hipGetLastError());
+  return LBM_OK;
+}
+
+extern "C" int lbm_mlp_loss_grad(lbm_mlp* m, const float* x_dev, const float* y_dev, int64_t n, double* loss,
+                                 float* grad) {
+  if (!m || !x_dev || !y_dev || n < 1) return LBM_EINVAL;
+  double* dl = nullptr;
+  MLPCHK(m, hipMalloc((void**)&dl, sizeof(double)));
+  int rc = mlp_pass(m, x_dev, y_dev, n, n, 0, 0, 0, 0.0f, dl);
+  double hl = 0.0;
+  if (rc == LBM_OK) {
+    hipError_t e = hipMemcpyAsync(&hl, dl, sizeof(double), hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess && grad) e = hipMemcpyAsync(grad, m->G, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) rc = mlp_err(m, LBM_EHIP, "lbm_mlp_loss_grad: %s", hipGetErrorString(e));
+  }
+  (void)hipFree(dl);
+  if (loss) *loss = hl;
+  return rc;
+}
+
+extern "C" int lbm_mlp_train(lbm_mlp* m, const float* x_dev, const float* y_dev, int64_t n, int32_t batch,
+                             int32_t steps, float lr, uint64_t seed, double* loss_out) {
+  if (!m || !x_dev || !y_dev || n < 1 || batch < 1 || steps < 0 || !(lr > 0.0f)) return LBM_EINVAL;
+  if (m->loss_cap < steps) {
+    if (m->loss) (void)hipFree(m->loss);
+    m->loss = nullptr;
+    MLPCHK(m, hipMalloc((void**)&m->loss, sizeof(double) * (steps > 0 ? steps : 1)));
+    m->loss_cap = steps;
+  }
+  for (int s = 0; s < steps; ++s) {
+    const int rc = mlp_pass(m, x_dev, y_dev, n, batch, 1, seed, 1, lr, m->loss + s);
+    if (rc) return rc;
+  }
+  if (loss_out && steps > 0)
+    MLPCHK(m, hipMemcpyAsync(loss_out, m->loss, sizeof(double) * steps, hipMemcpyDeviceToHost, m->stream));
+  MLPCHK(m, hipStreamSynchronize(m->stream));
+  return LBM_OK;
+}
+
+// parameters acting on raw features and returning raw nu_t:
+// W1' = W1 diag(1/sigma), b1' = b1 - W1' mu, W3' = s_y W3, b3' = s_y b3
+extern "C" int lbm_mlp_export(lbm_mlp* m, float* out) {
+  if (!m || !out) return LBM_EINVAL;
+  float mu[NIN], sig[NIN], sy;
+  int rc = lbm_mlp_get_normalisation(m, mu, sig, &sy);
+  if (!rc) rc = lbm_mlp_get_params(m, out);
+  if (rc) return rc;
+  for (int j = 0; j < NH; ++j) {
+    double b = out[OFF_B1 + j];
+    for (int k = 0; k < NIN; ++k) {
+      const float w = sig[k] > 0.0f ? out[OFF_W1 + j * NIN + k] / sig[k] : 0.0f;
+      out[OFF_W1 + j * NIN + k] = w;
+      b -= (double)w * mu[k];
+    }
+    out[OFF_B1 + j] = (float)b;
+  }
+  for (int i = OFF_W3; i < NPARAM; ++i) out[i] *= sy;
+  return LBM_OK;
+}

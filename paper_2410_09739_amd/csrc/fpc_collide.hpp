@@ -160,18 +160,14 @@ __host__ __device__ __forceinline__ void density_momentum(const T (&v)[3][3][3],
 }
 
 // ---------------------------------------------------------------------------
-// Collision of one node.  v: deviation cube in, post-collision deviations out.
-// F: body force.  ws[6], cs[6]: the second-order rates omega_4..omega_9 to use
-// at this node (the rates table, or a per-node closure) and 1 - ws.  Returns
-// rho and u (Step 7).
+// Pre-collision part of one node: Step 7 fields (rho = 1 + rho', rho u =
+// sum f e + F/2) and the forward sweeps; on return v holds kappa'.
 template <typename T, bool FORCE>
-__host__ __device__ __forceinline__ void collide(T (&v)[3][3][3], const Rates<T>& R, const T (&ws)[6],
-                                                 const T (&cs)[6], T Fx, T Fy, T Fz, T& rho_out, T& ux,
-                                                 T& uy, T& uz) {
-  const T third = T(1.0 / 3.0), ninth = T(1.0 / 9.0);
-  T rhop, jx, jy, jz;
+__host__ __device__ __forceinline__ void pre_collision(T (&v)[3][3][3], T Fx, T Fy, T Fz, T& rhop, T& rho,
+                                                       T& ux, T& uy, T& uz) {
+  T jx, jy, jz;
   density_momentum(v, rhop, jx, jy, jz);
-  const T rho = T(1) + rhop;
+  rho = T(1) + rhop;
   const T ir = T(1) / rho;
   if (FORCE) {
     jx += T(0.5) * Fx;
@@ -181,10 +177,19 @@ __host__ __device__ __forceinline__ void collide(T (&v)[3][3][3], const Rates<T>
   ux = jx * ir;
   uy = jy * ir;
   uz = jz * ir;
-  rho_out = rho;
-
   forward_x(v, ux);
   forward_yz(v, uy, uz);
+}
+
+// Step 3 on the primed moments in v (as left by pre_collision), then the
+// inverse sweeps.  ws[6], cs[6]: the second-order rates omega_4..omega_9 to use
+// at this node (the rates table, or a per-node closure) and 1 - ws.
+template <typename T, bool FORCE>
+__host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& R, const T (&ws)[6],
+                                               const T (&cs)[6], T Fx, T Fy, T Fz, T rhop, T rho, T ux,
+                                               T uy, T uz) {
+  const T third = T(1.0 / 3.0), ninth = T(1.0 / 9.0);
+  const T ir = T(1) / rho;
 
   // pre-collision primed central moments (v[c][b][a] = kappa'_abc)
   const T k100 = v[0][0][1], k010 = v[0][1][0], k001 = v[1][0][0];
@@ -307,6 +312,17 @@ __host__ __device__ __forceinline__ void collide(T (&v)[3][3][3], const Rates<T>
   v[2][2][2] = t222;
 
   inverse_all(v, ux, uy, uz);
+}
+
+// Whole collision of one node (Appendix D Steps 7, 1-5): deviation cube in,
+// post-collision deviations (times 2^inv_shift) out.
+template <typename T, bool FORCE>
+__host__ __device__ __forceinline__ void collide(T (&v)[3][3][3], const Rates<T>& R, const T (&ws)[6],
+                                                 const T (&cs)[6], T Fx, T Fy, T Fz, T& rho, T& ux, T& uy,
+                                                 T& uz) {
+  T rhop;
+  pre_collision<T, FORCE>(v, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
+  relax<T, FORCE>(v, R, ws, cs, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
 }
 
 }  // namespace fpc

@@ -17,136 +17,26 @@
 #include <cstring>
 #include <new>
 
-#include "../../include/lbm.h"
-#include "d3q27.hpp"
-#include "fpc_collide.hpp"
-
-using namespace fpc;
+#include "lbm_internal.hpp"
 
 // ===========================================================================
-// storage forms
-template <int ST>
-struct Stor;
-
-template <>
-struct Stor<LBM_F64> {
-  using S = double;
-  using R = double;
-  static __device__ __forceinline__ R dec(S s, int) { return s; }
-  // f: exact power of two still carried by r (see inverse_all)
-  static __device__ __forceinline__ S enc(R r, int, double f = 1.0) { return r * f; }
-};
-
-template <>
-struct Stor<LBM_F32> {
-  using S = float;
-  using R = float;
-  static __device__ __forceinline__ R dec(S s, int) { return s; }
-  static __device__ __forceinline__ S enc(R r, int, double f = 1.0) { return r * (float)f; }
-};
-
-template <>
-struct Stor<LBM_F16DEV> {
-  using S = _Float16;
-  using R = float;
-  static __device__ __forceinline__ R dec(S s, int a) { return (float)s * (1.0f / dev_scale(a)); }
-  // float -> half conversion rounds to nearest even (default rounding mode)
-  static __device__ __forceinline__ S enc(R r, int a, double f = 1.0) { return (_Float16)(r * (float)(dev_scale(a) * f)); }
-};
-
-template <>
-struct Stor<LBM_BF16DEV> {
-  using S = uint16_t;
-  using R = float;
-  static __device__ __forceinline__ R dec(S s, int a) {
-    return __uint_as_float((uint32_t)s << 16) * (1.0f / dev_scale(a));
-  }
-  // hardware conversion (v_cvt_pk_bf16_f32): round to nearest even, NaN stays NaN
-  static __device__ __forceinline__ S enc(R r, int a, double f = 1.0) {
-    const __bf16 h = (__bf16)(r * (float)(dev_scale(a) * f));
-    return __builtin_bit_cast(uint16_t, h);
-  }
-};
-
-struct Geom {
-  int nx, ny, nz;
-  int64_t stride;  // values between direction arrays
-};
-
-template <typename T>
-struct StepArgs {
-  Geom g;
-  Rates<T> r;
-  T F[3];
-};
-
-// ===========================================================================
-// fused stream + collide
-//
-// One thread per node.  ROW = true: a block is one segment of an x row, so y
-// and z are uniform across the wavefront and every row/plane offset lives in
-// scalar registers; the only per-lane address terms are the three x offsets.
-// ROW = false: 2D blocks (small nx), y per lane.  All addresses are a uniform
-// 64-bit base per direction plus a 32-bit per-lane byte offset (the state of
-// one direction is < 4 GiB, checked at creation).
+// fused stream + collide (plain method)
 template <int ST, bool WALLS, bool FORCE, bool ROW>
 __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>::S* __restrict__ src,
                                                         typename Stor<ST>::S* __restrict__ dst,
                                                         StepArgs<typename Stor<ST>::R> A) {
   using T = typename Stor<ST>::R;
-  using S = typename Stor<ST>::S;
-  using SS = Stor<ST>;
-  constexpr uint32_t SZ = sizeof(S);
-  const int nx = A.g.nx, ny = A.g.ny, nz = A.g.nz;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = ROW ? (int)blockIdx.y : (int)(blockIdx.y * blockDim.y + threadIdx.y);
   const int z = blockIdx.z;
-  if (x >= nx || (!ROW && y >= ny)) return;
-  const uint32_t rowb = (uint32_t)nx * SZ;
-  const uint32_t planeb = rowb * (uint32_t)ny;
-  // byte offsets of the source x, y, z for e = -1, 0, +1 (periodic wrap)
-  const uint32_t x0 = (uint32_t)x * SZ;
-  const uint32_t xb[3] = {x == nx - 1 ? 0u : x0 + SZ, x0, x == 0 ? rowb - SZ : x0 - SZ};
-  const uint32_t y0 = (uint32_t)y * rowb;
-  const uint32_t yb[3] = {y == ny - 1 ? 0u : y0 + rowb, y0, y == 0 ? planeb - rowb : y0 - rowb};
-  const uint32_t z0 = (uint32_t)z * planeb;
-  const uint32_t zb[3] = {z == nz - 1 ? 0u : z0 + planeb, z0, z == 0 ? (uint32_t)(nz - 1) * planeb : z0 - planeb};
-  const uint64_t stb = (uint64_t)A.g.stride * SZ;
-  const char* __restrict__ sb = (const char*)src;
-  char* __restrict__ db = (char*)dst;
-
+  if (x >= A.g.nx || (!ROW && y >= A.g.ny)) return;
   T v[3][3][3];
-#pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const int ex = EX[a], ey = EY[a], ez = EZ[a];
-    // halfway bounce-back: if x - e_alpha is a wall node, take the node's own
-    // opposite population (same weight, so the deviation carries over)
-    const bool bb = WALLS && ((ey == 1 && y == 0) || (ey == -1 && y == ny - 1));
-    const int o = opposite(a);
-    T val;
-    if (ROW) {
-      // bb is uniform here: the base is chosen in scalar registers
-      const char* base = bb ? sb + o * stb + (uint64_t)(z0 + y0) : sb + a * stb + (uint64_t)(zb[ez + 1] + yb[ey + 1]);
-      const uint32_t off = bb ? x0 : xb[ex + 1];
-      val = SS::dec(*(const S*)(base + off), a);  // w_opp = w_alpha, scales equal
-    } else if (bb) {
-      val = SS::dec(*(const S*)(sb + o * stb + (uint32_t)(z0 + y0 + x0)), o);
-    } else {
-      val = SS::dec(*(const S*)(sb + a * stb + (uint32_t)(zb[ez + 1] + yb[ey + 1] + xb[ex + 1])), a);
-    }
-    v[ez + 1][ey + 1][ex + 1] = val;
-  }
-
+  const uint32_t ib = pull<ST, WALLS, ROW>(src, A.g, x, y, z, v);
   const T ws[6] = {A.r.w[4], A.r.w[5], A.r.w[6], A.r.w[7], A.r.w[8], A.r.w[9]};
   const T cs[6] = {A.r.c[4], A.r.c[5], A.r.c[6], A.r.c[7], A.r.c[8], A.r.c[9]};
   T rho, ux, uy, uz;
   collide<T, FORCE>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rho, ux, uy, uz);
-
-#pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    S* p = ROW ? (S*)(db + a * stb + (uint64_t)(z0 + y0) + x0) : (S*)(db + a * stb + (uint32_t)(z0 + y0 + x0));
-    *p = SS::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
-  }
+  push<ST, ROW>(dst, A.g, y, z, ib, v);
 }
 
 // ===========================================================================
@@ -373,23 +263,6 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_final(const double* __res
 
 // ===========================================================================
 // host side
-struct lbm_ctx {
-  lbm_config cfg;
-  int device = 0;
-  int64_t n = 0, stride = 0;
-  size_t elem = 0;
-  void* buf[2] = {nullptr, nullptr};
-  int cur = 0;  // buffer holding the current post-collision state
-  bool initialised = false;
-  int64_t steps = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  double omega[LBM_Q];
-  double* scratch = nullptr;  // 4 N doubles for moments / diagnostics
-  double* part = nullptr;     // DIAG_BLOCKS * (NP + 1) + NP doubles
-  double* host_out = nullptr; // pinned NP doubles
-  char err[512] = {0};
-};
 
 static char g_create_err[512] = "";
 
@@ -403,7 +276,7 @@ constexpr int64_t kStridePad = 4352;
 // 256, 192 or 128 nodes, whichever divides nx; 256 with a ragged tail for other
 // nx >= 256) when nx >= 128, otherwise 2D blocks of 256 threads covering
 // several rows.  Returns true for row blocks.
-static bool step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid) {
+bool step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid) {
   if (nx >= 128) {
     int bx = 256;
     if (nx % 256 != 0) {
@@ -421,7 +294,7 @@ static bool step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid) {
   return false;
 }
 
-static int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
+int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
   char* dst = c ? c->err : g_create_err;
   va_list ap;
   va_start(ap, fmt);
@@ -430,17 +303,7 @@ static int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIPCHK(ctx, call)                                                                  \
-  do {                                                                                     \
-    hipError_t e_ = (call);                                                                \
-    if (e_ != hipSuccess) return set_err(ctx, LBM_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
 
-#define LAUNCHCHK(ctx)                                                                     \
-  do {                                                                                     \
-    hipError_t e_ = hipGetLastError();                                                     \
-    if (e_ != hipSuccess) return set_err(ctx, LBM_EHIP, "kernel launch: %s", hipGetErrorString(e_)); \
-  } while (0)
 
 extern "C" void lbm_config_default(lbm_config* cfg) {
   if (!cfg) return;
@@ -480,7 +343,7 @@ extern "C" int lbm_omega_table(const lbm_config* cfg, double out[LBM_Q]) {
   return LBM_OK;
 }
 
-static size_t elem_size(int st) {
+size_t elem_size(int st) {
   switch (st) {
     case LBM_F64: return 8;
     case LBM_F32: return 4;
@@ -555,6 +418,7 @@ extern "C" void lbm_destroy(lbm_ctx* c) {
   if (c->scratch) (void)hipFree(c->scratch);
   if (c->part) (void)hipFree(c->part);
   if (c->host_out) (void)hipHostFree(c->host_out);
+  if (c->closure) (void)hipFree(c->closure);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -564,18 +428,9 @@ extern "C" void* lbm_stream(const lbm_ctx* c) { return c ? (void*)c->stream : nu
 extern "C" int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->steps : -1; }
 extern "C" int64_t lbm_state_bytes(const lbm_ctx* c) { return c ? (int64_t)(LBM_Q * c->n * c->elem) : -1; }
 
-static unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// dispatch a functor over the four storage forms
-#define DISPATCH_ST(st, ...)                                   \
-  switch (st) {                                                \
-    case LBM_F64: { constexpr int ST = LBM_F64; __VA_ARGS__; } break;         \
-    case LBM_F32: { constexpr int ST = LBM_F32; __VA_ARGS__; } break;         \
-    case LBM_F16DEV: { constexpr int ST = LBM_F16DEV; __VA_ARGS__; } break;   \
-    case LBM_BF16DEV: { constexpr int ST = LBM_BF16DEV; __VA_ARGS__; } break; \
-  }
 
-static int alloc_scratch(lbm_ctx* c) {
+int alloc_scratch(lbm_ctx* c) {
   if (!c->scratch) HIPCHK(c, hipMalloc((void**)&c->scratch, sizeof(double) * 4 * c->n));
   return LBM_OK;
 }
@@ -644,6 +499,7 @@ extern "C" int lbm_step(lbm_ctx* c, int64_t n) {
   if (!c || n < 0) return LBM_EINVAL;
   if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_step: state not initialised (call lbm_init or lbm_set_f)");
   HIPCHK(c, hipSetDevice(c->device));
+  if (c->closure) return launch_closure_steps(c, n);
   int rc = LBM_OK;
   DISPATCH_ST(c->cfg.storage, rc = launch_steps<ST>(c, n));
   return rc;

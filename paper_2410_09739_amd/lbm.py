@@ -55,8 +55,10 @@ class lbm_diag(ctypes.Structure):
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
 _vp = ctypes.c_void_p
 _ctx = ctypes.c_void_p
+_mlp = ctypes.c_void_p
 
 # name -> (restype, argtypes); the exported C ABI
 SIGNATURES = {
@@ -78,6 +80,25 @@ SIGNATURES = {
     "lbm_step_count": (ctypes.c_int64, [_ctx]),
     "lbm_destroy": (None, [_ctx]),
     "lbm_last_error": (ctypes.c_char_p, [_ctx]),
+    # learned closure
+    "lbm_set_closure": (ctypes.c_int, [_ctx, _fp]),
+    "lbm_closure_features": (ctypes.c_int, [_ctx, _vp]),
+    "lbm_closure_eval": (ctypes.c_int, [_fp, _vp, _vp, ctypes.c_int64, _vp]),
+    "lbm_coarsen": (ctypes.c_int, [_ctx, _vp, _vp, _vp]),
+    "lbm_init_device": (ctypes.c_int, [_ctx, _vp, _vp]),
+    "lbm_closure_targets": (ctypes.c_int, [_ctx, _vp, _vp, _vp, ctypes.c_double, _vp]),
+    "lbm_mlp_create": (ctypes.c_int, [ctypes.c_uint64, _vp, ctypes.POINTER(_mlp)]),
+    "lbm_mlp_set_params": (ctypes.c_int, [_mlp, _fp]),
+    "lbm_mlp_get_params": (ctypes.c_int, [_mlp, _fp]),
+    "lbm_mlp_set_normalisation": (ctypes.c_int, [_mlp, _fp, _fp, ctypes.c_float]),
+    "lbm_mlp_get_normalisation": (ctypes.c_int, [_mlp, _fp, _fp, ctypes.POINTER(ctypes.c_float)]),
+    "lbm_mlp_fit_normalisation": (ctypes.c_int, [_mlp, _vp, _vp, ctypes.c_int64]),
+    "lbm_mlp_loss_grad": (ctypes.c_int, [_mlp, _vp, _vp, ctypes.c_int64, _dp, _fp]),
+    "lbm_mlp_train": (ctypes.c_int, [_mlp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_float, ctypes.c_uint64, _dp]),
+    "lbm_mlp_export": (ctypes.c_int, [_mlp, _fp]),
+    "lbm_mlp_destroy": (None, [_mlp]),
+    "lbm_mlp_last_error": (ctypes.c_char_p, [_mlp]),
 }
 
 _lib = None
@@ -312,3 +333,107 @@ class Lattice:
     @property
     def steps(self) -> int:
         return lbm_step_count(self.ctx)
+
+
+# ------------------------------------------------------------------ closure
+def _f32(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_fp)
+
+
+def _check_mlp(rc: int, m=None):
+    if rc != LBM_OK:
+        msg = load().lbm_mlp_last_error(m)
+        raise LBMError(rc, msg.decode() if msg else "")
+
+
+def lbm_set_closure(ctx, params: Optional[np.ndarray]):
+    p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+    if p is not None:
+        assert p.shape == (CLOSURE_NPARAM,)
+    _check(load().lbm_set_closure(ctx, _f32(p)), ctx)
+
+
+def lbm_closure_features(ctx, x_ptr: int):
+    _check(load().lbm_closure_features(ctx, x_ptr), ctx)
+
+
+def lbm_closure_eval(params: np.ndarray, x_ptr: int, nu_ptr: int, n: int, stream: Optional[int] = None):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.shape == (CLOSURE_NPARAM,)
+    _check_mlp(load().lbm_closure_eval(_f32(p), x_ptr, nu_ptr, int(n), stream))
+
+
+def lbm_coarsen(ctx, rho_ptr: int, u_ptr: int, tau_ptr: int):
+    _check(load().lbm_coarsen(ctx, rho_ptr, u_ptr, tau_ptr), ctx)
+
+
+def lbm_init_device(ctx, rho_ptr: int, u_ptr: int):
+    _check(load().lbm_init_device(ctx, rho_ptr, u_ptr), ctx)
+
+
+def lbm_closure_targets(ctx, rho_ptr: int, u_ptr: int, tau_ptr: int, eps_rel: float, y_ptr: int):
+    _check(load().lbm_closure_targets(ctx, rho_ptr, u_ptr, tau_ptr, float(eps_rel), y_ptr), ctx)
+
+
+class MLP:
+    """The closure network's training state on the GPU (lbm_mlp)."""
+
+    def __init__(self, seed: int = 0, stream: Optional[int] = None):
+        h = _mlp()
+        _check_mlp(load().lbm_mlp_create(int(seed), stream, ctypes.byref(h)))
+        self.m = h.value
+
+    def close(self):
+        if self.m:
+            load().lbm_mlp_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check_mlp(load().lbm_mlp_set_params(self.m, _f32(p)), self.m)
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(CLOSURE_NPARAM, dtype=np.float32)
+        _check_mlp(load().lbm_mlp_get_params(self.m, _f32(p)), self.m)
+        return p
+
+    def set_normalisation(self, mu, sigma, s_y: float):
+        mu = np.ascontiguousarray(mu, dtype=np.float32)
+        sg = np.ascontiguousarray(sigma, dtype=np.float32)
+        _check_mlp(load().lbm_mlp_set_normalisation(self.m, _f32(mu), _f32(sg), float(s_y)), self.m)
+
+    def get_normalisation(self):
+        mu = np.zeros(27, dtype=np.float32)
+        sg = np.zeros(27, dtype=np.float32)
+        sy = ctypes.c_float()
+        _check_mlp(load().lbm_mlp_get_normalisation(self.m, _f32(mu), _f32(sg), ctypes.byref(sy)), self.m)
+        return mu, sg, sy.value
+
+    def fit_normalisation(self, x_ptr: int, y_ptr: int, n: int):
+        _check_mlp(load().lbm_mlp_fit_normalisation(self.m, x_ptr, y_ptr, int(n)), self.m)
+
+    def loss_grad(self, x_ptr: int, y_ptr: int, n: int):
+        loss = ctypes.c_double()
+        g = np.zeros(CLOSURE_NPARAM, dtype=np.float32)
+        _check_mlp(load().lbm_mlp_loss_grad(self.m, x_ptr, y_ptr, int(n), ctypes.byref(loss), _f32(g)), self.m)
+        return loss.value, g
+
+    def train(self, x_ptr: int, y_ptr: int, n: int, batch: int, steps: int, lr: float, seed: int = 0) -> np.ndarray:
+        hist = np.zeros(max(int(steps), 1))
+        _check_mlp(load().lbm_mlp_train(self.m, x_ptr, y_ptr, int(n), int(batch), int(steps), float(lr), int(seed),
+                                        _dptr(hist)), self.m)
+        return hist[:steps]
+
+    def export(self) -> np.ndarray:
+        p = np.zeros(CLOSURE_NPARAM, dtype=np.float32)
+        _check_mlp(load().lbm_mlp_export(self.m, _f32(p)), self.m)
+        return p

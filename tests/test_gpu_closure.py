@@ -1,0 +1,303 @@
+"""GPU parity of the learned closure against its FP64 oracle (oracle/closure_oracle.py):
+BF16-MFMA inference, FP32 training gradients and Adam steps, normalisation,
+feature extraction, the Favre box filter, the eddy-viscosity targets, and the
+fused stream-collide step with the closure.
+
+Tolerances: inference is compared with the oracle's bf16-quantised forward
+(same rounding of inputs, weights and hidden activations; the sums differ in
+FP32 accumulation order, which can move a hidden activation by one bf16 ulp):
+|nu_gpu - nu_ref| <= 2e-2 * rms(nu_ref) + 1e-6 per output.  Training runs in
+FP32: gradients within 1e-4 of max |g_ref|, losses within 1e-5 relative.
+FP64 filters and targets: 1e-12 relative (targets are stored as FP32: 1e-6).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import closure_oracle as C
+from paper_2410_09739_amd import lbm as L
+from paper_2410_09739_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+W_ALPHA = O.feq(1.0, [0, 0, 0])
+
+
+def _params(seed, bias=0.1):
+    rng = np.random.default_rng(seed)
+    p = C.init_params(seed)
+    W1, b1, W2, b2, W3, b3 = C.unpack(p)
+    b1 += bias * rng.standard_normal(64)
+    b2 += bias * rng.standard_normal(64)
+    b3 += bias * rng.standard_normal(6)
+    return C.pack(W1, b1, W2, b2, W3, b3).astype(np.float32).astype(np.float64)
+
+
+def _dev(a):
+    """Device copy of a host array; the caller keeps the tensor alive while the
+    library uses its pointer (the library runs on its own stream)."""
+    t = torch.tensor(np.ascontiguousarray(a), device="cuda")
+    torch.cuda.synchronize()
+    return t
+
+
+@pytest.mark.parametrize("n", [64, 1000, 4099])
+def test_mfma_inference_matches_bf16_oracle(n):
+    p = _params(1)
+    X = np.random.default_rng(2).standard_normal((n, 27)).astype(np.float32)
+    xd = _dev(X)
+    nud = torch.zeros((n, 6), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    L.lbm_closure_eval(p.astype(np.float32), xd.data_ptr(), nud.data_ptr(), n)
+    got = nud.cpu().numpy().astype(np.float64)
+    ref = C.forward_bf16(p, X.astype(np.float64))
+    scale = np.sqrt(np.mean(ref ** 2))
+    err = np.abs(got - ref).max()
+    assert err <= 2e-2 * scale + 1e-6, (err, scale)
+    # and close to the exact network as well (BF16 quantisation only)
+    exact, _ = C.forward(p, X)
+    assert np.sqrt(np.mean((got - exact) ** 2)) <= 3e-2 * scale
+
+
+def test_mlp_loss_and_gradient_match_oracle():
+    rng = np.random.default_rng(3)
+    n = 1000  # not a multiple of the 32-sample chunk
+    X = rng.standard_normal((n, 27)).astype(np.float32)
+    Y = rng.standard_normal((n, 6)).astype(np.float32)
+    p = _params(4)
+    m = L.MLP(seed=0)
+    m.set_params(p.astype(np.float32))
+    m.set_normalisation(np.zeros(27), np.ones(27), 1.0)
+    xd, yd = _dev(X), _dev(Y)
+    loss, g = m.loss_grad(xd.data_ptr(), yd.data_ptr(), n)
+    lref, gref = C.loss_and_grad(p, X.astype(np.float64), Y.astype(np.float64))
+    assert loss == pytest.approx(lref, rel=1e-5)
+    assert np.abs(g - gref).max() <= 1e-4 * np.abs(gref).max()
+    m.close()
+
+
+def test_mlp_normalised_gradient_and_adam_steps_match_oracle():
+    rng = np.random.default_rng(5)
+    n = 777
+    X = (3e-4 * rng.standard_normal((n, 27)) + 1e-3).astype(np.float32)
+    Y = (2e-3 * np.abs(rng.standard_normal((n, 6)))).astype(np.float32)
+    xd, yd = _dev(X), _dev(Y)
+    m = L.MLP(seed=0)
+    p0 = _params(6)
+    m.set_params(p0.astype(np.float32))
+    m.fit_normalisation(xd.data_ptr(), yd.data_ptr(), n)
+    mu, sg, sy = m.get_normalisation()
+    np.testing.assert_allclose(mu, X.astype(np.float64).mean(0), rtol=1e-5, atol=1e-10)
+    np.testing.assert_allclose(sg, X.astype(np.float64).std(0), rtol=1e-4)
+    assert sy == pytest.approx(np.sqrt(np.mean(Y.astype(np.float64) ** 2)), rel=1e-5)
+    Xs = (X.astype(np.float64) - mu) / sg
+    Ys = Y.astype(np.float64) / sy
+    # three Adam steps on sampled minibatches, replayed by the oracle
+    batch, lr, seed = 96, 1e-3, 11
+    hist = m.train(xd.data_ptr(), yd.data_ptr(), n, batch, 3, lr, seed)
+    p, mm, vv = p0.copy(), np.zeros(C.NPARAM), np.zeros(C.NPARAM)
+    for t in range(3):
+        idx = C.sample_indices(seed, t, batch, n)
+        lref, g = C.loss_and_grad(p, Xs[idx], Ys[idx])
+        assert hist[t] == pytest.approx(lref, rel=1e-4)
+        p, mm, vv = C.adam_step(p, g, mm, vv, t + 1, lr)
+    got = m.get_params().astype(np.float64)
+    # Adam moves every weight by about lr per step whatever the gradient size, so a
+    # gradient entry near zero whose sign differs between FP32 and FP64 may move
+    # one weight the other way: bound the fraction of such entries, not the max.
+    d = np.abs(got - p)
+    assert np.mean(d > 1e-5) < 2e-3 and d.max() <= 6 * lr
+    # exported parameters act on raw features and return raw targets
+    raw = m.export().astype(np.float64)
+    ref_raw = C.fold_normalisation(got, mu.astype(np.float64), sg.astype(np.float64), sy)
+    np.testing.assert_allclose(raw, ref_raw, rtol=1e-5, atol=1e-6 * np.abs(ref_raw).max())
+    m.close()
+
+
+def test_training_reduces_the_loss():
+    rng = np.random.default_rng(7)
+    n = 4096
+    X = rng.standard_normal((n, 27)).astype(np.float32)
+    Wt = rng.standard_normal((6, 27)) * 0.3
+    Y = np.maximum(X @ Wt.T, 0.0).astype(np.float32)  # a learnable map
+    m = L.MLP(seed=3)
+    xd, yd = _dev(X), _dev(Y)
+    m.fit_normalisation(xd.data_ptr(), yd.data_ptr(), n)
+    l0, _ = m.loss_grad(xd.data_ptr(), yd.data_ptr(), n)
+    hist = m.train(xd.data_ptr(), yd.data_ptr(), n, 256, 300, 3e-3, 1)
+    l1, _ = m.loss_grad(xd.data_ptr(), yd.data_ptr(), n)
+    assert np.all(np.isfinite(hist))
+    assert l1 < 0.1 * l0, (l0, l1)
+    m.close()
+
+
+def _state(shape, seed, amp=0.05):
+    nx, ny, nz = shape
+    rho, u = W.random_fields(nx, ny, nz, seed=seed, u_amp=0.05)
+    return O.init(rho, u) * W.random_factors((27, nz, ny, nx), seed=seed + 1, amplitude=amp)
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_coarsen_and_targets_match_oracle(walls):
+    shape = (16, 12, 8)
+    F = (2e-5, 0.0, 1e-5)
+    g0 = _state(shape, 13)
+    with L.Lattice(L.Config(*shape, storage="f64", walls_y=walls, nu=0.02, force=F)) as fine:
+        fine.set_f(g0)
+        fine.step(2)
+        g = fine.get_f()
+        nc = np.prod(shape) // 8
+        rd = torch.zeros(nc, dtype=torch.float64, device="cuda")
+        ud = torch.zeros(3 * nc, dtype=torch.float64, device="cuda")
+        td = torch.zeros(6 * nc, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        L.lbm_coarsen(fine.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr())
+        fine.synchronize()
+    rho, u = O.macroscopic(g, F)
+    rb, ut, tau = C.box_filter(rho, u)
+    cshape = (shape[0] // 2, shape[1] // 2, shape[2] // 2)
+    np.testing.assert_allclose(rd.cpu().numpy().reshape(rb.shape), rb, rtol=1e-13)
+    np.testing.assert_allclose(ud.cpu().numpy().reshape(ut.shape), ut, rtol=1e-11, atol=1e-15)
+    np.testing.assert_allclose(td.cpu().numpy().reshape(tau.shape), tau, rtol=1e-9, atol=1e-15)
+    with L.Lattice(L.Config(*cshape, storage="f64", walls_y=walls, nu=0.01)) as coarse:
+        yd = torch.zeros((nc, 6), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        L.lbm_closure_targets(coarse.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), 0.1, yd.data_ptr())
+    ref = C.targets(rb, tau, C.strain(ut, walls), eps_rel=0.1)
+    got = np.moveaxis(yd.cpu().numpy().reshape(cshape[::-1] + (6,)), -1, 0)
+    np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max() + 1e-30)
+
+
+def _oracle_pre_collision(g, F, walls):
+    """Streamed populations, Step 7 fields and central moments about u (FP64)."""
+    e, _, _ = O.lattice()
+    f = O.stream(g, walls_y=walls)
+    rho, u = O.macroscopic(f, F, post_collision=False)
+    kap = C.central_moments(f, u, e)
+    return f, rho, u, kap
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_features_match_oracle(walls):
+    shape = (64, 5, 4)
+    F = (1e-5, -2e-5, 0.0)
+    g0 = _state(shape, 17)
+    with L.Lattice(L.Config(*shape, storage="f64", walls_y=walls, nu=0.02, force=F)) as lat:
+        lat.set_f(g0)
+        xd = torch.zeros((np.prod(shape), 27), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        L.lbm_closure_features(lat.ctx, xd.data_ptr())
+        lat.synchronize()
+    _, rho, _, kap = _oracle_pre_collision(g0, F, walls)
+    ref = C.features(kap, rho).reshape(-1, 27)
+    got = xd.cpu().numpy().astype(np.float64)
+    # per feature, relative to its own range (floored: x_001 is ~1e-16 when F_z = 0)
+    scale = np.maximum(np.abs(ref).max(0), 1e-6 * np.abs(ref).max())
+    assert np.max(np.abs(got - ref) / scale) <= 1e-6
+
+
+# The bound is set by the closure's BF16 inference, not by the storage form: a
+# hidden activation one bf16 ulp apart moves nu_t by ~1e-3 of itself, omega_j,eff
+# by ~omega^2 * 3 dnu and the populations by that times the second-order
+# non-equilibrium moments (~1e-3 here): well below 1e-6 w_alpha.
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-6), ("f32", 2e-6)])
+def test_fused_closure_step_matches_oracle(storage, tol):
+    """One fused step with the closure: the oracle streams, computes features,
+    evaluates the bf16-quantised network, sets omega_4..9 per node and collides."""
+    shape = (64, 6, 3)
+    F = (1e-5, 0.0, -1e-5)
+    walls = True
+    nu = 0.005
+    g0 = _state(shape, 23, amp=0.02)
+    p = _params(8, bias=0.0)
+    W1, b1, W2, b2, W3, b3 = C.unpack(p)
+    # make the network's outputs O(1e-2) so that the eddy viscosities matter
+    p = C.pack(W1 * 20.0, b1, W2, b2, W3 * 0.01, b3 + 5e-3).astype(np.float32).astype(np.float64)
+    with L.Lattice(L.Config(*shape, storage=storage, walls_y=walls, nu=nu, force=F)) as lat:
+        lat.set_f(g0)
+        g0q = lat.get_f()  # the state as stored (rounded to the storage form)
+        lat.step(0)
+        L.lbm_set_closure(lat.ctx, p.astype(np.float32))
+        lat.step(1)
+        got = lat.get_f()
+    f, rho, u, kap = _oracle_pre_collision(g0q, F, walls)
+    X = C.features(kap, rho).reshape(-1, 27)
+    nu_t = C.forward_bf16(p, X)
+    om = O.omega_table(nu)
+    wf = C.closure_rates(nu_t, om)
+    ff = f.reshape(27, -1)
+    ref = np.zeros_like(ff)
+    for i in range(ff.shape[1]):
+        w = om.copy()
+        w[4:10] = wf[i]
+        ref[:, i] = O.collide_node(ff[:, i], w, F)
+    err = np.abs(got.reshape(27, -1) - ref) / W_ALPHA[:, None]
+    assert err.max() <= tol, err.max()
+    assert np.any(np.clip(nu_t, 0, None) > 1e-3)  # the closure was active
+
+
+def test_set_closure_validates():
+    with L.Lattice(L.Config(40, 4, 4, nu=0.02)) as lat:
+        with pytest.raises(L.LBMError):
+            L.lbm_set_closure(lat.ctx, np.zeros(C.NPARAM, np.float32))
+    with L.Lattice(L.Config(64, 4, 4, nu=0.02)) as lat:
+        bad = np.zeros(C.NPARAM, np.float32)
+        bad[5] = np.nan
+        with pytest.raises(L.LBMError):
+            L.lbm_set_closure(lat.ctx, bad)
+        L.lbm_set_closure(lat.ctx, np.zeros(C.NPARAM, np.float32))
+        L.lbm_set_closure(lat.ctx, None)
+
+
+def test_closure_pipeline_end_to_end():
+    """Fine forced channel -> 2x2x2 filter -> coarse features and targets ->
+    training on the GPU -> exported parameters drive a coarse run (acoustic
+    scaling: nu_c = nu_f / 2, F_c = 2 F_f).  Checks the plumbing and that the
+    trained closure changes the coarse run without destabilising it."""
+    fine_shape = (128, 32, 32)
+    nu_f, F_f = 0.01, 4e-6
+    rho0, u0 = W.channel_turbulent_start(*fine_shape, u_bulk=0.03, amp=0.2, seed=3, kmax=2)
+    with L.Lattice(L.Config(*fine_shape, storage="f32", walls_y=True, nu=nu_f, force=(F_f, 0, 0))) as fine:
+        fine.init(rho0, u0)
+        fine.step(300)
+        nc = np.prod(fine_shape) // 8
+        rd = torch.zeros(nc, dtype=torch.float64, device="cuda")
+        ud = torch.zeros(3 * nc, dtype=torch.float64, device="cuda")
+        td = torch.zeros(6 * nc, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        L.lbm_coarsen(fine.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr())
+        fine.synchronize()
+    cshape = tuple(s // 2 for s in fine_shape)
+    ccfg = L.Config(*cshape, storage="f32", walls_y=True, nu=nu_f / 2, force=(2 * F_f, 0, 0))
+    xd = torch.zeros((nc, 27), dtype=torch.float32, device="cuda")
+    yd = torch.zeros((nc, 6), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    with L.Lattice(ccfg) as coarse:
+        L.lbm_init_device(coarse.ctx, rd.data_ptr(), ud.data_ptr())
+        L.lbm_closure_features(coarse.ctx, xd.data_ptr())
+        L.lbm_closure_targets(coarse.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), 0.1, yd.data_ptr())
+        coarse.synchronize()
+    y = yd.cpu().numpy()
+    assert np.all(np.isfinite(xd.cpu().numpy())) and np.all(y >= 0) and y.max() > 0
+    m = L.MLP(seed=1)
+    m.fit_normalisation(xd.data_ptr(), yd.data_ptr(), nc)
+    l0, _ = m.loss_grad(xd.data_ptr(), yd.data_ptr(), nc)
+    hist = m.train(xd.data_ptr(), yd.data_ptr(), nc, 512, 400, 2e-3, 7)
+    l1, _ = m.loss_grad(xd.data_ptr(), yd.data_ptr(), nc)
+    assert np.all(np.isfinite(hist)) and l1 < 0.8 * l0, (l0, l1)
+    params = m.export()
+    m.close()
+    results = {}
+    for use in (False, True):
+        with L.Lattice(ccfg) as coarse:
+            L.lbm_init_device(coarse.ctx, rd.data_ptr(), ud.data_ptr())
+            if use:
+                L.lbm_set_closure(coarse.ctx, params)
+            coarse.step(200)
+            d = coarse.diagnostics()
+            results[use] = (d, coarse.moments()[1])
+    assert results[True][0]["n_nonfinite"] == 0
+    assert results[True][0]["mass"] == pytest.approx(results[False][0]["mass"], rel=1e-5)
+    du = np.abs(results[True][1] - results[False][1]).max()
+    assert du > 0.0  # the closure acts
+    assert du < 0.5 * np.abs(results[False][1]).max()
