@@ -31,7 +31,22 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_channel_256x128x128.json")
 KERNEL_SOURCES = ["paper_2410_09739_amd/csrc/lbm.hip", "paper_2410_09739_amd/csrc/fpc_collide.hpp",
-                  "paper_2410_09739_amd/csrc/d3q27.hpp"]
+                  "paper_2410_09739_amd/csrc/d3q27.hpp", "paper_2410_09739_amd/csrc/lbm_internal.hpp"]
+
+
+def closure_params():
+    """Parameters of the trained closure if the repository holds them, else a
+    He-initialised network (throughput does not depend on the weights)."""
+    path = os.path.join(ROOT, "paper_2410_09739_amd", "data", "closure_channel_192x96x96.npy")
+    if os.path.exists(path):
+        return np.load(path).astype(np.float32)
+    rng = np.random.default_rng(0)
+    sizes = [(64, 27), (64,), (64, 64), (64,), (6, 64), (6,)]
+    parts = []
+    for shp in sizes:
+        fan = shp[1] if len(shp) == 2 else 1
+        parts.append((rng.uniform(-1, 1, shp) * np.sqrt(6.0 / fan) * (len(shp) == 2)).ravel())
+    return np.concatenate(parts).astype(np.float32) * 1e-3
 
 
 def kernel_source_hash() -> str:
@@ -76,6 +91,41 @@ def run_form(L, torch, storage, shape, nu, F, steps, warmup):
     return ms, u, diag
 
 
+def run_closure_form(L, torch, storage, shape, nu, F, steps, warmup, params):
+    """MLUPS of the fused closure kernel (params: raw-feature parameters) or of
+    the plain kernel (params None) on the coarse channel."""
+    nx, ny, nz = shape
+    stream = torch.cuda.Stream()
+    cfg = L.Config(nx, ny, nz, storage=storage, walls_y=True, nu=nu, force=(F, 0.0, 0.0),
+                   hip_stream=stream.cuda_stream)
+    with L.Lattice(cfg) as lat:
+        lat.init()
+        if params is not None:
+            L.lbm_set_closure(lat.ctx, params)
+        lat.step(warmup)
+        lat.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        lat.step(steps)
+        end.record(stream)
+        end.synchronize()
+        ms = start.elapsed_time(end) / steps
+        d = lat.diagnostics()
+    n = nx * ny * nz
+    return {"mlups": n / (ms * 1e-3) / 1e6, "ms_per_step": ms, "finite": d["n_nonfinite"] == 0}
+
+
+def copy_calibration(torch, nbytes: int = 1 << 31, reps: int = 5):
+    """A plain device copy of known size, to scale the HBM byte counters."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}), flush=True)
+
+
 def cpu_baseline(shape, nu, F, steps):
     import oracle as O
     nx, ny, nz = shape
@@ -95,6 +145,9 @@ def main():
     ap.add_argument("--forms", default="f32,f64,f16dev,bf16dev")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--closure-steps", type=int, default=500)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain copy of known size (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
@@ -106,6 +159,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     shape = (256, 128, 128)
     nx, ny, nz = shape
     N = nx * ny * nz
@@ -142,6 +198,19 @@ def main():
         for st in results:
             results[st]["max_abs_u_err_vs_f64_over_umax"] = float(np.abs(profiles[st][0] - u64).max() / umax)
 
+    # learned-closure forms on the coarse channel 192 x 96 x 96 (the closure
+    # workload: nu and force of the fine channel under acoustic 2x coarsening)
+    closure = {}
+    if args.closure_steps > 0:
+        cshape = (192, 96, 96)
+        params = closure_params()
+        for st, use in [("f32", False), ("f16dev", False), ("f32", True), ("f16dev", True)]:
+            key = st + ("+closure" if use else "")
+            closure[key] = run_closure_form(L, torch, st, cshape, nu / 2, 2 * F, args.closure_steps, 20,
+                                            params if use else None)
+            closure[key] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in closure[key].items()}
+            print(f"# coarse {key}: {closure[key]['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+
     main_form = results["f32"]
     roof = {"bound": "hbm", "achieved": round(main_form["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(main_form["frac_hbm"], 4), "traffic": None}
@@ -170,6 +239,7 @@ def main():
         "roofline": roof,
         "forms": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in results.items()},
+        "closure_forms_192x96x96": closure,
     }
     if not args.no_cpu_baseline:
         cshape = (256, 128, 16)

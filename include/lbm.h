@@ -31,7 +31,9 @@
  * Storage forms: the distributions are held as deviations f - w_alpha from the
  *   D3Q27 lattice weights (8/27, 2/27, 1/54, 1/216), in FP64, FP32, FP16 or
  *   BF16.  FP16 and BF16 values carry an exact power-of-two scale per weight
- *   class; arithmetic is FP64 for LBM_F64 and FP32 otherwise.
+ *   class and are rounded stochastically by default (see lbm_storage);
+ *   arithmetic is FP64 for LBM_F64 and FP32 otherwise.  lbm_init, lbm_set_f
+ *   round to nearest even.
  * Streams: every device operation is enqueued on the configured HIP stream.
  * Errors: functions return LBM_OK (0) or a negative code; lbm_last_error gives
  *   a text.  No entry point throws, aborts or exits.
@@ -63,7 +65,17 @@ extern "C" {
 /* W1[64][27] b1[64] W2[64][64] b2[64] W3[6][64] b3[6] */
 #define LBM_CLOSURE_NPARAM 6342
 
-typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2, LBM_BF16DEV = 3 } lbm_storage;
+/* Storage forms.  LBM_F16DEV / LBM_BF16DEV round every stored value
+ * stochastically (hardware conversion with a counter-based random word of
+ * node and step: unbiased, reproducible); the _RNE forms round to nearest even. */
+typedef enum {
+  LBM_F64 = 0,
+  LBM_F32 = 1,
+  LBM_F16DEV = 2,
+  LBM_BF16DEV = 3,
+  LBM_F16DEV_RNE = 4,
+  LBM_BF16DEV_RNE = 5
+} lbm_storage;
 
 /* How the 27 relaxation rates omega_0..omega_26 (Appendix D numbering) are set.
  * In all modes omega_4,5,6,8,9 come from the shear viscosity through
@@ -164,6 +176,10 @@ void* lbm_stream(const lbm_ctx* c);
 
 /* Completed time steps since lbm_init / lbm_set_f / lbm_set_raw. */
 int64_t lbm_step_count(const lbm_ctx* c);
+
+/* Sets the step counter (e.g. after lbm_set_raw, so that a resumed run draws
+ * the same stochastic-rounding words as an uninterrupted one). */
+int lbm_set_step_count(lbm_ctx* c, int64_t steps);
 
 /* Releases every resource of c (NULL is ignored).  Synchronizes first. */
 void lbm_destroy(lbm_ctx* c);

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_closure(const typename S
     T ws[6], cs[6];
     closure_rates(nu, C.inv_w, ws, cs);
     relax<T, FORCE>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
-    push<ST, true>(dst, A.g, y, z, ib, v);
+    push<ST, true>(dst, A.g, y, z, ib, v, A.step);
   }
 }
 
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void k_init_dev(const double* __restrict__ rho
       for (int a = 0; a < 3; ++a) v[c][b][a] = rp * T(C1[a] * C1[b] * C1[c]);
   inverse_all(v, ux, uy, uz);
 #pragma unroll
-  for (int a = 0; a < Q; ++a) dst[a * st + i] = Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
+  for (int a = 0; a < Q; ++a) dst[a * st + i] = Stor<ST>::enc_nearest(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
 }
 
 // ---------------------------------------------------------------------------
@@ -528,13 +528,15 @@ static int closure_steps(lbm_ctx* c, int64_t nsteps) {
   const int grid = (int)(want < 2048 ? want : 2048);
   const bool walls = c->cfg.walls_y != 0;
   const bool force = c->cfg.force[0] != 0.0 || c->cfg.force[1] != 0.0 || c->cfg.force[2] != 0.0;
+  StepArgs<T> As = A;
   for (int64_t s = 0; s < nsteps; ++s) {
+    As.step = (uint32_t)c->steps;
     if (walls) {
-      if (force) launch_closure_kernel<ST, true, true>(c, grid, A, C);
-      else launch_closure_kernel<ST, true, false>(c, grid, A, C);
+      if (force) launch_closure_kernel<ST, true, true>(c, grid, As, C);
+      else launch_closure_kernel<ST, true, false>(c, grid, As, C);
     } else {
-      if (force) launch_closure_kernel<ST, false, true>(c, grid, A, C);
-      else launch_closure_kernel<ST, false, false>(c, grid, A, C);
+      if (force) launch_closure_kernel<ST, false, true>(c, grid, As, C);
+      else launch_closure_kernel<ST, false, false>(c, grid, As, C);
     }
     LAUNCHCHK(c);
     c->cur ^= 1;

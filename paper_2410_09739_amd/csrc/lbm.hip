@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>:
   const T cs[6] = {A.r.c[4], A.r.c[5], A.r.c[6], A.r.c[7], A.r.c[8], A.r.c[9]};
   T rho, ux, uy, uz;
   collide<T, FORCE>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rho, ux, uy, uz);
-  push<ST, ROW>(dst, A.g, y, z, ib, v);
+  push<ST, ROW>(dst, A.g, y, z, ib, v, A.step);
 }
 
 // ===========================================================================
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, co
       for (int a = 0; a < 3; ++a) v[c][b][a] = rp * T(C1[a] * C1[b] * C1[c]);
   inverse_all(v, ux, uy, uz);
 #pragma unroll
-  for (int a = 0; a < Q; ++a) dst[a * st + i] = Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
+  for (int a = 0; a < Q; ++a) dst[a * st + i] = Stor<ST>::enc_nearest(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
 }
 
 template <int ST>
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_set_f(const double* __restrict__ f, typ
   if (i >= n) return;
 #pragma unroll
   for (int a = 0; a < Q; ++a)
-    dst[a * st + i] = Stor<ST>::enc((typename Stor<ST>::R)(f[a * n + i] - weight(a)), a);
+    dst[a * st + i] = Stor<ST>::enc_nearest((typename Stor<ST>::R)(f[a * n + i] - weight(a)), a);
 }
 
 template <int ST>
@@ -348,7 +348,9 @@ size_t elem_size(int st) {
     case LBM_F64: return 8;
     case LBM_F32: return 4;
     case LBM_F16DEV:
-    case LBM_BF16DEV: return 2;
+    case LBM_BF16DEV:
+    case LBM_F16DEV_RNE:
+    case LBM_BF16DEV_RNE: return 2;
     default: return 0;
   }
 }
@@ -426,6 +428,11 @@ extern "C" void lbm_destroy(lbm_ctx* c) {
 extern "C" const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err : g_create_err; }
 extern "C" void* lbm_stream(const lbm_ctx* c) { return c ? (void*)c->stream : nullptr; }
 extern "C" int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->steps : -1; }
+extern "C" int lbm_set_step_count(lbm_ctx* c, int64_t steps) {
+  if (!c || steps < 0) return LBM_EINVAL;
+  c->steps = steps;
+  return LBM_OK;
+}
 extern "C" int64_t lbm_state_bytes(const lbm_ctx* c) { return c ? (int64_t)(LBM_Q * c->n * c->elem) : -1; }
 
 
@@ -487,6 +494,7 @@ static int launch_steps(lbm_ctx* c, int64_t nsteps) {
   for (int64_t s = 0; s < nsteps; ++s) {
     const S* src = (const S*)c->buf[c->cur];
     S* dst = (S*)c->buf[c->cur ^ 1];
+    A.step = (uint32_t)c->steps;
     kern<<<grid, block, 0, c->stream>>>(src, dst, A);
     LAUNCHCHK(c);
     c->cur ^= 1;

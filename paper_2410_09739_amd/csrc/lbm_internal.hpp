@@ -24,7 +24,9 @@ struct Stor<LBM_F64> {
   using R = double;
   static __device__ __forceinline__ R dec(S s, int) { return s; }
   // f: exact power of two still carried by r (see inverse_all)
-  static __device__ __forceinline__ S enc(R r, int, double f = 1.0) { return r * f; }
+  static constexpr bool stochastic = false;
+  static __device__ __forceinline__ S enc(R r, int, double f = 1.0, uint32_t = 0) { return r * f; }
+  static __device__ __forceinline__ S enc_nearest(R r, int a, double f = 1.0) { return enc(r, a, f); }
 };
 
 template <>
@@ -32,31 +34,79 @@ struct Stor<LBM_F32> {
   using S = float;
   using R = float;
   static __device__ __forceinline__ R dec(S s, int) { return s; }
-  static __device__ __forceinline__ S enc(R r, int, double f = 1.0) { return r * (float)f; }
+  static constexpr bool stochastic = false;
+  static __device__ __forceinline__ S enc(R r, int, double f = 1.0, uint32_t = 0) { return r * (float)f; }
+  static __device__ __forceinline__ S enc_nearest(R r, int a, double f = 1.0) { return enc(r, a, f); }
 };
 
-template <>
-struct Stor<LBM_F16DEV> {
+// FP16 / BF16 deviation storage.  SR = true: stochastic rounding with the
+// gfx950 conversions v_cvt_sr_{f16,bf16}_f32, which compare the dropped bits
+// with the high bits of a random word (E[round(x)] = x), so that increments
+// smaller than half an ulp (a small body force, slow viscous change) are kept
+// on average instead of being rounded away.  SR = false: round to nearest even.
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+template <bool SR>
+struct StorF16 {
   using S = _Float16;
   using R = float;
+  static constexpr bool stochastic = SR;
   static __device__ __forceinline__ R dec(S s, int a) { return (float)s * (1.0f / dev_scale(a)); }
-  // float -> half conversion rounds to nearest even (default rounding mode)
-  static __device__ __forceinline__ S enc(R r, int a, double f = 1.0) { return (_Float16)(r * (float)(dev_scale(a) * f)); }
+  static __device__ __forceinline__ S enc(R r, int a, double f = 1.0, uint32_t rnd = 0) {
+    const float x = r * (float)(dev_scale(a) * f);
+    if (SR) {
+      f16x2_t h = {};
+      h = __builtin_amdgcn_cvt_sr_f16_f32(h, x, rnd, false);
+      return h[0];
+    }
+    return (_Float16)x;  // round to nearest even (default mode)
+  }
+  static __device__ __forceinline__ S enc_nearest(R r, int a, double f = 1.0) {
+    return (_Float16)(r * (float)(dev_scale(a) * f));
+  }
 };
 
-template <>
-struct Stor<LBM_BF16DEV> {
+template <bool SR>
+struct StorBF16 {
   using S = uint16_t;
   using R = float;
+  static constexpr bool stochastic = SR;
   static __device__ __forceinline__ R dec(S s, int a) {
     return __uint_as_float((uint32_t)s << 16) * (1.0f / dev_scale(a));
   }
-  // hardware conversion (v_cvt_pk_bf16_f32): round to nearest even, NaN stays NaN
-  static __device__ __forceinline__ S enc(R r, int a, double f = 1.0) {
-    const __bf16 h = (__bf16)(r * (float)(dev_scale(a) * f));
-    return __builtin_bit_cast(uint16_t, h);
+  static __device__ __forceinline__ S enc(R r, int a, double f = 1.0, uint32_t rnd = 0) {
+    const float x = r * (float)(dev_scale(a) * f);
+    if (SR) {
+      bf16x2_t h = {};
+      h = __builtin_amdgcn_cvt_sr_bf16_f32(h, x, rnd, false);
+      return __builtin_bit_cast(uint16_t, h[0]);
+    }
+    return __builtin_bit_cast(uint16_t, (__bf16)x);  // v_cvt_pk_bf16_f32: nearest even
+  }
+  static __device__ __forceinline__ S enc_nearest(R r, int a, double f = 1.0) {
+    return __builtin_bit_cast(uint16_t, (__bf16)(r * (float)(dev_scale(a) * f)));
   }
 };
+
+template <> struct Stor<LBM_F16DEV> : StorF16<true> {};
+template <> struct Stor<LBM_BF16DEV> : StorBF16<true> {};
+template <> struct Stor<LBM_F16DEV_RNE> : StorF16<false> {};
+template <> struct Stor<LBM_BF16DEV_RNE> : StorBF16<false> {};
+
+// random word of the stored values of one node in one step: a published
+// 32-bit integer hash (lowbias32) of the node's byte offset and the step,
+// plus a golden-ratio Weyl increment per direction (its high bits, the ones
+// the conversions use, are well spread)
+__device__ __forceinline__ uint32_t node_hash(uint32_t node, uint32_t step) {
+  uint32_t h = node ^ (step * 0x9E3779B1u + 0x7F4A7C15u);
+  h ^= h >> 16;
+  h *= 0x7FEB352Du;
+  h ^= h >> 15;
+  h *= 0x846CA68Bu;
+  h ^= h >> 16;
+  return h;
+}
 
 struct Geom {
   int nx, ny, nz;
@@ -68,6 +118,7 @@ struct StepArgs {
   Geom g;
   Rates<T> r;
   T F[3];
+  uint32_t step;  // completed steps before this one (random words of SR storage)
 };
 
 // ===========================================================================
@@ -126,16 +177,17 @@ __device__ __forceinline__ uint32_t pull(const typename Stor<ST>::S* __restrict_
 // store the post-collision cube (deviations times 2^inv_shift) at byte offset ib
 template <int ST, bool ROW>
 __device__ __forceinline__ void push(typename Stor<ST>::S* __restrict__ dst, const Geom& g, int y, int z, uint32_t ib,
-                                     const typename Stor<ST>::R (&v)[3][3][3]) {
+                                     const typename Stor<ST>::R (&v)[3][3][3], uint32_t step) {
   using S = typename Stor<ST>::S;
   constexpr uint32_t SZ = sizeof(S);
   const uint64_t stb = (uint64_t)g.stride * SZ;
   char* __restrict__ db = (char*)dst;
   const uint32_t rowbase = ROW ? ((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.nx * SZ : 0u;
+  const uint32_t h = Stor<ST>::stochastic ? node_hash(ib, step) : 0u;
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     S* p = ROW ? (S*)(db + a * stb + (uint64_t)rowbase + (ib - rowbase)) : (S*)(db + a * stb + ib);
-    *p = Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
+    *p = Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a), h + (uint32_t)a * 0x9E3779B9u);
   }
 }
 
@@ -181,13 +233,15 @@ int launch_closure_steps(lbm_ctx* c, int64_t nsteps);
     if (e_ != hipSuccess) return set_err(ctx, LBM_EHIP, "kernel launch: %s", hipGetErrorString(e_)); \
   } while (0)
 
-// dispatch over the four storage forms
+// dispatch over the storage forms
 #define DISPATCH_ST(st, ...)                                   \
   switch (st) {                                                \
     case LBM_F64: { constexpr int ST = LBM_F64; __VA_ARGS__; } break;         \
     case LBM_F32: { constexpr int ST = LBM_F32; __VA_ARGS__; } break;         \
     case LBM_F16DEV: { constexpr int ST = LBM_F16DEV; __VA_ARGS__; } break;   \
     case LBM_BF16DEV: { constexpr int ST = LBM_BF16DEV; __VA_ARGS__; } break; \
+    case LBM_F16DEV_RNE: { constexpr int ST = LBM_F16DEV_RNE; __VA_ARGS__; } break; \
+    case LBM_BF16DEV_RNE: { constexpr int ST = LBM_BF16DEV_RNE; __VA_ARGS__; } break; \
   }
 
 static inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }

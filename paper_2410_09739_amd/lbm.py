@@ -19,13 +19,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
-LBM_F64, LBM_F32, LBM_F16DEV, LBM_BF16DEV = 0, 1, 2, 3
+LBM_F64, LBM_F32, LBM_F16DEV, LBM_BF16DEV, LBM_F16DEV_RNE, LBM_BF16DEV_RNE = 0, 1, 2, 3, 4, 5
 LBM_OMEGA_PAPER, LBM_OMEGA_ORDER_SCALED, LBM_OMEGA_EXPLICIT = 0, 1, 2
 Q = 27
 CLOSURE_NPARAM = 6342
 
-STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16dev": LBM_F16DEV, "bf16dev": LBM_BF16DEV}
-STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16DEV: 2, LBM_BF16DEV: 2}
+STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16dev": LBM_F16DEV, "bf16dev": LBM_BF16DEV,
+           "f16dev_rne": LBM_F16DEV_RNE, "bf16dev_rne": LBM_BF16DEV_RNE}
+STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16DEV: 2, LBM_BF16DEV: 2, LBM_F16DEV_RNE: 2, LBM_BF16DEV_RNE: 2}
 OMEGA_MODE = {"paper": LBM_OMEGA_PAPER, "order_scaled": LBM_OMEGA_ORDER_SCALED, "explicit": LBM_OMEGA_EXPLICIT}
 
 
@@ -78,6 +79,7 @@ SIGNATURES = {
     "lbm_set_raw": (ctypes.c_int, [_ctx, _vp, ctypes.c_int64]),
     "lbm_stream": (_vp, [_ctx]),
     "lbm_step_count": (ctypes.c_int64, [_ctx]),
+    "lbm_set_step_count": (ctypes.c_int, [_ctx, ctypes.c_int64]),
     "lbm_destroy": (None, [_ctx]),
     "lbm_last_error": (ctypes.c_char_p, [_ctx]),
     # learned closure
@@ -216,6 +218,10 @@ def lbm_step_count(ctx) -> int:
     return int(load().lbm_step_count(ctx))
 
 
+def lbm_set_step_count(ctx, n: int):
+    _check(load().lbm_set_step_count(ctx, int(n)), ctx)
+
+
 def lbm_destroy(ctx):
     load().lbm_destroy(ctx)
 
@@ -333,6 +339,10 @@ class Lattice:
     @property
     def steps(self) -> int:
         return lbm_step_count(self.ctx)
+
+    @steps.setter
+    def steps(self, n: int):
+        lbm_set_step_count(self.ctx, n)
 
 
 # ------------------------------------------------------------------ closure
