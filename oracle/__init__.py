@@ -52,19 +52,19 @@ def _load():
     if _lib is None:
         build()
         lib = ctypes.CDLL(_LIB_PATH)
-        lib.orc_collide_node.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp]
+        lib.orc_collide_node.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
         lib.orc_feq.argtypes = [ctypes.c_double, _dp, _dp]
         lib.orc_lattice.argtypes = [_ip, _ip, _ip, _ip, _ip]
         lib.orc_matrices.argtypes = [_dp, _dp, _dp, _dp, _dp]
         lib.orc_attractor.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
         lib.orc_attractor.restype = ctypes.c_double
         lib.orc_init.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, _dp]
-        lib.orc_collide.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, _dp, _dp]
+        lib.orc_collide.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, _dp, _dp, ctypes.c_int]
         lib.orc_stream.argtypes = [ctypes.c_int] * 4 + [_dp, _dp]
-        lib.orc_run.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, ctypes.c_int]
+        lib.orc_run.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, ctypes.c_int, ctypes.c_int]
         lib.orc_run.restype = ctypes.c_int
         lib.orc_num_threads.restype = ctypes.c_int
-        lib.orc_step_nodes.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, _i64p, ctypes.c_int64, _dp]
+        lib.orc_step_nodes.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, _i64p, ctypes.c_int64, _dp, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -135,12 +135,17 @@ def attractor(m: int, n: int, p: int, D, pi) -> float:
     return _load().orc_attractor(m, n, p, _d(_f64(D)), _d(_f64(pi)))
 
 
-def collide_node(f, omega, force=(0.0, 0.0, 0.0), return_moments: bool = False):
+def _model(attractor: str) -> int:
+    """0: FPC Markovian attractors; 1: Maxwellian attractors (the MCM comparison model)."""
+    return {"fpc": 0, "maxwell": 1}[attractor]
+
+
+def collide_node(f, omega, force=(0.0, 0.0, 0.0), return_moments: bool = False, attractor: str = "fpc"):
     """Appendix D Steps 1-5 at one node (27 populations in, 27 out)."""
     lib = _load()
     f = _f64(f)
     ft, kpre, kpost = np.zeros(Q), np.zeros(Q), np.zeros(Q)
-    lib.orc_collide_node(_d(f), _d(_f64(omega)), _d(_f64(force)), _d(ft), _d(kpre), _d(kpost))
+    lib.orc_collide_node(_d(f), _d(_f64(omega)), _d(_f64(force)), _d(ft), _d(kpre), _d(kpost), _model(attractor))
     return (ft, kpre, kpost) if return_moments else ft
 
 
@@ -163,12 +168,12 @@ def init(rho: np.ndarray, u: np.ndarray) -> np.ndarray:
     return f
 
 
-def collide(f: np.ndarray, omega, force=(0.0, 0.0, 0.0)) -> np.ndarray:
+def collide(f: np.ndarray, omega, force=(0.0, 0.0, 0.0), attractor: str = "fpc") -> np.ndarray:
     lib = _load()
     f = _f64(f)
     _, nz, ny, nx = f.shape
     g = np.zeros_like(f)
-    lib.orc_collide(nx, ny, nz, _d(f), _d(g), _d(_f64(omega)), _d(_f64(force)))
+    lib.orc_collide(nx, ny, nz, _d(f), _d(g), _d(_f64(omega)), _d(_f64(force)), _model(attractor))
     return g
 
 
@@ -181,18 +186,21 @@ def stream(g: np.ndarray, walls_y: bool = False) -> np.ndarray:
     return f
 
 
-def run(g: np.ndarray, omega, force=(0.0, 0.0, 0.0), walls_y: bool = False, steps: int = 1) -> np.ndarray:
+def run(g: np.ndarray, omega, force=(0.0, 0.0, 0.0), walls_y: bool = False, steps: int = 1,
+        attractor: str = "fpc") -> np.ndarray:
     """``steps`` full time steps (stream, then collide) from a post-collision state."""
     lib = _load()
     g = _f64(g).copy()
     _, nz, ny, nx = g.shape
-    rc = lib.orc_run(nx, ny, nz, int(bool(walls_y)), _d(_f64(omega)), _d(_f64(force)), _d(g), int(steps))
+    rc = lib.orc_run(nx, ny, nz, int(bool(walls_y)), _d(_f64(omega)), _d(_f64(force)), _d(g), int(steps),
+                     _model(attractor))
     if rc != 0:
         raise MemoryError("oracle run failed")
     return g
 
 
-def step_nodes(g: np.ndarray, sel, omega, force=(0.0, 0.0, 0.0), walls_y: bool = False) -> np.ndarray:
+def step_nodes(g: np.ndarray, sel, omega, force=(0.0, 0.0, 0.0), walls_y: bool = False,
+               attractor: str = "fpc") -> np.ndarray:
     """One step evaluated at the flat node indices ``sel`` only; returns [27, len(sel)]."""
     lib = _load()
     g = _f64(g)
@@ -200,7 +208,7 @@ def step_nodes(g: np.ndarray, sel, omega, force=(0.0, 0.0, 0.0), walls_y: bool =
     sel = np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
     out = np.zeros((Q, sel.size))
     lib.orc_step_nodes(nx, ny, nz, int(bool(walls_y)), _d(_f64(omega)), _d(_f64(force)), _d(g),
-                       sel.ctypes.data_as(_i64p), sel.size, _d(out))
+                       sel.ctypes.data_as(_i64p), sel.size, _d(out), _model(attractor))
     return out
 
 

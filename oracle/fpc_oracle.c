@@ -37,6 +37,11 @@
  *   R11 third-order attractors are zero, as printed.
  *   R12 halfway bounce-back (pull form): if the upstream node x - e_alpha is a
  *       wall node, f_alpha(x, t+1) = f~_opp(alpha)(x, t).
+ *   R22 the comparison model with Maxwellian equilibria (MCM-LBM, Sec. 4, the
+ *       doubly periodic shear layer and crossing shear wave studies) relaxes
+ *       every non-conserved central moment to the discrete Maxwellian's,
+ *       rho c_a c_b c_c with c = (1, 0, c_s^2), with the same rates, grouping
+ *       and sources as FPC; only the attractors of order >= 4 differ.
  */
 #include <math.h>
 #include <stdint.h>
@@ -178,6 +183,13 @@ static double mv_attractor(int m, int n, int p, const double D[6], const double*
   return r;
 }
 
+/* central moment (m,n,p) of the discrete Maxwellian (reading R2/R22):
+ * rho c_m c_n c_p with c_0 = 1, c_1 = 0, c_2 = c_s^2 */
+static double maxwell_central(int m, int n, int p, double rho) {
+  const double c[3] = {1.0, 0.0, CS2};
+  return rho * c[m] * c[n] * c[p];
+}
+
 /* relaxation with source, Appendix D Step 3:
  * kappa~ = kappa + omega (kappa^Mv - kappa) + (1 - omega/2) sigma delta_t, delta_t = 1 */
 static double relax(double k, double kmv, double w, double s) {
@@ -186,9 +198,11 @@ static double relax(double k, double kmv, double w, double s) {
 
 /* One collision (Appendix D Steps 7 (for rho,u), 1, 2, 3, 4, 5) at one node.
  * f: 27 pre-collision populations; omega: omega_0..omega_26 (App. D numbering);
- * F: body force.  Writes f~ and optionally the pre/post central moments. */
+ * F: body force; model: 0 = FPC (Markovian attractors), 1 = Maxwellian
+ * attractors (MCM, reading R22).  Writes f~ and optionally the pre/post
+ * central moments. */
 void orc_collide_node(const double* f, const double* omega, const double* F, double* ft,
-                      double* kappa_pre, double* kappa_post) {
+                      double* kappa_pre, double* kappa_post, int model) {
   setup();
   /* Step 7 definitions: rho = sum f, rho u = sum f e + F/2. */
   double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -290,7 +304,9 @@ void orc_collide_node(const double* f, const double* omega, const double* F, dou
                         kt[K110] / rho, kt[K011] / rho, kt[K101] / rho};
 
   /* fourth order: attractors from post-collision second order */
-  for (int q = K220; q <= K112; ++q) mv[q] = mv_attractor(MNP[q][0], MNP[q][1], MNP[q][2], Dh, cur);
+  for (int q = K220; q <= K112; ++q)
+    mv[q] = model == 1 ? maxwell_central(MNP[q][0], MNP[q][1], MNP[q][2], rho)
+                       : mv_attractor(MNP[q][0], MNP[q][1], MNP[q][2], Dh, cur);
   const double mv4s1 = mv[K220] + mv[K202] + mv[K022], mv4d1 = mv[K220] + mv[K202] - mv[K022], mv4d2 = mv[K220] - mv[K202];
   const double kt4s1 = relax(k4s1, mv4s1, omega[17], s4s1);
   const double kt4d1 = relax(k4d1, mv4d1, omega[18], s4d1);
@@ -304,14 +320,16 @@ void orc_collide_node(const double* f, const double* omega, const double* F, dou
   for (int q = K220; q <= K112; ++q) cur[q] = kt[q];
 
   /* fifth order: attractors from post-collision second and third order */
-  for (int q = K122; q <= K221; ++q) mv[q] = mv_attractor(MNP[q][0], MNP[q][1], MNP[q][2], Dh, cur);
+  for (int q = K122; q <= K221; ++q)
+    mv[q] = model == 1 ? maxwell_central(MNP[q][0], MNP[q][1], MNP[q][2], rho)
+                       : mv_attractor(MNP[q][0], MNP[q][1], MNP[q][2], Dh, cur);
   kt[K122] = relax(k[K122], mv[K122], omega[23], sg[K122]);
   kt[K212] = relax(k[K212], mv[K212], omega[24], sg[K212]);
   kt[K221] = relax(k[K221], mv[K221], omega[25], sg[K221]);
   for (int q = K122; q <= K221; ++q) cur[q] = kt[q];
 
   /* sixth order: attractor from post-collision second and fourth order */
-  mv[K222] = mv_attractor(2, 2, 2, Dh, cur);
+  mv[K222] = model == 1 ? maxwell_central(2, 2, 2, rho) : mv_attractor(2, 2, 2, Dh, cur);
   kt[K222] = relax(k[K222], mv[K222], omega[26], sg[K222]);
   if (kappa_post) memcpy(kappa_post, kt, sizeof kt);
 
@@ -384,14 +402,14 @@ void orc_init(int nx, int ny, int nz, const double* rho, const double* u, double
 
 /* Collision at every node (Steps 1-5); g may alias nothing. */
 void orc_collide(int nx, int ny, int nz, const double* f, double* g, const double* omega,
-                 const double* F) {
+                 const double* F, int model) {
   setup();
   const int64_t N = (int64_t)nx * ny * nz;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i) {
     double fi[Q], fo[Q];
     for (int a = 0; a < Q; ++a) fi[a] = f[a * N + i];
-    orc_collide_node(fi, omega, F, fo, NULL, NULL);
+    orc_collide_node(fi, omega, F, fo, NULL, NULL, model);
     for (int a = 0; a < Q; ++a) g[a * N + i] = fo[a];
   }
 }
@@ -424,14 +442,14 @@ void orc_stream(int nx, int ny, int nz, int walls_y, const double* g, double* f)
  * seen from the post-collision state).  g holds the post-collision state on
  * entry and on exit. */
 int orc_run(int nx, int ny, int nz, int walls_y, const double* omega, const double* F, double* g,
-            int nsteps) {
+            int nsteps, int model) {
   setup();
   const int64_t N = (int64_t)nx * ny * nz;
   double* f = (double*)malloc(sizeof(double) * Q * N);
   if (!f) return -1;
   for (int s = 0; s < nsteps; ++s) {
     orc_stream(nx, ny, nz, walls_y, g, f);
-    orc_collide(nx, ny, nz, f, g, omega, F);
+    orc_collide(nx, ny, nz, f, g, omega, F, model);
   }
   free(f);
   return 0;
@@ -440,7 +458,7 @@ int orc_run(int nx, int ny, int nz, int walls_y, const double* omega, const doub
 /* One step (stream then collide) evaluated only at the listed nodes, reading
  * the full post-collision state g; out is [27][nsel]. */
 void orc_step_nodes(int nx, int ny, int nz, int walls_y, const double* omega, const double* F,
-                    const double* g, const int64_t* sel, int64_t nsel, double* out) {
+                    const double* g, const int64_t* sel, int64_t nsel, double* out, int model) {
   setup();
   const int64_t N = (int64_t)nx * ny * nz;
 #pragma omp parallel for schedule(static)
@@ -459,7 +477,7 @@ void orc_step_nodes(int nx, int ny, int nz, int walls_y, const double* omega, co
       ys = (ys % ny + ny) % ny;
       fi[a] = g[a * N + (xs + (int64_t)nx * (ys + (int64_t)ny * zs))];
     }
-    orc_collide_node(fi, omega, F, fo, NULL, NULL);
+    orc_collide_node(fi, omega, F, fo, NULL, NULL, model);
     for (int a = 0; a < Q; ++a) out[a * nsel + s] = fo[a];
   }
 }

@@ -407,3 +407,94 @@ def test_poiseuille_steady_state_with_halfway_bounce_back():
         if e[a, 1] == 1:
             wall += 2 * g[a, 0, ny - 1, 0] * e[a, 0]
     assert wall == pytest.approx(Fx * ny, rel=1e-3)  # force of the fluid on the walls
+
+
+# ------------------------------------------------------------------ Maxwellian comparison model
+def test_markovian_attractors_at_equilibrium_are_the_maxwellian_central_moments():
+    """Sec. 1 and Sec. 3: with the lower moments at their equilibrium values the
+    Markovian attractors coincide with the Maxwellian's central moments.  Built
+    up order by order from the general formula, the attractor of every moment
+    equals the central moment of f^eq (the discrete Maxwellian of reading R2)."""
+    e, _, mnp = O.lattice()
+    rho = 1.17
+    fe = O.feq(rho, (0.0, 0.0, 0.0))
+    maxwell = np.array([fe @ np.prod(e ** m, axis=1) for m in mnp])
+    pi = np.zeros(27)
+    pi[0] = rho
+    D = np.array([1 / 3, 1 / 3, 1 / 3, 0, 0, 0])
+    for order in range(2, 7):
+        for q, m in enumerate(mnp):
+            if sum(m) == order:
+                pi[q] = O.attractor(*m, D, pi)
+    np.testing.assert_allclose(pi, maxwell, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_maxwellian_model_relaxes_higher_orders_to_fixed_values(seed):
+    """MCM comparison model (reading R22): with unit rates for orders >= 4 the
+    post-collision moments of orders >= 4 are rho c_a c_b c_c whatever the
+    second-order state; the FPC model's are not (they follow the post-collision
+    second order)."""
+    rng = np.random.default_rng(40 + seed)
+    f = _state(60 + seed, amp=0.3)
+    om = np.ones(27)
+    om[4:10] = rng.uniform(1.2, 1.9, 6)
+    _, kpre, kpost = O.collide_node(f, om, return_moments=True, attractor="maxwell")
+    rho = kpre[0]
+    c = {0: 1.0, 1: 0.0, 2: 1 / 3}
+    for q, name in enumerate(ORDER):
+        if sum(map(int, name)) >= 4:
+            a, b, d = map(int, name)
+            assert kpost[q] == pytest.approx(rho * c[a] * c[b] * c[d], abs=1e-15), name
+    _, _, kfpc = O.collide_node(f, om, return_moments=True)
+    assert abs(kfpc[IX["220"]] - rho / 9) > 1e-6
+    # orders <= 3 are the same in both models
+    np.testing.assert_allclose(kfpc[:17], kpost[:17], rtol=0, atol=1e-16)
+
+
+def test_maxwellian_model_keeps_the_conservation_laws_and_fixed_point():
+    e, _, _ = O.lattice()
+    f = _state(71, amp=0.2)
+    rng = np.random.default_rng(71)
+    om = rng.uniform(0.3, 1.9, 27)
+    F = (2e-4, -1e-4, 3e-4)
+    ft = O.collide_node(f, om, F, attractor="maxwell")
+    assert ft.sum() == pytest.approx(f.sum(), rel=0, abs=1e-15)
+    np.testing.assert_allclose(ft @ e, f @ e + np.array(F), rtol=0, atol=1e-16)
+    fe = O.feq(1.05, (0.03, -0.02, 0.05))
+    np.testing.assert_allclose(O.collide_node(fe, om, attractor="maxwell"), fe, rtol=0, atol=1e-15)
+
+
+def _crossing_shear_wave_amplitudes(attractor, marks, nx=30, ny=2, nz=30, amp=1e-5, nu=1e-7):
+    x, z = np.arange(nx), np.arange(nz)
+    Z, _, X = np.meshgrid(z, np.arange(ny), x, indexing="ij")
+    k = 2 * np.pi / nx
+    mode = np.cos(k * X) * np.cos(k * Z)
+    u = np.zeros((3, nz, ny, nx))
+    u[1] = amp * mode
+    g = O.init(np.ones((nz, ny, nx)), u)
+    om = O.omega_table(nu)
+    out, done = [], 0
+    for m in marks:
+        g = O.run(g, om, steps=m - done, attractor=attractor)
+        done = m
+        _, uu = O.macroscopic(g)
+        out.append((uu[1] * mode).sum() / (mode * mode).sum() / amp)
+    return np.array(out), 2 * k * k * nu
+
+
+def test_crossing_shear_waves_show_hyperviscosity_only_with_maxwellian_attractors():
+    """Sec. 4 (orthogonal crossing shear waves, nu = 1e-7, L = 30): the wave
+    should hardly decay (the exact rate nu (k_x^2 + k_z^2) is 8.8e-9 per step).
+    With Maxwellian attractors for the higher moments it decays at a rate that
+    is orders of magnitude larger (numerical hyperviscosity); with the
+    Markovian attractors of FPC-LBM it does not.  Rates are measured after the
+    initial odd-even transient of omega ~ 2 has settled."""
+    marks = [300, 2300]
+    a_fpc, exact = _crossing_shear_wave_amplitudes("fpc", marks)
+    a_mcm, _ = _crossing_shear_wave_amplitudes("maxwell", marks)
+    rate_fpc = np.log(a_fpc[0] / a_fpc[1]) / (marks[1] - marks[0])
+    rate_mcm = np.log(a_mcm[0] / a_mcm[1]) / (marks[1] - marks[0])
+    assert rate_mcm > 1000 * exact
+    assert rate_mcm > 50 * rate_fpc
+    assert abs(a_fpc[1] - 1.0) < 0.02 and a_mcm[1] < 0.92
