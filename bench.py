@@ -17,7 +17,6 @@ CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -29,9 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_channel_256x128x128.json")
-KERNEL_SOURCES = ["paper_2410_09739_amd/csrc/lbm.hip", "paper_2410_09739_amd/csrc/fpc_collide.hpp",
-                  "paper_2410_09739_amd/csrc/d3q27.hpp", "paper_2410_09739_amd/csrc/lbm_internal.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_channel_256x128x128.md")
 
 
 def closure_params():
@@ -47,14 +44,6 @@ def closure_params():
         fan = shp[1] if len(shp) == 2 else 1
         parts.append((rng.uniform(-1, 1, shp) * np.sqrt(6.0 / fan) * (len(shp) == 2)).ravel())
     return np.concatenate(parts).astype(np.float32) * 1e-3
-
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def analytic_startup(ny: int, nu: float, F: float, t: float, nterms: int = 400) -> np.ndarray:
@@ -156,6 +145,7 @@ def main():
 
     import torch
     from paper_2410_09739_amd import lbm as L
+    from paper_2410_09739_amd import profiling as P
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -214,11 +204,9 @@ def main():
     main_form = results["f32"]
     roof = {"bound": "hbm", "achieved": round(main_form["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(main_form["frac_hbm"], 4), "traffic": None}
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        if tr.get("kernel_source_sha") == kernel_source_hash() and "f32" in tr.get("forms", {}):
-            roof["traffic"] = tr["forms"]["f32"]["hbm_bytes_per_launch"]
+    tr = P.read_traffic_md(TRAFFIC_FILE)
+    if tr and tr.get("kernel_source_sha") == P.kernel_source_hash() and "f32" in tr.get("forms", {}):
+        roof["traffic"] = tr["forms"]["f32"]["hbm_bytes_per_launch"]
 
     line = {
         "metric": "D3Q27 FPC-LBM MLUPS & % HBM peak, FP32 vs FP16-storage at stated error",

@@ -91,6 +91,17 @@ typedef enum {
  * Every rate must lie in (0, 2). */
 typedef enum { LBM_OMEGA_PAPER = 0, LBM_OMEGA_ORDER_SCALED = 1, LBM_OMEGA_EXPLICIT = 2 } lbm_omega_mode;
 
+/* Attractors of the central moments of order >= 4.
+ *   LBM_ATTRACTOR_FPC      the Markovian attractors of FPC-LBM, Eq. (Mvcmattractor3D)
+ *                          with the diffusion tensor of Eq. (diffusion-tensor-parameter-3D),
+ *                          built from the post-collision lower moments (Appendix D Step 3).
+ *   LBM_ATTRACTOR_MAXWELL  the discrete Maxwellian's central moments rho c_a c_b c_c,
+ *                          c = (1, 0, c_s^2): the central-moment scheme with Maxwellian
+ *                          equilibria (MCM-LBM) that Sec. 4 compares against, e.g. in the
+ *                          crossing shear wave study.  Orders <= 3, rates and sources are
+ *                          the same in both.  Not available with the learned closure. */
+typedef enum { LBM_ATTRACTOR_FPC = 0, LBM_ATTRACTOR_MAXWELL = 1 } lbm_attractor;
+
 typedef struct {
   int32_t nx, ny, nz;   /* >= 1 each; N = nx*ny*nz must be < 2^31              */
   int32_t storage;      /* lbm_storage                                          */
@@ -102,6 +113,7 @@ typedef struct {
   double omega[LBM_Q];  /* LBM_OMEGA_EXPLICIT only                              */
   double force[3];      /* body force per unit volume, lattice units, dt = 1    */
   void* hip_stream;     /* hipStream_t to run on; NULL: the library makes one   */
+  int32_t attractor;    /* lbm_attractor (default LBM_ATTRACTOR_FPC)            */
 } lbm_config;
 
 typedef struct {
@@ -121,7 +133,8 @@ typedef struct {
 typedef struct lbm_ctx lbm_ctx;
 
 /* Fills cfg with defaults: 0 sizes, LBM_F32, periodic, LBM_OMEGA_PAPER,
- * nu = 1/6, omega_bulk = omega_higher = 1, zero force, NULL stream. */
+ * nu = 1/6, omega_bulk = omega_higher = 1, zero force, NULL stream,
+ * LBM_ATTRACTOR_FPC. */
 void lbm_config_default(lbm_config* cfg);
 
 /* Host-only: the 27 rates the configuration implies (no GPU needed).

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_closure(const typename S
     T ws[6], cs[6];
     closure_rates(nu, C.inv_w, ws, cs);
     relax<T, FORCE>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
-    push<ST, true>(dst, A.g, y, z, ib, v, A.step);
+    push<ST, true>(dst, A.g, x, y, z, ib, v, A.step);
   }
 }
 
@@ -564,6 +564,8 @@ extern "C" int lbm_set_closure(lbm_ctx* c, const float* params) {
   }
   if (c->cfg.nx % 64 != 0)
     return set_err(c, LBM_EINVAL, "lbm_set_closure: nx must be a multiple of 64 (one wavefront per row segment)");
+  if (params && c->cfg.attractor != LBM_ATTRACTOR_FPC)
+    return set_err(c, LBM_EINVAL, "lbm_set_closure: the closure runs with the FPC attractors only");
   for (int p = 0; p < NPARAM; ++p)
     if (!std::isfinite(params[p])) return set_err(c, LBM_EINVAL, "lbm_set_closure: parameter %d is not finite", p);
   std::vector<char> packed;

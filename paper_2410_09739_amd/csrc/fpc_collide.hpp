@@ -28,6 +28,11 @@
 // sources follow Eq. (cmupdatesourceD3Q27) with the pre-collision moments,
 // kappa_000 = rho and first-order moments taken as zero.  kappa^Mv_122 uses the
 // product kappa~_110 kappa~_012 that the general attractor formula gives.
+//
+// MAXWELL = true is the comparison model with Maxwellian equilibria (the
+// MCM-LBM of Sec. 4): orders >= 4 relax to the discrete Maxwellian's central
+// moments rho c_a c_b c_c (c = 1, 0, c_s^2) instead of the Markovian
+// attractors; orders <= 3, rates, grouping and sources are unchanged.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -184,7 +189,7 @@ __host__ __device__ __forceinline__ void pre_collision(T (&v)[3][3][3], T Fx, T 
 // Step 3 on the primed moments in v (as left by pre_collision), then the
 // inverse sweeps.  ws[6], cs[6]: the second-order rates omega_4..omega_9 to use
 // at this node (the rates table, or a per-node closure) and 1 - ws.
-template <typename T, bool FORCE>
+template <typename T, bool FORCE, bool MAXWELL = false>
 __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& R, const T (&ws)[6],
                                                const T (&cs)[6], T Fx, T Fy, T Fz, T rhop, T rho, T ux,
                                                T uy, T uz) {
@@ -265,13 +270,14 @@ __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& 
 
   // ---- order 4: attractors from post-collision order 2 (primed form of
   // (K200 K020 + 2 K110^2)/rho - 1/9 etc.).
-  const T m220 = ((t200 + t020) * third + t200 * t020 + T(2) * t110 * t110 - ninth * rhop) * ir;
-  const T m202 = ((t200 + t002) * third + t200 * t002 + T(2) * t101 * t101 - ninth * rhop) * ir;
-  const T m022 = ((t020 + t002) * third + t020 * t002 + T(2) * t011 * t011 - ninth * rhop) * ir;
+  // (Maxwellian model: rho' c_s^4 and 0, the primed discrete Maxwellian.)
+  const T m220 = MAXWELL ? ninth * rhop : ((t200 + t020) * third + t200 * t020 + T(2) * t110 * t110 - ninth * rhop) * ir;
+  const T m202 = MAXWELL ? ninth * rhop : ((t200 + t002) * third + t200 * t002 + T(2) * t101 * t101 - ninth * rhop) * ir;
+  const T m022 = MAXWELL ? ninth * rhop : ((t020 + t002) * third + t020 * t002 + T(2) * t011 * t011 - ninth * rhop) * ir;
   const T A2 = third + t200, B2 = third + t020, C2 = third + t002;  // full post-collision order 2
-  const T m211 = (A2 * t011 + T(2) * t110 * t101) * ir;
-  const T m121 = (B2 * t101 + T(2) * t110 * t011) * ir;
-  const T m112 = (C2 * t110 + T(2) * t011 * t101) * ir;
+  const T m211 = MAXWELL ? T(0) : (A2 * t011 + T(2) * t110 * t101) * ir;
+  const T m121 = MAXWELL ? T(0) : (B2 * t101 + T(2) * t110 * t011) * ir;
+  const T m112 = MAXWELL ? T(0) : (C2 * t110 + T(2) * t011 * t101) * ir;
   const T c4s1 = k220 + k202 + k022, c4d1 = k220 + k202 - k022, c4d2 = k220 - k202;
   const T t4s1 = c4s1 + R.w[17] * ((m220 + m202 + m022) - c4s1) + R.h[17] * (s220 + s202 + s022);
   const T t4d1 = c4d1 + R.w[18] * ((m220 + m202 - m022) - c4d1) + R.h[18] * (s220 + s202 - s022);
@@ -285,15 +291,15 @@ __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& 
 
   // ---- order 5: attractors from post-collision orders 2 and 3.
   const T f5 = T(0.4) * ir;  // 2 / (5 rho)
-  const T m122 = f5 * (B2 * t102 + C2 * t120 + T(4) * t011 * t111 + T(2) * (t101 * t021 + t110 * t012));
-  const T m212 = f5 * (A2 * t012 + C2 * t210 + T(4) * t101 * t111 + T(2) * (t110 * t102 + t011 * t201));
-  const T m221 = f5 * (A2 * t021 + B2 * t201 + T(4) * t110 * t111 + T(2) * (t011 * t210 + t101 * t120));
+  const T m122 = MAXWELL ? T(0) : f5 * (B2 * t102 + C2 * t120 + T(4) * t011 * t111 + T(2) * (t101 * t021 + t110 * t012));
+  const T m212 = MAXWELL ? T(0) : f5 * (A2 * t012 + C2 * t210 + T(4) * t101 * t111 + T(2) * (t110 * t102 + t011 * t201));
+  const T m221 = MAXWELL ? T(0) : f5 * (A2 * t021 + B2 * t201 + T(4) * t110 * t111 + T(2) * (t011 * t210 + t101 * t120));
   const T t122 = k122 + R.w[23] * (m122 - k122) + R.h[23] * s122;
   const T t212 = k212 + R.w[24] * (m212 - k212) + R.h[24] * s212;
   const T t221 = k221 + R.w[25] * (m221 - k221) + R.h[25] * s221;
 
   // ---- order 6: attractor from post-collision orders 2 and 4 (primed form).
-  const T m222 = ((t200 + t020 + t002) * ninth + (t022 + t202 + t220) * third + t200 * t022 + t020 * t202 +
+  const T m222 = MAXWELL ? rhop * T(1.0 / 27.0) : ((t200 + t020 + t002) * ninth + (t022 + t202 + t220) * third + t200 * t022 + t020 * t202 +
                   t002 * t220 + T(4) * (t110 * t112 + t101 * t121 + t011 * t211)) *
                      (third * ir) -
                  rhop * (T(1.0 / 27.0) * ir);
@@ -316,13 +322,13 @@ __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& 
 
 // Whole collision of one node (Appendix D Steps 7, 1-5): deviation cube in,
 // post-collision deviations (times 2^inv_shift) out.
-template <typename T, bool FORCE>
+template <typename T, bool FORCE, bool MAXWELL = false>
 __host__ __device__ __forceinline__ void collide(T (&v)[3][3][3], const Rates<T>& R, const T (&ws)[6],
                                                  const T (&cs)[6], T Fx, T Fy, T Fz, T& rho, T& ux, T& uy,
                                                  T& uz) {
   T rhop;
   pre_collision<T, FORCE>(v, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
-  relax<T, FORCE>(v, R, ws, cs, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
+  relax<T, FORCE, MAXWELL>(v, R, ws, cs, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
 }
 
 }  // namespace fpc

@@ -21,7 +21,7 @@
 
 // ===========================================================================
 // fused stream + collide (plain method)
-template <int ST, bool WALLS, bool FORCE, bool ROW>
+template <int ST, bool WALLS, bool FORCE, bool ROW, bool MAXWELL>
 __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>::S* __restrict__ src,
                                                         typename Stor<ST>::S* __restrict__ dst,
                                                         StepArgs<typename Stor<ST>::R> A) {
@@ -35,8 +35,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>:
   const T ws[6] = {A.r.w[4], A.r.w[5], A.r.w[6], A.r.w[7], A.r.w[8], A.r.w[9]};
   const T cs[6] = {A.r.c[4], A.r.c[5], A.r.c[6], A.r.c[7], A.r.c[8], A.r.c[9]};
   T rho, ux, uy, uz;
-  collide<T, FORCE>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rho, ux, uy, uz);
-  push<ST, ROW>(dst, A.g, y, z, ib, v, A.step);
+  collide<T, FORCE, MAXWELL>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rho, ux, uy, uz);
+  push<ST, ROW>(dst, A.g, x, y, z, ib, v, A.step);
 }
 
 // ===========================================================================
@@ -374,6 +374,8 @@ extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   const size_t es = elem_size(cfg->storage);
   if (!es) return set_err(nullptr, LBM_EINVAL, "lbm_create: unknown storage %d", cfg->storage);
   if (cfg->walls_y != 0 && cfg->walls_y != 1) return set_err(nullptr, LBM_EINVAL, "lbm_create: walls_y must be 0 or 1");
+  if (cfg->attractor != LBM_ATTRACTOR_FPC && cfg->attractor != LBM_ATTRACTOR_MAXWELL)
+    return set_err(nullptr, LBM_EINVAL, "lbm_create: unknown attractor %d", cfg->attractor);
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(cfg->force[d])) return set_err(nullptr, LBM_EINVAL, "lbm_create: non-finite force");
   double w[LBM_Q];
@@ -485,12 +487,16 @@ static int launch_steps(lbm_ctx* c, int64_t nsteps) {
   dim3 block, grid;
   const bool row = step_launch_shape(c->cfg.nx, c->cfg.ny, c->cfg.nz, block, grid);
   using KFn = void (*)(const S*, S*, StepArgs<T>);
-  static const KFn table[2][2][2] = {
-      {{k_stream_collide<ST, false, false, false>, k_stream_collide<ST, false, false, true>},
-       {k_stream_collide<ST, false, true, false>, k_stream_collide<ST, false, true, true>}},
-      {{k_stream_collide<ST, true, false, false>, k_stream_collide<ST, true, false, true>},
-       {k_stream_collide<ST, true, true, false>, k_stream_collide<ST, true, true, true>}}};
-  const KFn kern = table[walls][force][row];
+  static const KFn table[2][2][2][2] = {
+      {{{k_stream_collide<ST, false, false, false, false>, k_stream_collide<ST, false, false, true, false>},
+        {k_stream_collide<ST, false, true, false, false>, k_stream_collide<ST, false, true, true, false>}},
+       {{k_stream_collide<ST, true, false, false, false>, k_stream_collide<ST, true, false, true, false>},
+        {k_stream_collide<ST, true, true, false, false>, k_stream_collide<ST, true, true, true, false>}}},
+      {{{k_stream_collide<ST, false, false, false, true>, k_stream_collide<ST, false, false, true, true>},
+        {k_stream_collide<ST, false, true, false, true>, k_stream_collide<ST, false, true, true, true>}},
+       {{k_stream_collide<ST, true, false, false, true>, k_stream_collide<ST, true, false, true, true>},
+        {k_stream_collide<ST, true, true, false, true>, k_stream_collide<ST, true, true, true, true>}}}};
+  const KFn kern = table[c->cfg.attractor == LBM_ATTRACTOR_MAXWELL][walls][force][row];
   for (int64_t s = 0; s < nsteps; ++s) {
     const S* src = (const S*)c->buf[c->cur];
     S* dst = (S*)c->buf[c->cur ^ 1];

@@ -140,6 +140,9 @@ __device__ __forceinline__ uint32_t pull(const typename Stor<ST>::S* __restrict_
   using SS = Stor<ST>;
   constexpr uint32_t SZ = sizeof(S);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
+  // rows away from the walls (all but two per plane) take the wall-free gather,
+  // whose loads keep the scalar-base form; the branch is wavefront-uniform
+  if (ROW && WALLS && y > 0 && y < ny - 1) return pull<ST, false, true>(src, g, x, y, z, v);
   const uint32_t rowb = (uint32_t)nx * SZ;
   const uint32_t planeb = rowb * (uint32_t)ny;
   // byte offsets of the source x, y, z for e = -1, 0, +1 (periodic wrap)
@@ -175,19 +178,22 @@ __device__ __forceinline__ uint32_t pull(const typename Stor<ST>::S* __restrict_
 }
 
 // store the post-collision cube (deviations times 2^inv_shift) at byte offset ib
+// ROW: the row's byte offset (uniform) is folded into a scalar base that walks
+// the 27 direction arrays; the per-lane part is the x offset only.
 template <int ST, bool ROW>
-__device__ __forceinline__ void push(typename Stor<ST>::S* __restrict__ dst, const Geom& g, int y, int z, uint32_t ib,
-                                     const typename Stor<ST>::R (&v)[3][3][3], uint32_t step) {
+__device__ __forceinline__ void push(typename Stor<ST>::S* __restrict__ dst, const Geom& g, int x, int y, int z,
+                                     uint32_t ib, const typename Stor<ST>::R (&v)[3][3][3], uint32_t step) {
   using S = typename Stor<ST>::S;
   constexpr uint32_t SZ = sizeof(S);
   const uint64_t stb = (uint64_t)g.stride * SZ;
-  char* __restrict__ db = (char*)dst;
-  const uint32_t rowbase = ROW ? ((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.nx * SZ : 0u;
   const uint32_t h = Stor<ST>::stochastic ? node_hash(ib, step) : 0u;
+  const uint32_t xoff = (uint32_t)x * SZ;
+  char* base = (char*)dst + (ROW ? (uint64_t)(((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.nx * SZ) : 0);
+  const uint32_t off = ROW ? xoff : ib;
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
-    S* p = ROW ? (S*)(db + a * stb + (uint64_t)rowbase + (ib - rowbase)) : (S*)(db + a * stb + ib);
-    *p = Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a), h + (uint32_t)a * 0x9E3779B9u);
+    *(S*)(base + off) = Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a), h + (uint32_t)a * 0x9E3779B9u);
+    base += stb;
   }
 }
 

@@ -1,0 +1,236 @@
+"""Learned-closure channel study: a fine turbulent channel at Re_tau = 180
+(384 x 192 x 192, half-width h = 96, u_tau = 0.0025, nu_f = u_tau h / 180,
+F_f = rho u_tau^2 / h) gives box-filtered snapshots on the 192 x 96 x 96 grid;
+the per-node MLP closure is trained on them on the GPU and drives coarse runs
+(acoustic scaling: nu_c = nu_f / 2, F_c = 2 F_f).  Reports mean and RMS
+velocity profiles of the plain coarse run, the closure run and the filtered
+fine run, the wall friction velocity of each, the wall time of each, and the
+trained parameters (saved as .npy).
+
+    python -m paper_2410_09739_amd.experiments.closure_channel [--tstar-transient 6] [--tstar-stats 4]
+
+Time unit T* = h / u_tau (38,400 fine steps).  The coarse runs start from the
+filtered fine state at the end of the fine transient and cover the same
+physical time as the fine statistics window.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def log(msg: str) -> None:
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+class ProfileStats:
+    """x-z and time averages of u, v, w, their squares and u v, per y row."""
+
+    def __init__(self, torch, ny: int):
+        self.torch = torch
+        self.sum = torch.zeros((7, ny), dtype=torch.float64, device="cuda")
+        self.count = 0
+
+    def add(self, u):  # u: [3, nz, ny, nx] float64 on the device
+        t = self.torch
+        m = t.stack([u[0], u[1], u[2], u[0] * u[0], u[1] * u[1], u[2] * u[2], u[0] * u[1]])
+        self.sum += m.mean(dim=(1, 3))
+        self.count += 1
+
+    def result(self) -> dict:
+        s = (self.sum / max(self.count, 1)).cpu().numpy()
+        U, V, Wm = s[0], s[1], s[2]
+        return {"U": U, "u_rms": np.sqrt(np.maximum(s[3] - U * U, 0)), "v_rms": np.sqrt(np.maximum(s[4] - V * V, 0)),
+                "w_rms": np.sqrt(np.maximum(s[5] - Wm * Wm, 0)), "uv": s[6] - U * V, "samples": self.count}
+
+
+def device_moments(L, torch, lat):
+    rho = torch.empty(lat.n, dtype=torch.float64, device="cuda")
+    u = torch.empty(3 * lat.n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    L.lbm_moments_device(lat.ctx, rho.data_ptr(), u.data_ptr(), True)
+    lat.synchronize()
+    return rho.view(lat.shape), u.view((3,) + lat.shape)
+
+
+def friction_velocity(d: dict, nx: int, nz: int) -> float:
+    tau_w = d["wall_force"][0] / (2.0 * nx * nz)  # two walls, unit area per node
+    return float(np.sqrt(max(tau_w, 0.0)))
+
+
+def run_window(L, torch, lat, steps: int, every: int, stats: ProfileStats | None, tag: str, on_sample=None):
+    done = 0
+    t_run = 0.0
+    while done < steps:
+        k = min(every, steps - done)
+        t0 = time.perf_counter()
+        lat.step(k)
+        lat.synchronize()
+        t_run += time.perf_counter() - t0
+        done += k
+        if stats is not None:
+            _, u = device_moments(L, torch, lat)
+            stats.add(u)
+        if on_sample is not None:
+            on_sample(done)
+        d = lat.diagnostics()
+        log(f"{tag} step {lat.steps}: u_bulk {d['momentum'][0] / d['mass']:.5f} "
+            f"u_tau {friction_velocity(d, lat.cfg.nx, lat.cfg.nz):.5f} max|u| {d['max_speed']:.4f}")
+    return t_run
+
+
+def coarse_profile_of_fine(p: dict) -> dict:
+    """Average pairs of fine rows onto the coarse rows (the y part of the 2x2x2 filter)."""
+    return {k: (0.5 * (v[0::2] + v[1::2]) if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--shape", default="384,192,192")
+    ap.add_argument("--u-tau", type=float, default=0.0025)
+    ap.add_argument("--re-tau", type=float, default=180.0)
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--tstar-transient", type=float, default=6.0)
+    ap.add_argument("--tstar-stats", type=float, default=4.0)
+    ap.add_argument("--samples-per-tstar", type=int, default=4)
+    ap.add_argument("--snapshots", type=int, default=8)
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=2048)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eps-rel", type=float, default=0.1)
+    ap.add_argument("--perturbation", type=float, default=0.3)
+    ap.add_argument("--save-params", default="gpurun_out/closure_params.npy")
+    args = ap.parse_args()
+    import torch
+
+    from paper_2410_09739_amd import lbm as L
+    from paper_2410_09739_amd import workloads as W
+
+    nx, ny, nz = map(int, args.shape.split(","))
+    h = ny / 2.0
+    ut = args.u_tau
+    nu_f = ut * h / args.re_tau
+    F_f = ut * ut / h
+    tstar = int(round(h / ut))
+    cshape = (nx // 2, ny // 2, nz // 2)
+    nc = cshape[0] * cshape[1] * cshape[2]
+    out = {"workload": f"turbulent channel {nx}x{ny}x{nz}, Re_tau={args.re_tau}, u_tau={ut}, nu={nu_f:.6e}, "
+                       f"F={F_f:.6e}; closure grid {cshape[0]}x{cshape[1]}x{cshape[2]}",
+           "tstar_steps": tstar, "args": vars(args)}
+
+    # ---- fine run: transient, then statistics and training snapshots
+    u_bulk0 = 15.7 * ut  # bulk velocity of the turbulent state at Re_tau = 180 (u_b / u_tau ~ 15.7)
+    rho0, u0 = W.channel_turbulent_start(nx, ny, nz, u_bulk=u_bulk0, amp=args.perturbation, seed=1234)
+    fcfg = L.Config(nx, ny, nz, storage=args.storage, walls_y=True, nu=nu_f, force=(F_f, 0, 0))
+    every = max(1, tstar // args.samples_per_tstar)
+    n_trans, n_stats = int(args.tstar_transient * tstar), int(args.tstar_stats * tstar)
+    snap_every = max(every, n_stats // args.snapshots)
+    xs, ys = [], []
+    with L.Lattice(fcfg) as fine:
+        fine.init(rho0, u0)
+        del rho0, u0
+        log(f"fine transient {n_trans} steps")
+        t_fine = run_window(L, torch, fine, n_trans, every, None, "fine")
+        # filtered state at the end of the transient: start of every coarse run
+        rc0 = torch.zeros(nc, dtype=torch.float64, device="cuda")
+        uc0 = torch.zeros(3 * nc, dtype=torch.float64, device="cuda")
+        tc0 = torch.zeros(6 * nc, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        L.lbm_coarsen(fine.ctx, rc0.data_ptr(), uc0.data_ptr(), tc0.data_ptr())
+        fine.synchronize()
+        ccfg = L.Config(*cshape, storage="f32", walls_y=True, nu=nu_f / 2, force=(2 * F_f, 0, 0))
+        feat_lat = L.Lattice(ccfg)
+
+        def snapshot(done):
+            if done % snap_every:
+                return
+            rd = torch.zeros(nc, dtype=torch.float64, device="cuda")
+            ud = torch.zeros(3 * nc, dtype=torch.float64, device="cuda")
+            td = torch.zeros(6 * nc, dtype=torch.float64, device="cuda")
+            xd = torch.zeros((nc, 27), dtype=torch.float32, device="cuda")
+            yd = torch.zeros((nc, 6), dtype=torch.float32, device="cuda")
+            torch.cuda.synchronize()
+            L.lbm_coarsen(fine.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr())
+            fine.synchronize()
+            L.lbm_init_device(feat_lat.ctx, rd.data_ptr(), ud.data_ptr())
+            L.lbm_closure_features(feat_lat.ctx, xd.data_ptr())
+            L.lbm_closure_targets(feat_lat.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), args.eps_rel,
+                                  yd.data_ptr())
+            feat_lat.synchronize()
+            xs.append(xd)
+            ys.append(yd)
+            log(f"snapshot {len(xs)}: mean target nu_t {yd.mean(dim=0).cpu().numpy()}")
+
+        fstats = ProfileStats(torch, ny)
+        log(f"fine statistics {n_stats} steps, snapshot every {snap_every}")
+        t_fine += run_window(L, torch, fine, n_stats, every, fstats, "fine", snapshot)
+        dfin = fine.diagnostics()
+        feat_lat.close()
+    fine_prof = fstats.result()
+    out["fine"] = {"wall_s": t_fine, "steps": n_trans + n_stats, "u_tau_end": friction_velocity(dfin, nx, nz),
+                   "u_bulk_end": dfin["momentum"][0] / dfin["mass"]}
+    filt = coarse_profile_of_fine(fine_prof)
+
+    # ---- training on all snapshots but the last; the last is held out
+    X = torch.cat(xs[:-1]) if len(xs) > 1 else xs[0]
+    Y = torch.cat(ys[:-1]) if len(ys) > 1 else ys[0]
+    Xh, Yh = xs[-1], ys[-1]
+    ntr = X.shape[0]
+    m = L.MLP(seed=11)
+    m.fit_normalisation(X.data_ptr(), Y.data_ptr(), ntr)
+    l0, _ = m.loss_grad(X.data_ptr(), Y.data_ptr(), ntr)
+    lh0, _ = m.loss_grad(Xh.data_ptr(), Yh.data_ptr(), Xh.shape[0])
+    t0 = time.perf_counter()
+    hist = m.train(X.data_ptr(), Y.data_ptr(), ntr, args.batch, args.train_steps, args.lr, 5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    l1, _ = m.loss_grad(X.data_ptr(), Y.data_ptr(), ntr)
+    lh1, _ = m.loss_grad(Xh.data_ptr(), Yh.data_ptr(), Xh.shape[0])
+    params = m.export()
+    m.close()
+    np.save(args.save_params, params)
+    out["training"] = {"samples": int(ntr), "held_out": int(Xh.shape[0]), "loss_train_before": l0,
+                       "loss_train_after": l1, "loss_heldout_before": lh0, "loss_heldout_after": lh1,
+                       "wall_s": t_train, "steps": args.train_steps, "batch": args.batch,
+                       "loss_history_every_100": [float(v) for v in hist[::100]]}
+    log(f"training: loss {l0:.4e} -> {l1:.4e}, held-out {lh0:.4e} -> {lh1:.4e}, {t_train:.1f} s")
+    del X, Y, xs, ys
+
+    # ---- coarse runs from the filtered fine state
+    ctrans, cstats = n_trans // 2, n_stats // 2  # same physical time (dt_c = 2 dt_f)
+    cevery = max(1, every // 2)
+    res = {}
+    for name, p in (("plain", None), ("closure", params)):
+        with L.Lattice(ccfg) as c:
+            L.lbm_init_device(c.ctx, rc0.data_ptr(), uc0.data_ptr())
+            if p is not None:
+                L.lbm_set_closure(c.ctx, p)
+            cs = ProfileStats(torch, cshape[1])
+            t_c = run_window(L, torch, c, cstats, cevery, cs, f"coarse {name}")
+            dc = c.diagnostics()
+        pr = cs.result()
+        res[name] = {"wall_s": t_c, "steps": cstats, "u_tau_end": friction_velocity(dc, cshape[0], cshape[2]),
+                     "u_bulk_end": dc["momentum"][0] / dc["mass"], "profile": pr}
+    for name in res:
+        pr = res[name].pop("profile")
+        res[name]["rel_l2_U_vs_filtered_fine"] = float(np.sqrt(np.sum((pr["U"] - filt["U"]) ** 2) /
+                                                               np.sum(filt["U"] ** 2)))
+        for q in ("u_rms", "v_rms", "w_rms"):
+            res[name][f"rel_l2_{q}_vs_filtered_fine"] = float(np.sqrt(np.sum((pr[q] - filt[q]) ** 2) /
+                                                                      np.sum(filt[q] ** 2)))
+        res[name]["U_over_u_tau"] = [round(float(v) / ut, 4) for v in pr["U"][: cshape[1] // 2]]
+        log(f"coarse {name}: U rel L2 {res[name]['rel_l2_U_vs_filtered_fine']:.4f}, u_tau {res[name]['u_tau_end']:.5f}")
+    out["coarse"] = res
+    out["coarse_start_after_fine_steps"] = n_trans
+    out["filtered_fine_U_over_u_tau"] = [round(float(v) / ut, 4) for v in filt["U"][: cshape[1] // 2]]
+    out["filtered_fine_rms_over_u_tau"] = {q: [round(float(v) / ut, 4) for v in filt[q][: cshape[1] // 2]]
+                                           for q in ("u_rms", "v_rms", "w_rms")}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

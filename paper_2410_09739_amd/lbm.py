@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_F64, LBM_F32, LBM_F16DEV, LBM_BF16DEV, LBM_F16DEV_RNE, LBM_BF16DEV_RNE = 0, 1, 2, 3, 4, 5
 LBM_OMEGA_PAPER, LBM_OMEGA_ORDER_SCALED, LBM_OMEGA_EXPLICIT = 0, 1, 2
+LBM_ATTRACTOR_FPC, LBM_ATTRACTOR_MAXWELL = 0, 1
 Q = 27
 CLOSURE_NPARAM = 6342
 
@@ -28,6 +29,7 @@ STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16dev": LBM_F16DEV, "bf16dev": LBM_
            "f16dev_rne": LBM_F16DEV_RNE, "bf16dev_rne": LBM_BF16DEV_RNE}
 STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16DEV: 2, LBM_BF16DEV: 2, LBM_F16DEV_RNE: 2, LBM_BF16DEV_RNE: 2}
 OMEGA_MODE = {"paper": LBM_OMEGA_PAPER, "order_scaled": LBM_OMEGA_ORDER_SCALED, "explicit": LBM_OMEGA_EXPLICIT}
+ATTRACTOR = {"fpc": LBM_ATTRACTOR_FPC, "maxwell": LBM_ATTRACTOR_MAXWELL}
 
 
 class lbm_config(ctypes.Structure):
@@ -36,7 +38,7 @@ class lbm_config(ctypes.Structure):
         ("storage", ctypes.c_int32), ("walls_y", ctypes.c_int32), ("omega_mode", ctypes.c_int32),
         ("nu", ctypes.c_double), ("omega_bulk", ctypes.c_double), ("omega_higher", ctypes.c_double),
         ("omega", ctypes.c_double * Q), ("force", ctypes.c_double * 3),
-        ("hip_stream", ctypes.c_void_p),
+        ("hip_stream", ctypes.c_void_p), ("attractor", ctypes.c_int32),
     ]
 
 
@@ -246,6 +248,7 @@ class Config:
     omega: Optional[Sequence[float]] = None
     force: Sequence[float] = (0.0, 0.0, 0.0)
     hip_stream: Optional[int] = None
+    attractor: str = "fpc"
 
     def to_c(self) -> lbm_config:
         c = lbm_config_default()
@@ -262,6 +265,7 @@ class Config:
         for d in range(3):
             c.force[d] = float(self.force[d])
         c.hip_stream = self.hip_stream
+        c.attractor = ATTRACTOR[self.attractor]
         return c
 
 

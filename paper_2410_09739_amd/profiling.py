@@ -1,0 +1,171 @@
+"""Turn rocprofv3 CSV output into the short text summaries kept with the
+measurements.
+
+Two commands:
+
+``kernel-stats STATS_CSV OUT.md --title T --cmd C [--trace TRACE_CSV]``
+    Table of the ``*_kernel_stats.csv`` written by
+    ``rocprofv3 --kernel-trace --stats --output-format csv`` (with the trace
+    CSV: one row per kernel and launch grid).
+
+``traffic --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --out OUT.md --cmd C ...``
+    HBM bytes per launch of the stream-collide kernel of every storage form,
+    from one ``--pmc FETCH_SIZE`` and one ``--pmc WRITE_SIZE`` run of the bench
+    (counter values in KiB per dispatch), each scaled by what the same counter
+    reads for a plain device copy of known size.  The result is written as
+    markdown with one fenced JSON block that the bench reads back; the block
+    records a hash of the kernel sources so that a stale measurement is never
+    reported for a changed kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_2410_09739_amd/csrc/lbm.hip", "paper_2410_09739_amd/csrc/fpc_collide.hpp",
+                  "paper_2410_09739_amd/csrc/d3q27.hpp", "paper_2410_09739_amd/csrc/lbm_internal.hpp"]
+# storage form id (template argument of k_stream_collide) -> (name, bytes per population)
+FORMS = {0: ("f64", 8), 1: ("f32", 4), 2: ("f16dev", 2), 3: ("bf16dev", 2), 4: ("f16dev_rne", 2),
+         5: ("bf16dev_rne", 2)}
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_means(d: str) -> dict[str, list[float]]:
+    path = next(os.path.join(d, f) for f in sorted(os.listdir(d)) if f.endswith("counter_collection.csv"))
+    vals: dict[str, list[float]] = defaultdict(list)
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return vals
+
+
+def _copy_factor(d: str, nbytes: int) -> float:
+    """Bytes that one KiB of the counter stands for, from a copy of ``nbytes``."""
+    v = _counter_means(d)[COPY_KERNEL]
+    big = [x for x in v if x > 0.25 * max(v)]
+    return nbytes / (sum(big) / len(big))
+
+
+def traffic(args) -> dict:
+    nodes = args.nx * args.ny * args.nz
+    cf = _copy_factor(args.copy_fetch, args.copy_bytes)
+    cw = _copy_factor(args.copy_write, args.copy_bytes)
+    fetch, write = _counter_means(args.fetch), _counter_means(args.write)
+    forms = {}
+    for name in fetch:
+        m = re.match(r"void k_stream_collide<(\d+),", name)
+        if not m or name not in write:
+            continue
+        form, sb = FORMS[int(m.group(1))]
+        fk = sum(fetch[name]) / len(fetch[name])
+        wk = sum(write[name]) / len(write[name])
+        hbm = fk * cf + wk * cw
+        alg = nodes * 54 * sb
+        forms[form] = {"kernel": name, "launches": len(fetch[name]), "fetch_kib": round(fk, 3),
+                       "write_kib": round(wk, 3), "hbm_bytes_per_launch": round(hbm),
+                       "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": round(hbm / alg, 5)}
+    return {"kernel_source_sha": kernel_source_hash(), "shape": [args.nx, args.ny, args.nz], "nodes": nodes,
+            "copy_factor_fetch_bytes_per_kib": round(cf, 3), "copy_factor_write_bytes_per_kib": round(cw, 3),
+            "forms": forms}
+
+
+def write_traffic_md(res: dict, out: str, cmds: list[str]) -> None:
+    with open(out, "w") as fo:
+        fo.write("# HBM traffic of the fused stream-collide kernel, channel "
+                 + "x".join(str(n) for n in res["shape"]) + " (walls, body force)\n\n")
+        fo.write("FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from separate rocprofv3 --pmc runs, "
+                 "each scaled by the bytes per KiB that the same counter shows for a plain device "
+                 f"copy of known size (fetch {res['copy_factor_fetch_bytes_per_kib']} B/KiB, "
+                 f"write {res['copy_factor_write_bytes_per_kib']} B/KiB).  Algorithmic bytes per "
+                 "launch: 27 reads + 27 writes of the stored population per node.\n\n")
+        fo.write("Commands (run from the repository root):\n\n```\n" + "\n".join(cmds) + "\n```\n\n")
+        fo.write("| form | fetch KiB | write KiB | HBM bytes / launch | algorithmic | ratio |\n"
+                 "|---|---|---|---|---|---|\n")
+        for f, r in res["forms"].items():
+            fo.write(f"| {f} | {r['fetch_kib']:.1f} | {r['write_kib']:.1f} | {r['hbm_bytes_per_launch']} | "
+                     f"{r['algorithmic_bytes_per_launch']} | {r['traffic_over_algorithmic']:.4f} |\n")
+        fo.write("\n```json\n" + json.dumps(res, indent=1) + "\n```\n")
+
+
+def read_traffic_md(path: str) -> dict | None:
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        m = re.search(r"```json\n(.*?)\n```", fh.read(), re.S)
+    return json.loads(m.group(1)) if m else None
+
+
+def kernel_stats(args) -> None:
+    """Per-kernel table from ``*_kernel_stats.csv``; with ``--trace`` (the
+    ``*_kernel_trace.csv`` of the same run) one row per kernel and grid size,
+    so that launches of one kernel on different lattices are told apart."""
+    rows = []
+    if args.trace:
+        groups: dict[tuple, list[float]] = defaultdict(list)
+        with open(args.trace) as fh:
+            for r in csv.DictReader(fh):
+                grid = "x".join(r[f"Grid_Size_{d}"] for d in "XYZ")
+                groups[(r["Kernel_Name"], grid)].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        total = sum(sum(v) for v in groups.values())
+        for (name, grid), v in groups.items():
+            rows.append((name, grid, len(v), sum(v) / 1e3, sum(v) / len(v) / 1e3, 100.0 * sum(v) / total))
+        rows.sort(key=lambda r: -r[3])
+    else:
+        with open(args.stats) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((r["Name"], "", int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
+                             float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    with open(args.out, "w") as fo:
+        fo.write(f"# {args.title}\n\nCommand (run from the repository root):\n\n```\n{args.cmd}\n```\n\n")
+        if args.note:
+            fo.write(args.note + "\n\n")
+        fo.write("| kernel | grid (threads) | calls | total (us) | average (us) | % |\n|---|---|---|---|---|---|\n")
+        for name, grid, calls, tot, avg, pct in rows[: args.rows]:
+            n = name if len(name) < 120 else name[:117] + "..."
+            fo.write(f"| `{n}` | {grid} | {calls} | {tot:.1f} | {avg:.3f} | {pct:.2f} |\n")
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    k = sub.add_parser("kernel-stats")
+    k.add_argument("stats")
+    k.add_argument("out")
+    k.add_argument("--title", required=True)
+    k.add_argument("--cmd", required=True)
+    k.add_argument("--rows", type=int, default=16)
+    k.add_argument("--trace", default=None, help="the run's *_kernel_trace.csv: split rows by grid size")
+    k.add_argument("--note", default="")
+    t = sub.add_parser("traffic")
+    for a in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--out"):
+        t.add_argument(a, required=True)
+    t.add_argument("--copy-bytes", type=int, default=1 << 31)
+    t.add_argument("--nx", type=int, default=256)
+    t.add_argument("--ny", type=int, default=128)
+    t.add_argument("--nz", type=int, default=128)
+    t.add_argument("--cmd", action="append", default=[])
+    a = ap.parse_args()
+    if a.cmd_name == "kernel-stats":
+        kernel_stats(a)
+    else:
+        res = traffic(a)
+        write_traffic_md(res, a.out, a.cmd)
+        print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

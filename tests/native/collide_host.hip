@@ -7,7 +7,7 @@
 
 using namespace fpc;
 
-template <typename T>
+template <typename T, bool MAXWELL>
 static void run(const double* f, const double* omega, const double* F, double* out) {
   T v[3][3][3];
   for (int a = 0; a < Q; ++a) v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] = (T)(f[a] - weight(a));
@@ -22,17 +22,24 @@ static void run(const double* f, const double* omega, const double* F, double* o
   T rho, ux, uy, uz;
   const bool force = F[0] != 0.0 || F[1] != 0.0 || F[2] != 0.0;
   if (force)
-    collide<T, true>(v, R, ws, cs, (T)F[0], (T)F[1], (T)F[2], rho, ux, uy, uz);
+    collide<T, true, MAXWELL>(v, R, ws, cs, (T)F[0], (T)F[1], (T)F[2], rho, ux, uy, uz);
   else
-    collide<T, false>(v, R, ws, cs, T(0), T(0), T(0), rho, ux, uy, uz);
+    collide<T, false, MAXWELL>(v, R, ws, cs, T(0), T(0), T(0), rho, ux, uy, uz);
   for (int a = 0; a < Q; ++a) out[a] = weight(a) + (double)(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] * (T)inv_factor(a));
 }
 
 extern "C" void host_collide_f64(const double* f, const double* omega, const double* F, double* out) {
-  run<double>(f, omega, F, out);
+  run<double, false>(f, omega, F, out);
 }
 extern "C" void host_collide_f32(const double* f, const double* omega, const double* F, double* out) {
-  run<float>(f, omega, F, out);
+  run<float, false>(f, omega, F, out);
+}
+// the Maxwellian-attractor comparison model
+extern "C" void host_collide_maxwell_f64(const double* f, const double* omega, const double* F, double* out) {
+  run<double, true>(f, omega, F, out);
+}
+extern "C" void host_collide_maxwell_f32(const double* f, const double* omega, const double* F, double* out) {
+  run<float, true>(f, omega, F, out);
 }
 // f^eq(rho, u) through the kernels' inverse sweeps (what lbm_init stores)
 extern "C" void host_feq_f64(double rho, const double* u, double* out) {

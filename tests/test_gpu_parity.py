@@ -279,3 +279,61 @@ def test_small_force_momentum_is_kept_by_stochastic_rounding(storage, tol):
     n = np.prod(shape)
     gain = d1["momentum"][0] - d0["momentum"][0]
     assert gain == pytest.approx(400 * n * F[0], rel=tol)
+
+
+# ------------------------------------------------------------------ Maxwellian comparison model
+@pytest.mark.parametrize("shape,walls,force", [((13, 10, 9), False, (0, 0, 0)), ((32, 8, 5), True, (3e-5, -2e-5, 1e-5)),
+                                               ((256, 6, 3), True, (1e-5, 0, 0))])
+def test_maxwellian_attractors_match_oracle(shape, walls, force):
+    """LBM_ATTRACTOR_MAXWELL against the oracle's Maxwellian model, FP64 to
+    1e-12 and FP32 to the per-step bound; the last shape takes the row-block
+    launch (nx = 256)."""
+    g0 = _state(shape, seed=7 + shape[0], amp=0.1)
+    om = O.omega_table(0.002)
+    steps = 4
+    ref = O.run(g0, om, force, walls_y=walls, steps=steps, attractor="maxwell")
+    got = _run_gpu(shape, "f64", g0, steps, nu=0.002, walls=walls, force=force, attractor="maxwell")
+    assert _rel(got, ref) <= 1e-12
+    got32 = _run_gpu(shape, "f32", g0, steps, nu=0.002, walls=walls, force=force, attractor="maxwell")
+    assert np.all(np.abs(got32 - ref) <= _tol("f32", steps, ref))
+    fpc = O.run(g0, om, force, walls_y=walls, steps=steps)
+    assert _rel(fpc, ref) > 1e-6  # the two models differ on this state
+
+
+def test_crossing_shear_waves_fpc_and_maxwellian_on_gpu():
+    """The crossing shear wave of Sec. 4 (L = 30, nu = 1e-7, U_y = 1e-5) run
+    on the GPU in FP64 with both attractor sets: populations equal the
+    oracle's after 300 steps, and over 3,000 more steps the Maxwellian model
+    loses far more amplitude than FPC-LBM (numerical hyperviscosity)."""
+    nx, ny, nz = 30, 2, 30
+    k = 2 * np.pi / 30
+    Z, _, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    mode = np.cos(k * X) * np.cos(k * Z)
+    u = np.zeros((3, nz, ny, nx))
+    u[1] = 1e-5 * mode
+    rho = np.ones((nz, ny, nx))
+    om = O.omega_table(1e-7)
+    amps = {}
+    for att in ("fpc", "maxwell"):
+        with L.Lattice(L.Config(nx, ny, nz, storage="f64", nu=1e-7, attractor=att)) as lat:
+            lat.init(rho, u)
+            g0 = lat.get_f()
+            np.testing.assert_allclose(g0, O.init(rho, u), rtol=0, atol=4e-16)
+            lat.step(300)
+            ref = O.run(g0, om, steps=300, attractor=att)
+            assert _rel(lat.get_f(), ref) <= 1e-12
+            a = []
+            for extra in (0, 3000):
+                lat.step(extra)
+                uu = lat.moments()[1]
+                a.append((uu[1] * mode).sum() / (mode * mode).sum() / 1e-5)
+            amps[att] = a
+    loss_fpc = 1 - amps["fpc"][1] / amps["fpc"][0]
+    loss_mcm = 1 - amps["maxwell"][1] / amps["maxwell"][0]
+    assert loss_mcm > 0.1 and loss_mcm > 50 * abs(loss_fpc), (loss_fpc, loss_mcm)
+
+
+def test_closure_rejects_maxwellian_attractors():
+    with L.Lattice(L.Config(64, 4, 4, storage="f32", attractor="maxwell")) as lat:
+        with pytest.raises(L.LBMError):
+            L.lbm_set_closure(lat.ctx, np.zeros(L.CLOSURE_NPARAM, dtype=np.float32))

@@ -21,7 +21,7 @@ def host():
         from paper_2410_09739_amd import build
         build.build_host_check()
     lib = ctypes.CDLL(LIB)
-    for n in ("host_collide_f64", "host_collide_f32"):
+    for n in ("host_collide_f64", "host_collide_f32", "host_collide_maxwell_f64", "host_collide_maxwell_f32"):
         getattr(lib, n).argtypes = [_dp, _dp, _dp, _dp]
     lib.host_feq_f64.argtypes = [ctypes.c_double, _dp, _dp]
     return lib
@@ -37,8 +37,9 @@ def _call(fn, f, om, F):
 WA = O.feq(1.0, [0, 0, 0])
 
 
+@pytest.mark.parametrize("attractor", ["fpc", "maxwell"])
 @pytest.mark.parametrize("seed", range(12))
-def test_host_collision_matches_oracle(host, seed):
+def test_host_collision_matches_oracle(host, seed, attractor):
     rng = np.random.default_rng(100 + seed)
     u = 0.1 * rng.uniform(-1, 1, 3)
     f = O.feq(1 + 0.05 * rng.uniform(-1, 1), u) * W.random_factors(27, seed, 0.2)
@@ -46,11 +47,12 @@ def test_host_collision_matches_oracle(host, seed):
     om = O.omega_table(10 ** rng.uniform(-5, -0.5), omega_bulk=rng.uniform(0.5, 1.9),
                        omega_higher=rng.uniform(0.5, 1.9), mode=mode, explicit=rng.uniform(0.1, 1.99, 27))
     F = 1e-4 * rng.uniform(-1, 1, 3) if seed % 2 else np.zeros(3)
-    ref = O.collide_node(f, om, F)
-    got = _call(host.host_collide_f64, f, om, F)
+    ref = O.collide_node(f, om, F, attractor=attractor)
+    tag = "" if attractor == "fpc" else "maxwell_"
+    got = _call(getattr(host, f"host_collide_{tag}f64"), f, om, F)
     err = np.max(np.abs(got - ref) / np.maximum(np.abs(ref), WA))
     assert err <= 1e-13, err
-    got32 = _call(host.host_collide_f32, f, om, F)
+    got32 = _call(getattr(host, f"host_collide_{tag}f32"), f, om, F)
     assert np.all(np.abs(got32 - ref) <= 4e-7 * WA), np.max(np.abs(got32 - ref) / WA)
 
 
