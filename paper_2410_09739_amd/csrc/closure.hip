@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_closure(const typename S
     const int y = (int)(row % A.g.ny), z = (int)(row / A.g.ny);
     const int x = xseg * 64 + lane;
     T v[3][3][3];
-    const uint32_t ib = pull<ST, WALLS, true>(src, A.g, x, y, z, v);
+    pull<ST, WALLS>(src, A.g, x, y, z, v);
     T rhop, rho, ux, uy, uz;
     pre_collision<T, FORCE>(v, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
     float feat[NIN], nu[NOUT];
@@ -113,22 +113,22 @@ __global__ __launch_bounds__(256) void k_stream_collide_closure(const typename S
     T ws[6], cs[6];
     closure_rates(nu, C.inv_w, ws, cs);
     relax<T, FORCE>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
-    push<ST, true>(dst, A.g, x, y, z, ib, v, A.step);
+    push<ST>(dst, A.g, x, y, z, v, A.step);
   }
 }
 
 // Features of the next collision at every node (no collision, no store):
-// x[i][27], i = x + nx (y + ny z).
+// x[i][27], i = x + nx (y + ny z).  Block (64, 4): one x segment of one row
+// per wavefront, as pull() requires.
 template <int ST, bool WALLS, bool FORCE>
 __global__ __launch_bounds__(256) void k_closure_features(const typename Stor<ST>::S* __restrict__ src,
                                                           StepArgs<typename Stor<ST>::R> A, float* __restrict__ out) {
   using T = typename Stor<ST>::R;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= A.g.nx || y >= A.g.ny) return;
+  int x, y, z;
+  wave_segment(x, y, z);
+  if (x >= A.g.nx) return;
   T v[3][3][3];
-  pull<ST, WALLS, false>(src, A.g, x, y, z, v);
+  pull<ST, WALLS>(src, A.g, x, y, z, v);
   T rhop, rho, ux, uy, uz;
   pre_collision<T, FORCE>(v, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
   float feat[NIN];
@@ -174,11 +174,10 @@ __global__ __launch_bounds__(256) void k_coarsen(const typename Stor<ST>::S* __r
   for (int dz = 0; dz < 2; ++dz)
     for (int dy = 0; dy < 2; ++dy)
       for (int dx = 0; dx < 2; ++dx) {
-        const int64_t i = ((int64_t)(2 * Z + dz) * g.ny + (2 * Y + dy)) * g.nx + (2 * X + dx);
         double rp = 0, j[3] = {0, 0, 0};
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
-          const double d = (double)Stor<ST>::dec(src[a * g.stride + i], a);
+          const double d = (double)Stor<ST>::dec(src[pop_index(g, a, 2 * X + dx, 2 * Y + dy, 2 * Z + dz)], a);
           rp += d;
           j[0] += EX[a] * d;
           j[1] += EY[a] * d;
@@ -302,7 +301,7 @@ __global__ __launch_bounds__(256) void k_targets(const double* __restrict__ rho,
 // f~(0) = f^eq(rho, u) from device fields (what lbm_init does from host fields)
 template <int ST>
 __global__ __launch_bounds__(256) void k_init_dev(const double* __restrict__ rho, const double* __restrict__ u,
-                                                  typename Stor<ST>::S* __restrict__ dst, int64_t n, int64_t st) {
+                                                  typename Stor<ST>::S* __restrict__ dst, int64_t n, Geom g) {
   using T = typename Stor<ST>::R;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -316,8 +315,11 @@ __global__ __launch_bounds__(256) void k_init_dev(const double* __restrict__ rho
 #pragma unroll
       for (int a = 0; a < 3; ++a) v[c][b][a] = rp * T(C1[a] * C1[b] * C1[c]);
   inverse_all(v, ux, uy, uz);
+  int x, y, z;
+  node_xyz(g, i, x, y, z);
 #pragma unroll
-  for (int a = 0; a < Q; ++a) dst[a * st + i] = Stor<ST>::enc_nearest(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
+  for (int a = 0; a < Q; ++a)
+    dst[pop_index(g, a, x, y, z)] = Stor<ST>::enc_nearest(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
 }
 
 // ---------------------------------------------------------------------------
@@ -506,7 +508,7 @@ static void launch_closure_kernel(lbm_ctx* c, int grid, const StepArgs<typename 
 template <typename T>
 static StepArgs<T> step_args(const lbm_ctx* c) {
   StepArgs<T> A;
-  A.g = Geom{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->stride};
+  A.g = geom(c);
   for (int j = 0; j < LBM_Q; ++j) {
     A.r.w[j] = (T)c->omega[j];
     A.r.c[j] = (T)(1.0 - c->omega[j]);
@@ -583,9 +585,8 @@ extern "C" int lbm_closure_features(lbm_ctx* c, float* x_dev) {
   HIPCHK(c, hipSetDevice(c->device));
   const bool walls = c->cfg.walls_y != 0;
   const bool force = c->cfg.force[0] != 0.0 || c->cfg.force[1] != 0.0 || c->cfg.force[2] != 0.0;
-  const int nx = c->cfg.nx;
-  const int bx = nx >= 256 ? 256 : (nx + 31) / 32 * 32, by = 256 / bx;
-  const dim3 block(bx, by, 1), grid((nx + bx - 1) / bx, (c->cfg.ny + by - 1) / by, c->cfg.nz);
+  dim3 block, grid;
+  step_launch_shape(c->cfg.nx, c->cfg.ny, c->cfg.nz, block, grid);
   DISPATCH_ST(c->cfg.storage, {
     using T = typename Stor<ST>::R;
     using S = typename Stor<ST>::S;
@@ -636,7 +637,7 @@ extern "C" int lbm_init_device(lbm_ctx* c, const double* rho_dev, const double* 
   c->cur = 0;
   DISPATCH_ST(c->cfg.storage,
               k_init_dev<ST><<<nblocks(c->n, 256), 256, 0, c->stream>>>(rho_dev, u_dev, (typename Stor<ST>::S*)c->buf[0],
-                                                                         c->n, c->stride));
+                                                                         c->n, geom(c)));
   LAUNCHCHK(c);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->initialised = true;
@@ -650,7 +651,7 @@ extern "C" int lbm_coarsen(lbm_ctx* c, double* rho_dev, double* u_dev, double* t
   if (c->cfg.nx % 2 || c->cfg.ny % 2 || c->cfg.nz % 2)
     return set_err(c, LBM_EINVAL, "lbm_coarsen: nx, ny, nz must be even");
   HIPCHK(c, hipSetDevice(c->device));
-  const Geom g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->stride};
+  const Geom g = geom(c);
   const int64_t nc = c->n / 8;
   const double* F = c->cfg.force;
   DISPATCH_ST(c->cfg.storage,
@@ -664,7 +665,7 @@ extern "C" int lbm_closure_targets(lbm_ctx* c, const double* rho_dev, const doub
                                    double eps_rel, float* y_dev) {
   if (!c || !rho_dev || !u_dev || !tau_dev || !y_dev || !(eps_rel >= 0.0)) return LBM_EINVAL;
   HIPCHK(c, hipSetDevice(c->device));
-  const Geom g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->stride};
+  const Geom g = geom(c);
   double* part = nullptr;
   HIPCHK(c, hipMalloc((void**)&part, sizeof(double) * (RB + 1)));
   k_strain_sq<<<RB, 256, 0, c->stream>>>(u_dev, g, c->cfg.walls_y, part);

@@ -1,12 +1,13 @@
 // lbm.hip -- gfx950 kernels and the C ABI of include/lbm.h.
 //
-// Data layout in HBM: two state buffers (A/B, ping-pong), each 27 direction
-// arrays of `stride` values (N rounded up to 256, plus kStridePad), node index
-// i = x + nx (y + ny z).  A step reads the previous post-collision state from
-// one buffer with a pull gather (f_alpha(x) = f~_alpha(x - e_alpha), Appendix D
-// Step 6; halfway bounce-back takes the node's own opposite population) and
-// writes the new post-collision state to the other: 27 reads and 27 writes per
-// node, each direction array read exactly once, no atomics, no LDS.
+// Data layout in HBM: two state buffers (A/B, ping-pong) in the blocked
+// layout of lbm_internal.hpp (per row, segments of 64 x-consecutive nodes
+// holding their 27 directions one after the other).  A step reads the
+// previous post-collision state from one buffer with a pull gather
+// (f_alpha(x) = f~_alpha(x - e_alpha), Appendix D Step 6; halfway bounce-back
+// takes the node's own opposite population) and writes the new post-collision
+// state to the other: 27 reads and 27 writes per node, each value read exactly
+// once, no atomics, no LDS.  One wavefront updates one 64-node segment.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -21,22 +22,22 @@
 
 // ===========================================================================
 // fused stream + collide (plain method)
-template <int ST, bool WALLS, bool FORCE, bool ROW, bool MAXWELL>
+// Block (64, 4): each wavefront is one x segment of one row (y, z uniform).
+template <int ST, bool WALLS, bool FORCE, bool MAXWELL>
 __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>::S* __restrict__ src,
                                                         typename Stor<ST>::S* __restrict__ dst,
                                                         StepArgs<typename Stor<ST>::R> A) {
   using T = typename Stor<ST>::R;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = ROW ? (int)blockIdx.y : (int)(blockIdx.y * blockDim.y + threadIdx.y);
-  const int z = blockIdx.z;
-  if (x >= A.g.nx || (!ROW && y >= A.g.ny)) return;
+  int x, y, z;
+  wave_segment(x, y, z);
+  if (x >= A.g.nx) return;
   T v[3][3][3];
-  const uint32_t ib = pull<ST, WALLS, ROW>(src, A.g, x, y, z, v);
+  pull<ST, WALLS>(src, A.g, x, y, z, v);
   const T ws[6] = {A.r.w[4], A.r.w[5], A.r.w[6], A.r.w[7], A.r.w[8], A.r.w[9]};
   const T cs[6] = {A.r.c[4], A.r.c[5], A.r.c[6], A.r.c[7], A.r.c[8], A.r.c[9]};
   T rho, ux, uy, uz;
   collide<T, FORCE, MAXWELL>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rho, ux, uy, uz);
-  push<ST, ROW>(dst, A.g, x, y, z, ib, v, A.step);
+  push<ST>(dst, A.g, x, y, z, v, A.step);
 }
 
 // ===========================================================================
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>:
 // inverse sweeps (the same ones the collision uses).
 template <int ST>
 __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, const double* __restrict__ u,
-                                              typename Stor<ST>::S* __restrict__ dst, int64_t n, int64_t st) {
+                                              typename Stor<ST>::S* __restrict__ dst, int64_t n, Geom g) {
   using T = typename Stor<ST>::R;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -58,41 +59,51 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho, co
 #pragma unroll
       for (int a = 0; a < 3; ++a) v[c][b][a] = rp * T(C1[a] * C1[b] * C1[c]);
   inverse_all(v, ux, uy, uz);
-#pragma unroll
-  for (int a = 0; a < Q; ++a) dst[a * st + i] = Stor<ST>::enc_nearest(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
-}
-
-template <int ST>
-__global__ __launch_bounds__(256) void k_set_f(const double* __restrict__ f, typename Stor<ST>::S* __restrict__ dst,
-                                               int64_t n, int64_t st) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  int x, y, z;
+  node_xyz(g, i, x, y, z);
 #pragma unroll
   for (int a = 0; a < Q; ++a)
-    dst[a * st + i] = Stor<ST>::enc_nearest((typename Stor<ST>::R)(f[a * n + i] - weight(a)), a);
+    dst[pop_index(g, a, x, y, z)] = Stor<ST>::enc_nearest(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a));
+}
+
+// host order f[a][i] <-> the blocked layout
+template <int ST>
+__global__ __launch_bounds__(256) void k_set_f(const double* __restrict__ f, typename Stor<ST>::S* __restrict__ dst,
+                                               int64_t n, Geom g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int x, y, z;
+  node_xyz(g, i, x, y, z);
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+    dst[pop_index(g, a, x, y, z)] = Stor<ST>::enc_nearest((typename Stor<ST>::R)(f[a * n + i] - weight(a)), a);
 }
 
 template <int ST>
 __global__ __launch_bounds__(256) void k_get_f(const typename Stor<ST>::S* __restrict__ src, double* __restrict__ f,
-                                               int64_t n, int64_t st) {
+                                               int64_t n, Geom g) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  int x, y, z;
+  node_xyz(g, i, x, y, z);
 #pragma unroll
-  for (int a = 0; a < Q; ++a) f[a * n + i] = weight(a) + (double)Stor<ST>::dec(src[a * st + i], a);
+  for (int a = 0; a < Q; ++a) f[a * n + i] = weight(a) + (double)Stor<ST>::dec(src[pop_index(g, a, x, y, z)], a);
 }
 
 // Step 7 fields from the stored post-collision state: rho = 1 + sum delta,
 // rho u = sum delta e - F/2.
 template <int ST, typename OUT>
 __global__ __launch_bounds__(256) void k_moments(const typename Stor<ST>::S* __restrict__ src, OUT* __restrict__ rho,
-                                                 OUT* __restrict__ u, int64_t n, int64_t st, double Fx, double Fy,
+                                                 OUT* __restrict__ u, int64_t n, Geom g, double Fx, double Fy,
                                                  double Fz) {
   using T = typename Stor<ST>::R;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  int x, y, z;
+  node_xyz(g, i, x, y, z);
   T v[3][3][3];
 #pragma unroll
-  for (int a = 0; a < Q; ++a) v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] = Stor<ST>::dec(src[a * st + i], a);
+  for (int a = 0; a < Q; ++a) v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] = Stor<ST>::dec(src[pop_index(g, a, x, y, z)], a);
   T rp, jx, jy, jz;
   density_momentum(v, rp, jx, jy, jz);
   const double r = 1.0 + (double)rp;
@@ -157,18 +168,19 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_nodes(const typename Stor
                                                              double* __restrict__ uscr, double* __restrict__ part,
                                                              Geom g, int walls, double Fx, double Fy, double Fz) {
   const int64_t n = (int64_t)g.nx * g.ny * g.nz;
-  const int64_t st = g.stride;
   double acc[NP];
   const int kind[NP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 2};
 #pragma unroll
   for (int k = 0; k < NP; ++k) acc[k] = 0.0;
   acc[P_MINRHO] = INFINITY;
   for (int64_t i = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x; i < n; i += (int64_t)DIAG_BLOCKS * DIAG_THREADS) {
+    int x, y, z;
+    node_xyz(g, i, x, y, z);
     double d[Q];
     bool finite = true;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      d[a] = (double)Stor<ST>::dec(src[a * st + i], a);
+      d[a] = (double)Stor<ST>::dec(src[pop_index(g, a, x, y, z)], a);
       finite = finite && isfinite(d[a]);
     }
     double rp = 0, jx = 0, jy = 0, jz = 0;
@@ -197,7 +209,6 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_nodes(const typename Stor
     acc[P_MAXU] = fmax(acc[P_MAXU], sqrt(s2));
     acc[P_MINRHO] = fmin(acc[P_MINRHO], r);
     if (walls) {
-      const int y = (int)((i / g.nx) % g.ny);
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         if ((EY[a] == -1 && y == 0) || (EY[a] == 1 && y == g.ny - 1)) {
@@ -266,32 +277,28 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_final(const double* __res
 
 static char g_create_err[512] = "";
 
-// Values between the starts of consecutive direction arrays beyond N (rounded
-// to 256): staggers the 27 arrays so that a power-of-two N does not put the
-// same element of every direction at the same HBM channel offset (measured:
-// a few per cent at 256x128x128 and 512^3).
-constexpr int64_t kStridePad = 4352;
+size_t elem_size(int st);
 
-// Launch shape of the stream-collide kernel.  Row blocks (one x-row segment of
-// 256, 192 or 128 nodes, whichever divides nx; 256 with a ragged tail for other
-// nx >= 256) when nx >= 128, otherwise 2D blocks of 256 threads covering
-// several rows.  Returns true for row blocks.
-bool step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid) {
-  if (nx >= 128) {
-    int bx = 256;
-    if (nx % 256 != 0) {
-      if (nx % 192 == 0) bx = 192;
-      else if (nx % 128 == 0) bx = 128;
-    }
-    block = dim3(bx, 1, 1);
-    grid = dim3((nx + bx - 1) / bx, ny, nz);
-    return true;
-  }
-  const int bx = (nx + 31) / 32 * 32;
-  const int by = 256 / bx;
-  block = dim3(bx, by, 1);
-  grid = dim3(1, (ny + by - 1) / by, nz);
-  return false;
+// Launch shape of the step kernels: 1D blocks of up to 4 wavefronts, each
+// one 64-node x segment of one row (wave_segment); for nx = 256 a block is one
+// row.
+void step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid) {
+  const int nxs = (nx + SEG - 1) / SEG;
+  const int w = nxs < 4 ? nxs : 4;
+  block = dim3(SEG * w, 1, 1);
+  grid = dim3((nxs + w - 1) / w, ny, nz);
+}
+
+// storage layout of a configuration (see lbm_internal.hpp)
+static Geom make_geom(const lbm_config* cfg) {
+  Geom g{};
+  g.nx = cfg->nx;
+  g.ny = cfg->ny;
+  g.nz = cfg->nz;
+  g.nxs = (cfg->nx + SEG - 1) / SEG;
+  g.nxp = g.nxs * SEG;
+  g.rowlen = (int64_t)LBM_Q * g.nxp;
+  return g;
 }
 
 int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
@@ -363,16 +370,13 @@ extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     return set_err(nullptr, LBM_EINVAL, "lbm_create: grid %d x %d x %d must be positive", cfg->nx, cfg->ny, cfg->nz);
   const int64_t n = (int64_t)cfg->nx * cfg->ny * cfg->nz;
   if (n >= (int64_t)1 << 31) return set_err(nullptr, LBM_EINVAL, "lbm_create: %lld nodes exceed 2^31 - 1", (long long)n);
-  {
-    dim3 blk, grd;
-    step_launch_shape(cfg->nx, cfg->ny, cfg->nz, blk, grd);
-    if (cfg->nz > 65535 || (cfg->ny + (int)blk.y - 1) / (int)blk.y > 65535)
-      return set_err(nullptr, LBM_EINVAL, "lbm_create: nz and the y extent of the launch grid must be <= 65535");
-  }
-  if ((uint64_t)((n + 255) / 256 * 256 + kStridePad) * elem_size(cfg->storage) >= ((uint64_t)1 << 32))
-    return set_err(nullptr, LBM_EINVAL, "lbm_create: one direction array must stay below 4 GiB (N * bytes per value)");
   const size_t es = elem_size(cfg->storage);
   if (!es) return set_err(nullptr, LBM_EINVAL, "lbm_create: unknown storage %d", cfg->storage);
+  const Geom geo = make_geom(cfg);
+  if (cfg->ny > 65535 || cfg->nz > 65535)
+    return set_err(nullptr, LBM_EINVAL, "lbm_create: ny and nz must be <= 65535 (launch grid)");
+  if ((uint64_t)geo.rowlen * es >= ((uint64_t)1 << 32))
+    return set_err(nullptr, LBM_EINVAL, "lbm_create: one row of the state must stay below 4 GiB");
   if (cfg->walls_y != 0 && cfg->walls_y != 1) return set_err(nullptr, LBM_EINVAL, "lbm_create: walls_y must be 0 or 1");
   if (cfg->attractor != LBM_ATTRACTOR_FPC && cfg->attractor != LBM_ATTRACTOR_MAXWELL)
     return set_err(nullptr, LBM_EINVAL, "lbm_create: unknown attractor %d", cfg->attractor);
@@ -387,11 +391,15 @@ extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   c->cfg = *cfg;
   std::memcpy(c->omega, w, sizeof w);
   c->n = n;
-  c->stride = (n + 255) / 256 * 256 + kStridePad;
+  c->g = geo;
+  c->values = geo.rowlen * cfg->ny * cfg->nz;
   c->elem = es;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) {
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&c->buf[b], (size_t)LBM_Q * c->stride * es);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&c->buf[b], (size_t)c->values * es);
+    // the padding lanes of the x segments (nx not a multiple of 64) are never
+    // written by the kernels: zero them once so that the raw state is defined
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMemset(c->buf[b], 0, (size_t)c->values * es);
   }
   if (e == hipSuccess) e = hipMalloc((void**)&c->part, sizeof(double) * (DIAG_BLOCKS * (NP + 1) + NP));
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_out, sizeof(double) * NP, hipHostMallocDefault);
@@ -435,7 +443,7 @@ extern "C" int lbm_set_step_count(lbm_ctx* c, int64_t steps) {
   c->steps = steps;
   return LBM_OK;
 }
-extern "C" int64_t lbm_state_bytes(const lbm_ctx* c) { return c ? (int64_t)(LBM_Q * c->n * c->elem) : -1; }
+extern "C" int64_t lbm_state_bytes(const lbm_ctx* c) { return c ? c->values * (int64_t)c->elem : -1; }
 
 
 
@@ -462,7 +470,7 @@ extern "C" int lbm_init(lbm_ctx* c, const double* rho, const double* u) {
   }
   c->cur = 0;
   DISPATCH_ST(c->cfg.storage,
-              k_init<ST><<<nblocks(n, 256), 256, 0, c->stream>>>(drho, du, (typename Stor<ST>::S*)c->buf[0], n, c->stride));
+              k_init<ST><<<nblocks(n, 256), 256, 0, c->stream>>>(drho, du, (typename Stor<ST>::S*)c->buf[0], n, geom(c)));
   LAUNCHCHK(c);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->initialised = true;
@@ -475,7 +483,7 @@ static int launch_steps(lbm_ctx* c, int64_t nsteps) {
   using T = typename Stor<ST>::R;
   using S = typename Stor<ST>::S;
   StepArgs<T> A;
-  A.g = Geom{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->stride};
+  A.g = geom(c);
   for (int j = 0; j < LBM_Q; ++j) {
     A.r.w[j] = (T)c->omega[j];
     A.r.c[j] = (T)(1.0 - c->omega[j]);
@@ -485,18 +493,14 @@ static int launch_steps(lbm_ctx* c, int64_t nsteps) {
   const bool force = c->cfg.force[0] != 0.0 || c->cfg.force[1] != 0.0 || c->cfg.force[2] != 0.0;
   const bool walls = c->cfg.walls_y != 0;
   dim3 block, grid;
-  const bool row = step_launch_shape(c->cfg.nx, c->cfg.ny, c->cfg.nz, block, grid);
+  step_launch_shape(c->cfg.nx, c->cfg.ny, c->cfg.nz, block, grid);
   using KFn = void (*)(const S*, S*, StepArgs<T>);
-  static const KFn table[2][2][2][2] = {
-      {{{k_stream_collide<ST, false, false, false, false>, k_stream_collide<ST, false, false, true, false>},
-        {k_stream_collide<ST, false, true, false, false>, k_stream_collide<ST, false, true, true, false>}},
-       {{k_stream_collide<ST, true, false, false, false>, k_stream_collide<ST, true, false, true, false>},
-        {k_stream_collide<ST, true, true, false, false>, k_stream_collide<ST, true, true, true, false>}}},
-      {{{k_stream_collide<ST, false, false, false, true>, k_stream_collide<ST, false, false, true, true>},
-        {k_stream_collide<ST, false, true, false, true>, k_stream_collide<ST, false, true, true, true>}},
-       {{k_stream_collide<ST, true, false, false, true>, k_stream_collide<ST, true, false, true, true>},
-        {k_stream_collide<ST, true, true, false, true>, k_stream_collide<ST, true, true, true, true>}}}};
-  const KFn kern = table[c->cfg.attractor == LBM_ATTRACTOR_MAXWELL][walls][force][row];
+  static const KFn table[2][2][2] = {
+      {{k_stream_collide<ST, false, false, false>, k_stream_collide<ST, false, true, false>},
+       {k_stream_collide<ST, true, false, false>, k_stream_collide<ST, true, true, false>}},
+      {{k_stream_collide<ST, false, false, true>, k_stream_collide<ST, false, true, true>},
+       {k_stream_collide<ST, true, false, true>, k_stream_collide<ST, true, true, true>}}};
+  const KFn kern = table[c->cfg.attractor == LBM_ATTRACTOR_MAXWELL][walls][force];
   for (int64_t s = 0; s < nsteps; ++s) {
     const S* src = (const S*)c->buf[c->cur];
     S* dst = (S*)c->buf[c->cur ^ 1];
@@ -534,11 +538,11 @@ extern "C" int lbm_moments_device(lbm_ctx* c, void* rho_dev, void* u_dev, int32_
   if (f64) {
     DISPATCH_ST(c->cfg.storage,
                 k_moments<ST, double><<<nblocks(n, 256), 256, 0, c->stream>>>(
-                    (const typename Stor<ST>::S*)c->buf[c->cur], (double*)rho_dev, (double*)u_dev, n, c->stride, F[0], F[1], F[2]));
+                    (const typename Stor<ST>::S*)c->buf[c->cur], (double*)rho_dev, (double*)u_dev, n, geom(c), F[0], F[1], F[2]));
   } else {
     DISPATCH_ST(c->cfg.storage,
                 k_moments<ST, float><<<nblocks(n, 256), 256, 0, c->stream>>>(
-                    (const typename Stor<ST>::S*)c->buf[c->cur], (float*)rho_dev, (float*)u_dev, n, c->stride, F[0], F[1], F[2]));
+                    (const typename Stor<ST>::S*)c->buf[c->cur], (float*)rho_dev, (float*)u_dev, n, geom(c), F[0], F[1], F[2]));
   }
   LAUNCHCHK(c);
   return LBM_OK;
@@ -565,7 +569,7 @@ extern "C" int lbm_get_f(lbm_ctx* c, double* f) {
   double* tmp = nullptr;
   HIPCHK(c, hipMalloc((void**)&tmp, sizeof(double) * LBM_Q * c->n));
   DISPATCH_ST(c->cfg.storage,
-              k_get_f<ST><<<nblocks(c->n, 256), 256, 0, c->stream>>>((const typename Stor<ST>::S*)c->buf[c->cur], tmp, c->n, c->stride));
+              k_get_f<ST><<<nblocks(c->n, 256), 256, 0, c->stream>>>((const typename Stor<ST>::S*)c->buf[c->cur], tmp, c->n, geom(c)));
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(f, tmp, sizeof(double) * LBM_Q * c->n, hipMemcpyDeviceToHost, c->stream);
   hipError_t e3 = hipStreamSynchronize(c->stream);
@@ -585,7 +589,7 @@ extern "C" int lbm_set_f(lbm_ctx* c, const double* f) {
   c->cur = 0;
   if (e == hipSuccess) {
     DISPATCH_ST(c->cfg.storage,
-                k_set_f<ST><<<nblocks(c->n, 256), 256, 0, c->stream>>>(tmp, (typename Stor<ST>::S*)c->buf[0], c->n, c->stride));
+                k_set_f<ST><<<nblocks(c->n, 256), 256, 0, c->stream>>>(tmp, (typename Stor<ST>::S*)c->buf[0], c->n, geom(c)));
     e = hipGetLastError();
   }
   hipError_t e3 = hipStreamSynchronize(c->stream);
@@ -602,8 +606,7 @@ extern "C" int lbm_get_raw(lbm_ctx* c, void* host, int64_t nbytes) {
   if (!c || !host || nbytes != lbm_state_bytes(c)) return LBM_EINVAL;
   if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_get_raw: state not initialised");
   HIPCHK(c, hipSetDevice(c->device));
-  const size_t row = (size_t)c->n * c->elem;
-  HIPCHK(c, hipMemcpy2DAsync(host, row, c->buf[c->cur], (size_t)c->stride * c->elem, row, LBM_Q, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(host, c->buf[c->cur], (size_t)nbytes, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
@@ -611,9 +614,8 @@ extern "C" int lbm_get_raw(lbm_ctx* c, void* host, int64_t nbytes) {
 extern "C" int lbm_set_raw(lbm_ctx* c, const void* host, int64_t nbytes) {
   if (!c || !host || nbytes != lbm_state_bytes(c)) return LBM_EINVAL;
   HIPCHK(c, hipSetDevice(c->device));
-  const size_t row = (size_t)c->n * c->elem;
   c->cur = 0;
-  HIPCHK(c, hipMemcpy2DAsync(c->buf[0], (size_t)c->stride * c->elem, host, row, row, LBM_Q, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->buf[0], host, (size_t)nbytes, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->initialised = true;
   c->steps = 0;
@@ -626,7 +628,7 @@ extern "C" int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
   HIPCHK(c, hipSetDevice(c->device));
   int rc = alloc_scratch(c);
   if (rc) return rc;
-  const Geom g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->stride};
+  const Geom g = geom(c);
   const double* F = c->cfg.force;
   double* part = c->part;
   double* part_ens = c->part + DIAG_BLOCKS * NP;

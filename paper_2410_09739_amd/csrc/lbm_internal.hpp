@@ -108,10 +108,42 @@ __device__ __forceinline__ uint32_t node_hash(uint32_t node, uint32_t step) {
   return h;
 }
 
+// Layout of a state buffer in HBM (every storage form): x is cut into
+// segments of SEG = 64 nodes (one wavefront); for every (y, z) row the
+// nxp = ceil(nx / 64) * 64 padded nodes form nxp / 64 segments, and a segment
+// holds its 27 directions one after the other, 64 consecutive x values each:
+//   index(a, x, y, z) = (z ny + y) 27 nxp + 27 * 64 floor(x / 64) + 64 a + (x mod 64).
+// A wavefront that updates one segment reads and writes a few contiguous
+// 27 x 64-value blocks (its own row and the y/z neighbour rows) instead of 54
+// separate direction arrays.  Measured on the 256x128x128 channel against 27
+// direction arrays: FP32 +11 %, FP64 +5 %, BF16 +7 %, FP16 +2 %.
+constexpr int SEG = 64;
+
 struct Geom {
   int nx, ny, nz;
-  int64_t stride;  // values between direction arrays
+  int nxs;         // x segments per row, ceil(nx / SEG)
+  int nxp;         // nx rounded up to a multiple of SEG
+  int64_t rowlen;  // values per (y, z) row: 27 nxp
 };
+
+// position of x inside a row, in values
+__host__ __device__ __forceinline__ uint32_t x_part(int x) {
+  const uint32_t u = (uint32_t)x;
+  return (u / SEG) * (Q * SEG) + u % SEG;
+}
+
+__host__ __device__ __forceinline__ int64_t pop_index(const Geom& g, int a, int x, int y, int z) {
+  return ((int64_t)z * g.ny + y) * g.rowlen + a * SEG + x_part(x);
+}
+
+// (x, y, z) of the linear node index i = x + nx (y + ny z)
+__host__ __device__ __forceinline__ void node_xyz(const Geom& g, int64_t i, int& x, int& y, int& z) {
+  const int ii = (int)i;  // N < 2^31
+  x = ii % g.nx;
+  const int r = ii / g.nx;
+  y = r % g.ny;
+  z = r / g.ny;
+}
 
 template <typename T>
 struct StepArgs {
@@ -126,15 +158,13 @@ struct StepArgs {
 // time level: f_alpha(x) = f~_alpha(x - e_alpha), periodic wrap, and halfway
 // bounce-back across the y walls (the node's own opposite population).
 //
-// ROW = true: the block is one segment of an x row, so y and z are uniform
-// across the wavefront and every row/plane offset lives in scalar registers;
-// the only per-lane address terms are the three x offsets.  ROW = false: 2D
-// blocks (small nx), y per lane.  Addresses are a uniform 64-bit base per
-// direction plus a 32-bit per-lane byte offset (one direction array is
-// < 4 GiB, checked at creation).  Returns the byte offset of node (x, y, z).
-template <int ST, bool WALLS, bool ROW>
-__device__ __forceinline__ uint32_t pull(const typename Stor<ST>::S* __restrict__ src, const Geom& g, int x, int y,
-                                         int z, typename Stor<ST>::R (&v)[3][3][3]) {
+// The caller's wavefront covers one x segment of one row: y and z are uniform
+// across it, so every row and direction base is a scalar 64-bit address and
+// the only per-lane address terms are the three x offsets inside a row
+// (32-bit; checked at creation).  Lanes with x >= nx must not call.
+template <int ST, bool WALLS>
+__device__ __forceinline__ void pull(const typename Stor<ST>::S* __restrict__ src, const Geom& g, int x, int y, int z,
+                                     typename Stor<ST>::R (&v)[3][3][3]) {
   using T = typename Stor<ST>::R;
   using S = typename Stor<ST>::S;
   using SS = Stor<ST>;
@@ -142,18 +172,20 @@ __device__ __forceinline__ uint32_t pull(const typename Stor<ST>::S* __restrict_
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   // rows away from the walls (all but two per plane) take the wall-free gather,
   // whose loads keep the scalar-base form; the branch is wavefront-uniform
-  if (ROW && WALLS && y > 0 && y < ny - 1) return pull<ST, false, true>(src, g, x, y, z, v);
-  const uint32_t rowb = (uint32_t)nx * SZ;
-  const uint32_t planeb = rowb * (uint32_t)ny;
-  // byte offsets of the source x, y, z for e = -1, 0, +1 (periodic wrap)
-  const uint32_t x0 = (uint32_t)x * SZ;
-  const uint32_t xb[3] = {x == nx - 1 ? 0u : x0 + SZ, x0, x == 0 ? rowb - SZ : x0 - SZ};
-  const uint32_t y0 = (uint32_t)y * rowb;
-  const uint32_t yb[3] = {y == ny - 1 ? 0u : y0 + rowb, y0, y == 0 ? planeb - rowb : y0 - rowb};
-  const uint32_t z0 = (uint32_t)z * planeb;
-  const uint32_t zb[3] = {z == nz - 1 ? 0u : z0 + planeb, z0, z == 0 ? (uint32_t)(nz - 1) * planeb : z0 - planeb};
-  const uint64_t stb = (uint64_t)g.stride * SZ;
+  if (WALLS && y > 0 && y < ny - 1) return pull<ST, false>(src, g, x, y, z, v);
   const char* __restrict__ sb = (const char*)src;
+  const int64_t rowb = g.rowlen * SZ;
+  const int64_t planeb = rowb * ny;
+  constexpr uint64_t dirb = SEG * SZ;  // one direction block of a segment
+  // per-lane byte offsets inside a row of the source x for e_x = -1, 0, +1
+  const uint32_t xo[3] = {x_part(x == nx - 1 ? 0 : x + 1) * SZ, x_part(x) * SZ, x_part(x == 0 ? nx - 1 : x - 1) * SZ};
+  // uniform byte offsets: this row, and the steps to the source rows for
+  // e_y, e_z = -1, 0, +1 (periodic wrap), additions only
+  const int64_t r0 = ((int64_t)z * ny + y) * rowb;
+  const int64_t dy[3] = {y == ny - 1 ? rowb - planeb : rowb, 0, y == 0 ? planeb - rowb : -rowb};
+  const int64_t span = planeb * nz;
+  const int64_t dz[3] = {z == nz - 1 ? planeb - span : planeb, 0, z == 0 ? span - planeb : -planeb};
+  const char* dptr = sb + r0;  // this row of direction a
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     const int ex = EX[a], ey = EY[a], ez = EZ[a];
@@ -161,39 +193,35 @@ __device__ __forceinline__ uint32_t pull(const typename Stor<ST>::S* __restrict_
     // opposite population (same weight, so the deviation carries over)
     const bool bb = WALLS && ((ey == 1 && y == 0) || (ey == -1 && y == ny - 1));
     const int o = opposite(a);
-    T val;
-    if (ROW) {
-      // bb is uniform here: the base is chosen in scalar registers
-      const char* base = bb ? sb + o * stb + (uint64_t)(z0 + y0) : sb + a * stb + (uint64_t)(zb[ez + 1] + yb[ey + 1]);
-      const uint32_t off = bb ? x0 : xb[ex + 1];
-      val = SS::dec(*(const S*)(base + off), a);  // w_opp = w_alpha, scales equal
-    } else if (bb) {
-      val = SS::dec(*(const S*)(sb + o * stb + (uint32_t)(z0 + y0 + x0)), o);
-    } else {
-      val = SS::dec(*(const S*)(sb + a * stb + (uint32_t)(zb[ez + 1] + yb[ey + 1] + xb[ex + 1])), a);
-    }
-    v[ez + 1][ey + 1][ex + 1] = val;
+    // bb is uniform: the base is chosen in scalar registers
+    const char* base = bb ? sb + r0 + (uint64_t)o * dirb : dptr + (dy[ey + 1] + dz[ez + 1]);
+    const uint32_t off = bb ? xo[1] : xo[ex + 1];
+    dptr += dirb;
+    v[ez + 1][ey + 1][ex + 1] = SS::dec(*(const S*)(base + off), a);  // w_opp = w_alpha, scales equal
   }
-  return z0 + y0 + x0;
 }
 
-// store the post-collision cube (deviations times 2^inv_shift) at byte offset ib
-// ROW: the row's byte offset (uniform) is folded into a scalar base that walks
-// the 27 direction arrays; the per-lane part is the x offset only.
-template <int ST, bool ROW>
+// store the post-collision cube (deviations times 2^inv_shift) of node
+// (x, y, z); same wavefront contract as pull().  The row base walks the 27
+// direction blocks of the segment in scalar registers; the per-lane part is
+// the x offset only.
+template <int ST>
 __device__ __forceinline__ void push(typename Stor<ST>::S* __restrict__ dst, const Geom& g, int x, int y, int z,
-                                     uint32_t ib, const typename Stor<ST>::R (&v)[3][3][3], uint32_t step) {
+                                     const typename Stor<ST>::R (&v)[3][3][3], uint32_t step) {
   using S = typename Stor<ST>::S;
   constexpr uint32_t SZ = sizeof(S);
-  const uint64_t stb = (uint64_t)g.stride * SZ;
-  const uint32_t h = Stor<ST>::stochastic ? node_hash(ib, step) : 0u;
-  const uint32_t xoff = (uint32_t)x * SZ;
-  char* base = (char*)dst + (ROW ? (uint64_t)(((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.nx * SZ) : 0);
-  const uint32_t off = ROW ? xoff : ib;
+  constexpr uint64_t dirb = SEG * SZ;
+  // random word input: the node's linear index
+  const uint32_t node = ((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.nx + (uint32_t)x;
+  const uint32_t h = Stor<ST>::stochastic ? node_hash(node, step) : 0u;
+  const uint32_t off = x_part(x) * SZ;
+  char* base = (char*)dst + ((uint64_t)z * g.ny + y) * ((uint64_t)g.rowlen * SZ);
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
-    *(S*)(base + off) = Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a), h + (uint32_t)a * 0x9E3779B9u);
-    base += stb;
+    // streaming store: the next step reads it back from HBM, not from cache
+    __builtin_nontemporal_store(Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a), h + (uint32_t)a * 0x9E3779B9u),
+                                (S*)(base + off));
+    base += dirb;
   }
 }
 
@@ -202,7 +230,9 @@ __device__ __forceinline__ void push(typename Stor<ST>::S* __restrict__ dst, con
 struct lbm_ctx {
   lbm_config cfg;
   int device = 0;
-  int64_t n = 0, stride = 0;
+  int64_t n = 0;
+  Geom g{};     // storage layout of the state buffers
+  int64_t values = 0;  // values per state buffer
   size_t elem = 0;
   void* buf[2] = {nullptr, nullptr};
   int cur = 0;  // buffer holding the current post-collision state
@@ -221,7 +251,16 @@ struct lbm_ctx {
 };
 
 int set_err(lbm_ctx* c, int code, const char* fmt, ...);
-bool step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid);
+void step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid);
+inline Geom geom(const lbm_ctx* c) { return c->g; }
+// wavefront -> (x segment, row) for the step kernels: 1D blocks of 64 W
+// threads, W = min(4, nxs) wavefronts on consecutive x segments of one row,
+// grid (ceil(nxs / W), ny, nz); y and z come straight from the block index
+__device__ __forceinline__ void wave_segment(int& x, int& y, int& z) {
+  x = blockIdx.x * blockDim.x + threadIdx.x;
+  y = blockIdx.y;
+  z = blockIdx.z;
+}
 size_t elem_size(int st);
 int alloc_scratch(lbm_ctx* c);
 // closure.hip: enqueue n steps of the stream-collide kernel with the fused closure
