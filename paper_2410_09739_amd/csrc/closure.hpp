@@ -23,6 +23,7 @@
 #include <cstdint>
 
 #include "d3q27.hpp"
+#include "fpc_collide.hpp"
 
 namespace fpc {
 namespace cl {
@@ -63,7 +64,7 @@ __device__ __forceinline__ void features(const T (&v)[3][3][3], T rhop, T rho, f
                               {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 2, 0}, {1, 0, 2}, {2, 1, 0}, {0, 1, 2},
                               {2, 0, 1}, {0, 2, 1}, {1, 1, 1}, {2, 2, 0}, {2, 0, 2}, {0, 2, 2}, {2, 1, 1},
                               {1, 2, 1}, {1, 1, 2}, {1, 2, 2}, {2, 1, 2}, {2, 2, 1}, {2, 2, 2}};
-  const T ir = T(1) / rho;
+  const T ir = recip(rho);
   x[0] = (float)rhop;
 #pragma unroll
   for (int k = 1; k < NIN; ++k) {
@@ -100,12 +101,25 @@ __device__ __forceinline__ bf16x8 load_afrag(const char* w, int f, int lane) {
   return *(const bf16x8*)(w + (f * 64 + lane) * 16);
 }
 
-// elements 8 q' .. 8 q' + 7 of an accumulator block, ReLU'd, as a B fragment
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// elements 8 q' .. 8 q' + 7 of an accumulator block, ReLU'd, as a B fragment.
+// Rounding to bf16 (nearest even) and ReLU commute for finite values, so each
+// pair is converted with one packed conversion and the ReLU is a packed signed
+// 16-bit max with 0 on the bf16 bit patterns (negative values, -0 included,
+// have the sign bit).
 __device__ __forceinline__ bf16x8 relu_bf16(const f32x16& acc, int qp) {
-  bf16x8 r;
+  u32x4 w;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) r[i] = (__bf16)fmaxf(acc[8 * qp + i], 0.0f);
-  return r;
+  for (int i = 0; i < 4; ++i) {
+    const f32x2 f = {acc[8 * qp + 2 * i], acc[8 * qp + 2 * i + 1]};
+    const bf16x2 p = __builtin_convertvector(f, bf16x2);
+    w[i] = __builtin_bit_cast(unsigned, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), s16x2{0, 0}));
+  }
+  return __builtin_bit_cast(bf16x8, w);
 }
 
 // Evaluate the MLP for the 64 nodes of the calling wavefront.  Every lane of
