@@ -60,16 +60,18 @@ def _load():
         lib.orc_attractor.restype = ctypes.c_double
         lib.orc_init.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, _dp]
         lib.orc_collide.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, _dp, _dp, ctypes.c_int]
-        lib.orc_stream.argtypes = [ctypes.c_int] * 4 + [_dp, _dp]
-        lib.orc_run.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, ctypes.c_int, ctypes.c_int]
+        lib.orc_stream.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp]
+        lib.orc_run.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int]
         lib.orc_run.restype = ctypes.c_int
         lib.orc_num_threads.restype = ctypes.c_int
-        lib.orc_step_nodes.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, _i64p, ctypes.c_int64, _dp, ctypes.c_int]
+        lib.orc_step_nodes.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, _dp, _i64p, ctypes.c_int64, _dp, ctypes.c_int]
         _lib = lib
     return _lib
 
 
-def _d(a: np.ndarray):
+def _d(a):
+    if a is None:
+        return None
     assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(_dp)
 
@@ -177,37 +179,51 @@ def collide(f: np.ndarray, omega, force=(0.0, 0.0, 0.0), attractor: str = "fpc")
     return g
 
 
-def stream(g: np.ndarray, walls_y: bool = False) -> np.ndarray:
+def _walls(walls_y: bool, walls) -> int:
+    """Wall mask (reading R23): 1 = y faces, 2 = x faces, 4 = z faces.  ``walls``
+    overrides ``walls_y`` when given (a mask or a string of axes, e.g. "xyz")."""
+    if walls is None:
+        return 1 if walls_y else 0
+    if isinstance(walls, str):
+        return sum({"y": 1, "x": 2, "z": 4}[c] for c in walls)
+    return int(walls)
+
+
+def _lid(lid):
+    return None if lid is None else _f64(lid)
+
+
+def stream(g: np.ndarray, walls_y: bool = False, walls=None, lid=None) -> np.ndarray:
     lib = _load()
     g = _f64(g)
     _, nz, ny, nx = g.shape
     f = np.zeros_like(g)
-    lib.orc_stream(nx, ny, nz, int(bool(walls_y)), _d(g), _d(f))
+    lib.orc_stream(nx, ny, nz, _walls(walls_y, walls), _d(_lid(lid)), _d(g), _d(f))
     return f
 
 
 def run(g: np.ndarray, omega, force=(0.0, 0.0, 0.0), walls_y: bool = False, steps: int = 1,
-        attractor: str = "fpc") -> np.ndarray:
+        attractor: str = "fpc", walls=None, lid=None) -> np.ndarray:
     """``steps`` full time steps (stream, then collide) from a post-collision state."""
     lib = _load()
     g = _f64(g).copy()
     _, nz, ny, nx = g.shape
-    rc = lib.orc_run(nx, ny, nz, int(bool(walls_y)), _d(_f64(omega)), _d(_f64(force)), _d(g), int(steps),
-                     _model(attractor))
+    rc = lib.orc_run(nx, ny, nz, _walls(walls_y, walls), _d(_lid(lid)), _d(_f64(omega)), _d(_f64(force)), _d(g),
+                     int(steps), _model(attractor))
     if rc != 0:
         raise MemoryError("oracle run failed")
     return g
 
 
 def step_nodes(g: np.ndarray, sel, omega, force=(0.0, 0.0, 0.0), walls_y: bool = False,
-               attractor: str = "fpc") -> np.ndarray:
+               attractor: str = "fpc", walls=None, lid=None) -> np.ndarray:
     """One step evaluated at the flat node indices ``sel`` only; returns [27, len(sel)]."""
     lib = _load()
     g = _f64(g)
     _, nz, ny, nx = g.shape
     sel = np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
     out = np.zeros((Q, sel.size))
-    lib.orc_step_nodes(nx, ny, nz, int(bool(walls_y)), _d(_f64(omega)), _d(_f64(force)), _d(g),
+    lib.orc_step_nodes(nx, ny, nz, _walls(walls_y, walls), _d(_lid(lid)), _d(_f64(omega)), _d(_f64(force)), _d(g),
                        sel.ctypes.data_as(_i64p), sel.size, _d(out), _model(attractor))
     return out
 

@@ -37,6 +37,12 @@
  *   R11 third-order attractors are zero, as printed.
  *   R12 halfway bounce-back (pull form): if the upstream node x - e_alpha is a
  *       wall node, f_alpha(x, t+1) = f~_opp(alpha)(x, t).
+ *   R23 walls: bit 0 of `walls` = halfway bounce-back walls half a link outside
+ *       y = 0 and y = ny-1 (R12), bit 1 the same across x, bit 2 across z (the
+ *       cubic cavity of Sec. 4 uses all six).  A moving wall above y = ny-1
+ *       (velocity `lid`, Sec. 4 lid-driven cavity) adds the momentum
+ *       correction 2 w_a rho_w (e_a . U) / c_s^2 with rho_w = 1 to every link
+ *       that crosses it, corner and edge links included.
  *   R22 the comparison model with Maxwellian equilibria (MCM-LBM, Sec. 4, the
  *       doubly periodic shear layer and crossing shear wave studies) relaxes
  *       every non-conserved central moment to the discrete Maxwellian's,
@@ -414,41 +420,65 @@ void orc_collide(int nx, int ny, int nz, const double* f, double* g, const doubl
   }
 }
 
-/* Streaming, Eq. (LBMsteps-stream) / Appendix D Step 6, pull form:
- * f_alpha(x) = g_alpha(x - e_alpha).  Periodic in x and z; periodic in y when
- * walls_y == 0, otherwise halfway bounce-back walls half a link outside the
- * layers y = 0 and y = ny-1 (reading R12). */
-void orc_stream(int nx, int ny, int nz, int walls_y, const double* g, double* f) {
+/* rest weights w_a = f^eq(1, 0), for the moving-wall correction */
+static double WREST[Q];
+static int wrest_ready = 0;
+static void setup_wrest(void) {
+  if (wrest_ready) return;
+  const double zero[3] = {0.0, 0.0, 0.0};
+  orc_feq(1.0, zero, WREST);
+  wrest_ready = 1;
+}
+
+/* Streaming, Eq. (LBMsteps-stream) / Appendix D Step 6, pull form, at node i:
+ * fi[a] = g_a(x - e_a), periodic wrap across the faces without walls,
+ * halfway bounce-back across the faces with walls (readings R12, R23). */
+static void pull_node(int nx, int ny, int nz, int walls, const double* lid, const double* g, int64_t i,
+                      double* fi) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+  for (int a = 0; a < Q; ++a) {
+    int xs = x - EX[a], ys = y - EY[a], zs = z - EZ[a];
+    const int outx = (walls & 2) && (xs < 0 || xs >= nx);
+    const int outy = (walls & 1) && (ys < 0 || ys >= ny);
+    const int outz = (walls & 4) && (zs < 0 || zs >= nz);
+    if (outx || outy || outz) {
+      double v = g[OPP[a] * N + i];
+      if (lid && (walls & 1) && ys >= ny)
+        v += 2.0 * WREST[a] * (EX[a] * lid[0] + EY[a] * lid[1] + EZ[a] * lid[2]) / CS2;
+      fi[a] = v;
+      continue;
+    }
+    xs = (xs % nx + nx) % nx;
+    ys = (ys % ny + ny) % ny;
+    zs = (zs % nz + nz) % nz;
+    fi[a] = g[a * N + (xs + (int64_t)nx * (ys + (int64_t)ny * zs))];
+  }
+}
+
+void orc_stream(int nx, int ny, int nz, int walls, const double* lid, const double* g, double* f) {
   setup();
+  setup_wrest();
   const int64_t N = (int64_t)nx * ny * nz;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i) {
-    const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
-    for (int a = 0; a < Q; ++a) {
-      const int xs = ((x - EX[a]) % nx + nx) % nx;
-      const int zs = ((z - EZ[a]) % nz + nz) % nz;
-      int ys = y - EY[a];
-      if (walls_y && (ys < 0 || ys >= ny)) {
-        f[a * N + i] = g[OPP[a] * N + i];
-        continue;
-      }
-      ys = (ys % ny + ny) % ny;
-      f[a * N + i] = g[a * N + (xs + (int64_t)nx * (ys + (int64_t)ny * zs))];
-    }
+    double fi[Q];
+    pull_node(nx, ny, nz, walls, lid, g, i, fi);
+    for (int a = 0; a < Q; ++a) f[a * N + i] = fi[a];
   }
 }
 
 /* nsteps of: stream, then collide (one full time step in the paper's order,
  * seen from the post-collision state).  g holds the post-collision state on
  * entry and on exit. */
-int orc_run(int nx, int ny, int nz, int walls_y, const double* omega, const double* F, double* g,
+int orc_run(int nx, int ny, int nz, int walls, const double* lid, const double* omega, const double* F, double* g,
             int nsteps, int model) {
   setup();
   const int64_t N = (int64_t)nx * ny * nz;
   double* f = (double*)malloc(sizeof(double) * Q * N);
   if (!f) return -1;
   for (int s = 0; s < nsteps; ++s) {
-    orc_stream(nx, ny, nz, walls_y, g, f);
+    orc_stream(nx, ny, nz, walls, lid, g, f);
     orc_collide(nx, ny, nz, f, g, omega, F, model);
   }
   free(f);
@@ -457,26 +487,14 @@ int orc_run(int nx, int ny, int nz, int walls_y, const double* omega, const doub
 
 /* One step (stream then collide) evaluated only at the listed nodes, reading
  * the full post-collision state g; out is [27][nsel]. */
-void orc_step_nodes(int nx, int ny, int nz, int walls_y, const double* omega, const double* F,
+void orc_step_nodes(int nx, int ny, int nz, int walls, const double* lid, const double* omega, const double* F,
                     const double* g, const int64_t* sel, int64_t nsel, double* out, int model) {
   setup();
-  const int64_t N = (int64_t)nx * ny * nz;
+  setup_wrest();
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < nsel; ++s) {
-    const int64_t i = sel[s];
-    const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
     double fi[Q], fo[Q];
-    for (int a = 0; a < Q; ++a) {
-      const int xs = ((x - EX[a]) % nx + nx) % nx;
-      const int zs = ((z - EZ[a]) % nz + nz) % nz;
-      int ys = y - EY[a];
-      if (walls_y && (ys < 0 || ys >= ny)) {
-        fi[a] = g[OPP[a] * N + i];
-        continue;
-      }
-      ys = (ys % ny + ny) % ny;
-      fi[a] = g[a * N + (xs + (int64_t)nx * (ys + (int64_t)ny * zs))];
-    }
+    pull_node(nx, ny, nz, walls, lid, g, sel[s], fi);
     orc_collide_node(fi, omega, F, fo, NULL, NULL, model);
     for (int a = 0; a < Q; ++a) out[a * nsel + s] = fo[a];
   }

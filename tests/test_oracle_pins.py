@@ -498,3 +498,54 @@ def test_crossing_shear_waves_show_hyperviscosity_only_with_maxwellian_attractor
     assert rate_mcm > 1000 * exact
     assert rate_mcm > 50 * rate_fpc
     assert abs(a_fpc[1] - 1.0) < 0.02 and a_mcm[1] < 0.92
+
+
+# ------------------------------------------------------------------ walls on every face, moving lid
+@pytest.mark.parametrize("nu", [0.1, 0.02])
+def test_moving_wall_bounce_back_gives_exact_plane_couette_flow(nu):
+    """Sec. 4 cavity boundary (reading R23): halfway bounce-back with the
+    moving-wall momentum correction.  Between a resting wall half a link below
+    y = 0 and a wall moving at U half a link above y = ny - 1 the steady
+    solution is u_x = U (y + 1/2) / ny, which the scheme reproduces to
+    rounding."""
+    nx, ny, nz, U = 2, 8, 2, 0.02
+    g = O.init(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
+    g = O.run(g, O.omega_table(nu), walls="y", lid=(U, 0, 0), steps=int(12 * ny * ny / nu))
+    _, u = O.macroscopic(g)
+    exact = U * (np.arange(ny) + 0.5) / ny
+    np.testing.assert_allclose(u[0], np.broadcast_to(exact[None, :, None], u[0].shape), rtol=0, atol=1e-12 * U)
+    assert np.abs(u[1]).max() < 1e-14 and np.abs(u[2]).max() < 1e-14
+
+
+def _cavity(n, lid, steps, nu=0.05):
+    g = O.init(np.ones((n, n, n)), np.zeros((3, n, n, n)))
+    return O.run(g, O.omega_table(nu), walls="xyz", lid=lid, steps=steps)
+
+
+def test_lid_driven_cavity_is_mirror_symmetric_and_keeps_mass():
+    """Cubic cavity with the lid moving along x: the flow is symmetric under
+    z -> nz - 1 - z (u_z odd), and a tangential lid changes no mass."""
+    n, U = 8, 0.05
+    g = _cavity(n, (U, 0, 0), 150)
+    rho, u = O.macroscopic(g)
+    m = rho[::-1]
+    np.testing.assert_allclose(rho, m, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(u[0], u[0][::-1], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(u[1], u[1][::-1], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(u[2], -u[2][::-1], rtol=0, atol=1e-15)
+    assert rho.sum() == pytest.approx(n ** 3, rel=1e-13)
+    assert u[0][:, -1].mean() > 0.1 * U  # the lid drives the top layer
+
+
+def test_lid_driven_cavity_rotates_with_the_lid_direction():
+    """The lid moving along z gives the x <-> z mirror image of the lid moving
+    along x (walls on every face, cubic box): checks the x- and z-wall paths
+    against each other."""
+    n, U = 7, 0.05
+    rx, ux = O.macroscopic(_cavity(n, (U, 0, 0), 60))
+    rz, uz = O.macroscopic(_cavity(n, (0, 0, U), 60))
+    sw = lambda a: np.swapaxes(a, 0, 2)  # [z, y, x] -> [x, y, z]
+    np.testing.assert_allclose(rz, sw(rx), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(uz[2], sw(ux[0]), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(uz[0], sw(ux[2]), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(uz[1], sw(ux[1]), rtol=0, atol=1e-15)
