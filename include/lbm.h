@@ -114,6 +114,12 @@ typedef struct {
   double force[3];      /* body force per unit volume, lattice units, dt = 1    */
   void* hip_stream;     /* hipStream_t to run on; NULL: the library makes one   */
   int32_t attractor;    /* lbm_attractor (default LBM_ATTRACTOR_FPC)            */
+  int32_t walls_x;      /* 0: periodic in x; 1: halfway bounce-back walls half a */
+  int32_t walls_z;      /*   link outside the first and last layer (same for z)  */
+  double lid_velocity[3]; /* velocity of the wall above y = ny-1 (needs walls_y; */
+                        /* Sec. 4 lid-driven cavity): every link through it gets */
+                        /* the momentum correction 2 w_a (e_a . U) / c_s^2;      */
+                        /* zeros = resting wall.  Not with the learned closure.  */
 } lbm_config;
 
 typedef struct {
@@ -134,7 +140,7 @@ typedef struct lbm_ctx lbm_ctx;
 
 /* Fills cfg with defaults: 0 sizes, LBM_F32, periodic, LBM_OMEGA_PAPER,
  * nu = 1/6, omega_bulk = omega_higher = 1, zero force, NULL stream,
- * LBM_ATTRACTOR_FPC. */
+ * LBM_ATTRACTOR_FPC, no x/z walls, resting walls. */
 void lbm_config_default(lbm_config* cfg);
 
 /* Host-only: the 27 rates the configuration implies (no GPU needed).

@@ -580,6 +580,8 @@ extern "C" int lbm_set_closure(lbm_ctx* c, const float* params) {
     return set_err(c, LBM_EINVAL, "lbm_set_closure: nx must be a multiple of 64 (one wavefront per row segment)");
   if (params && c->cfg.attractor != LBM_ATTRACTOR_FPC)
     return set_err(c, LBM_EINVAL, "lbm_set_closure: the closure runs with the FPC attractors only");
+  if (params && bc_kind(c) == 2)
+    return set_err(c, LBM_EINVAL, "lbm_set_closure: the closure supports periodic and y-wall lattices only");
   for (int p = 0; p < NPARAM; ++p)
     if (!std::isfinite(params[p])) return set_err(c, LBM_EINVAL, "lbm_set_closure: parameter %d is not finite", p);
   std::vector<char> packed;
@@ -594,6 +596,8 @@ extern "C" int lbm_set_closure(lbm_ctx* c, const float* params) {
 extern "C" int lbm_closure_features(lbm_ctx* c, float* x_dev) {
   if (!c || !x_dev) return LBM_EINVAL;
   if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_closure_features: state not initialised");
+  if (bc_kind(c) == 2)
+    return set_err(c, LBM_EINVAL, "lbm_closure_features: periodic and y-wall lattices only");
   HIPCHK(c, hipSetDevice(c->device));
   const bool walls = c->cfg.walls_y != 0;
   const bool force = c->cfg.force[0] != 0.0 || c->cfg.force[1] != 0.0 || c->cfg.force[2] != 0.0;

@@ -23,7 +23,9 @@
 // ===========================================================================
 // fused stream + collide (plain method)
 // Block (64, 4): each wavefront is one x segment of one row (y, z uniform).
-template <int ST, bool WALLS, bool FORCE, bool MAXWELL>
+// BC: 0 periodic, 1 walls across y (the channel), 2 walls on any faces and a
+// moving lid (StepArgs::box).
+template <int ST, int BC, bool FORCE, bool MAXWELL>
 __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>::S* __restrict__ src,
                                                         typename Stor<ST>::S* __restrict__ dst,
                                                         StepArgs<typename Stor<ST>::R> A) {
@@ -32,7 +34,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>:
   wave_segment(x, y, z);
   if (x >= A.g.nx) return;
   T v[3][3][3];
-  pull<ST, WALLS>(src, A.g, x, y, z, v);
+  if (BC == 2) pull_box<ST>(src, A.g, A.box, x, y, z, v);
+  else pull<ST, BC == 1>(src, A.g, x, y, z, v);
   const T ws[6] = {A.r.w[4], A.r.w[5], A.r.w[6], A.r.w[7], A.r.w[8], A.r.w[9]};
   const T cs[6] = {A.r.c[4], A.r.c[5], A.r.c[6], A.r.c[7], A.r.c[8], A.r.c[9]};
   T rho, ux, uy, uz;
@@ -224,7 +227,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_nodes(const typename Stor
 }
 
 // 1/2 |curl u|^2 with centred differences; periodic, or an antisymmetric
-// ghost layer across the half-link walls (u = 0 at the wall).
+// ghost layer across the half-link walls (u = 0 at the wall).  walls: wall
+// mask (1 = y, 2 = x, 4 = z).
 __global__ __launch_bounds__(DIAG_THREADS) void k_diag_enstrophy(const double* __restrict__ u, double* __restrict__ part,
                                                                  Geom g, int walls) {
   const int64_t n = (int64_t)g.nx * g.ny * g.nz;
@@ -233,21 +237,29 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_enstrophy(const double* _
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   for (int64_t i = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x; i < n; i += (int64_t)DIAG_BLOCKS * DIAG_THREADS) {
     const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
-    const int xp = x == nx - 1 ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
-    const int zp = z == nz - 1 ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
+    int xp = x == nx - 1 ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+    int zp = z == nz - 1 ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
     int yp = y == ny - 1 ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
-    double sgp = 1.0, sgm = 1.0;
-    if (walls) {
-      if (y == ny - 1) { yp = y; sgp = -1.0; }
-      if (y == 0) { ym = y; sgm = -1.0; }
+    double sxp = 1.0, sxm = 1.0, syp = 1.0, sym = 1.0, szp = 1.0, szm = 1.0;
+    if (walls & 1) {
+      if (y == ny - 1) { yp = y; syp = -1.0; }
+      if (y == 0) { ym = y; sym = -1.0; }
+    }
+    if (walls & 2) {
+      if (x == nx - 1) { xp = x; sxp = -1.0; }
+      if (x == 0) { xm = x; sxm = -1.0; }
+    }
+    if (walls & 4) {
+      if (z == nz - 1) { zp = z; szp = -1.0; }
+      if (z == 0) { zm = z; szm = -1.0; }
     }
     auto at = [&](int c, int xx, int yy, int zz) { return u[(int64_t)c * n + ((int64_t)zz * ny + yy) * nx + xx]; };
-    const double dwy_dx = 0.5 * (at(2, xp, y, z) - at(2, xm, y, z));  // d uz / dx
-    const double dvy_dz = 0.5 * (at(1, x, y, zp) - at(1, x, y, zm));  // d uy / dz
-    const double duz_dy = 0.5 * (sgp * at(2, x, yp, z) - sgm * at(2, x, ym, z));
-    const double dux_dy = 0.5 * (sgp * at(0, x, yp, z) - sgm * at(0, x, ym, z));
-    const double dux_dz = 0.5 * (at(0, x, y, zp) - at(0, x, y, zm));
-    const double duy_dx = 0.5 * (at(1, xp, y, z) - at(1, xm, y, z));
+    const double dwy_dx = 0.5 * (sxp * at(2, xp, y, z) - sxm * at(2, xm, y, z));  // d uz / dx
+    const double dvy_dz = 0.5 * (szp * at(1, x, y, zp) - szm * at(1, x, y, zm));  // d uy / dz
+    const double duz_dy = 0.5 * (syp * at(2, x, yp, z) - sym * at(2, x, ym, z));
+    const double dux_dy = 0.5 * (syp * at(0, x, yp, z) - sym * at(0, x, ym, z));
+    const double dux_dz = 0.5 * (szp * at(0, x, y, zp) - szm * at(0, x, y, zm));
+    const double duy_dx = 0.5 * (sxp * at(1, xp, y, z) - sxm * at(1, xm, y, z));
     const double wx = duz_dy - dvy_dz, wy = dux_dz - dwy_dx, wz = duy_dx - dux_dy;
     acc[0] += 0.5 * (wx * wx + wy * wy + wz * wz);
   }
@@ -378,6 +390,12 @@ extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   if ((uint64_t)geo.rowlen * es >= ((uint64_t)1 << 32))
     return set_err(nullptr, LBM_EINVAL, "lbm_create: one row of the state must stay below 4 GiB");
   if (cfg->walls_y != 0 && cfg->walls_y != 1) return set_err(nullptr, LBM_EINVAL, "lbm_create: walls_y must be 0 or 1");
+  if ((cfg->walls_x != 0 && cfg->walls_x != 1) || (cfg->walls_z != 0 && cfg->walls_z != 1))
+    return set_err(nullptr, LBM_EINVAL, "lbm_create: walls_x and walls_z must be 0 or 1");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(cfg->lid_velocity[d])) return set_err(nullptr, LBM_EINVAL, "lbm_create: non-finite lid velocity");
+  if ((cfg->lid_velocity[0] != 0.0 || cfg->lid_velocity[1] != 0.0 || cfg->lid_velocity[2] != 0.0) && !cfg->walls_y)
+    return set_err(nullptr, LBM_EINVAL, "lbm_create: a moving lid needs walls_y = 1");
   if (cfg->attractor != LBM_ATTRACTOR_FPC && cfg->attractor != LBM_ATTRACTOR_MAXWELL)
     return set_err(nullptr, LBM_EINVAL, "lbm_create: unknown attractor %d", cfg->attractor);
   for (int d = 0; d < 3; ++d)
@@ -490,17 +508,19 @@ static int launch_steps(lbm_ctx* c, int64_t nsteps) {
     A.r.h[j] = (T)(1.0 - 0.5 * c->omega[j]);
   }
   for (int d = 0; d < 3; ++d) A.F[d] = (T)c->cfg.force[d];
+  A.box = box_args<T>(c);
   const bool force = c->cfg.force[0] != 0.0 || c->cfg.force[1] != 0.0 || c->cfg.force[2] != 0.0;
-  const bool walls = c->cfg.walls_y != 0;
   dim3 block, grid;
   step_launch_shape(c->cfg.nx, c->cfg.ny, c->cfg.nz, block, grid);
   using KFn = void (*)(const S*, S*, StepArgs<T>);
-  static const KFn table[2][2][2] = {
-      {{k_stream_collide<ST, false, false, false>, k_stream_collide<ST, false, true, false>},
-       {k_stream_collide<ST, true, false, false>, k_stream_collide<ST, true, true, false>}},
-      {{k_stream_collide<ST, false, false, true>, k_stream_collide<ST, false, true, true>},
-       {k_stream_collide<ST, true, false, true>, k_stream_collide<ST, true, true, true>}}};
-  const KFn kern = table[c->cfg.attractor == LBM_ATTRACTOR_MAXWELL][walls][force];
+  static const KFn table[2][3][2] = {
+      {{k_stream_collide<ST, 0, false, false>, k_stream_collide<ST, 0, true, false>},
+       {k_stream_collide<ST, 1, false, false>, k_stream_collide<ST, 1, true, false>},
+       {k_stream_collide<ST, 2, false, false>, k_stream_collide<ST, 2, true, false>}},
+      {{k_stream_collide<ST, 0, false, true>, k_stream_collide<ST, 0, true, true>},
+       {k_stream_collide<ST, 1, false, true>, k_stream_collide<ST, 1, true, true>},
+       {k_stream_collide<ST, 2, false, true>, k_stream_collide<ST, 2, true, true>}}};
+  const KFn kern = table[c->cfg.attractor == LBM_ATTRACTOR_MAXWELL][bc_kind(c)][force];
   for (int64_t s = 0; s < nsteps; ++s) {
     const S* src = (const S*)c->buf[c->cur];
     S* dst = (S*)c->buf[c->cur ^ 1];
@@ -637,7 +657,7 @@ extern "C" int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
               k_diag_nodes<ST><<<DIAG_BLOCKS, DIAG_THREADS, 0, c->stream>>>(
                   (const typename Stor<ST>::S*)c->buf[c->cur], c->scratch, part, g, c->cfg.walls_y, F[0], F[1], F[2]));
   LAUNCHCHK(c);
-  k_diag_enstrophy<<<DIAG_BLOCKS, DIAG_THREADS, 0, c->stream>>>(c->scratch, part_ens, g, c->cfg.walls_y);
+  k_diag_enstrophy<<<DIAG_BLOCKS, DIAG_THREADS, 0, c->stream>>>(c->scratch, part_ens, g, wall_mask(c));
   LAUNCHCHK(c);
   k_diag_final<<<1, DIAG_THREADS, 0, c->stream>>>(part, part_ens, dout);
   LAUNCHCHK(c);

@@ -145,12 +145,21 @@ __host__ __device__ __forceinline__ void node_xyz(const Geom& g, int64_t i, int&
   z = r / g.ny;
 }
 
+// walls on any face and a moving lid (the general boundary kernel)
+template <typename T>
+struct Box {
+  int wx, wy, wz;  // halfway bounce-back walls across x / y / z
+  int lid_on;      // the wall above y = ny - 1 moves with lid[]
+  T lid6[3];       // 6 U = 2 U / c_s^2 (momentum correction per unit weight)
+};
+
 template <typename T>
 struct StepArgs {
   Geom g;
   Rates<T> r;
   T F[3];
   uint32_t step;  // completed steps before this one (random words of SR storage)
+  Box<T> box;
 };
 
 // ===========================================================================
@@ -198,6 +207,57 @@ __device__ __forceinline__ void pull(const typename Stor<ST>::S* __restrict__ sr
     const uint32_t off = bb ? xo[1] : xo[ex + 1];
     dptr += dirb;
     v[ez + 1][ey + 1][ex + 1] = SS::dec(*(const S*)(base + off), a);  // w_opp = w_alpha, scales equal
+  }
+}
+
+// Gather with walls on any set of faces and an optional moving lid above
+// y = ny - 1 (the cavity of Sec. 4).  A link whose source lies outside a
+// walled face takes the node's own opposite population (halfway
+// bounce-back); a link through the lid adds the moving-wall correction
+// 2 w_a rho_w (e_a . U) / c_s^2 with rho_w = 1.  y and z walls are
+// wavefront-uniform; x walls touch only the first and last lane of a row, so
+// those lanes reload their own opposite population.  Wavefronts away from
+// every wall take the wall-free gather.
+template <int ST>
+__device__ __forceinline__ void pull_box(const typename Stor<ST>::S* __restrict__ src, const Geom& g,
+                                         const Box<typename Stor<ST>::R>& b, int x, int y, int z,
+                                         typename Stor<ST>::R (&v)[3][3][3]) {
+  using T = typename Stor<ST>::R;
+  using S = typename Stor<ST>::S;
+  using SS = Stor<ST>;
+  constexpr uint32_t SZ = sizeof(S);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int x0 = __builtin_amdgcn_readfirstlane(x - (x % SEG));  // first x of the segment
+  const bool yin = !b.wy || (y > 0 && y < ny - 1);
+  const bool zin = !b.wz || (z > 0 && z < nz - 1);
+  const bool xin = !b.wx || (x0 > 0 && x0 + SEG < nx);
+  if (yin && zin && xin) return pull<ST, false>(src, g, x, y, z, v);
+  const char* __restrict__ sb = (const char*)src;
+  const int64_t rowb = g.rowlen * SZ;
+  const int64_t planeb = rowb * ny;
+  constexpr uint64_t dirb = SEG * SZ;
+  const uint32_t xo[3] = {x_part(x == nx - 1 ? 0 : x + 1) * SZ, x_part(x) * SZ, x_part(x == 0 ? nx - 1 : x - 1) * SZ};
+  const int64_t r0 = ((int64_t)z * ny + y) * rowb;
+  const int64_t dy[3] = {y == ny - 1 ? rowb - planeb : rowb, 0, y == 0 ? planeb - rowb : -rowb};
+  const int64_t span = planeb * nz;
+  const int64_t dz[3] = {z == nz - 1 ? planeb - span : planeb, 0, z == 0 ? span - planeb : -planeb};
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const int ex = EX[a], ey = EY[a], ez = EZ[a];
+    const int o = opposite(a);
+    const bool top = ey == -1 && y == ny - 1;
+    const bool bby = b.wy && ((ey == 1 && y == 0) || top);
+    const bool bbz = b.wz && ((ez == 1 && z == 0) || (ez == -1 && z == nz - 1));
+    T val;
+    if (bby || bbz) {  // uniform
+      val = SS::dec(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
+      if (b.lid_on && b.wy && top) val += T(weight(a)) * (ex * b.lid6[0] + ey * b.lid6[1] + ez * b.lid6[2]);
+    } else {
+      val = SS::dec(*(const S*)(sb + r0 + (uint64_t)a * dirb + (dy[ey + 1] + dz[ez + 1]) + xo[ex + 1]), a);
+      if (b.wx && ex != 0 && ((ex == 1 && x == 0) || (ex == -1 && x == nx - 1)))  // per lane
+        val = SS::dec(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
+    }
+    v[ez + 1][ey + 1][ex + 1] = val;
   }
 }
 
@@ -253,6 +313,26 @@ struct lbm_ctx {
 int set_err(lbm_ctx* c, int code, const char* fmt, ...);
 void step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid);
 inline Geom geom(const lbm_ctx* c) { return c->g; }
+inline bool has_lid(const lbm_ctx* c) {
+  return c->cfg.lid_velocity[0] != 0.0 || c->cfg.lid_velocity[1] != 0.0 || c->cfg.lid_velocity[2] != 0.0;
+}
+// boundary kernel: 0 periodic, 1 walls across y only, 2 walls on any faces / moving lid
+inline int bc_kind(const lbm_ctx* c) {
+  if (c->cfg.walls_x || c->cfg.walls_z || has_lid(c)) return 2;
+  return c->cfg.walls_y ? 1 : 0;
+}
+template <typename T>
+inline Box<T> box_args(const lbm_ctx* c) {
+  Box<T> b;
+  b.wx = c->cfg.walls_x;
+  b.wy = c->cfg.walls_y;
+  b.wz = c->cfg.walls_z;
+  b.lid_on = has_lid(c) ? 1 : 0;
+  for (int d = 0; d < 3; ++d) b.lid6[d] = (T)(6.0 * c->cfg.lid_velocity[d]);
+  return b;
+}
+// wall mask of the diagnostics: 1 = y, 2 = x, 4 = z
+inline int wall_mask(const lbm_ctx* c) { return (c->cfg.walls_y ? 1 : 0) | (c->cfg.walls_x ? 2 : 0) | (c->cfg.walls_z ? 4 : 0); }
 // wavefront -> (x segment, row) for the step kernels: 1D blocks of 64 W
 // threads, W = min(4, nxs) wavefronts on consecutive x segments of one row,
 // grid (ceil(nxs / W), ny, nz); y and z come straight from the block index

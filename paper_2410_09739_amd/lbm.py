@@ -39,6 +39,7 @@ class lbm_config(ctypes.Structure):
         ("nu", ctypes.c_double), ("omega_bulk", ctypes.c_double), ("omega_higher", ctypes.c_double),
         ("omega", ctypes.c_double * Q), ("force", ctypes.c_double * 3),
         ("hip_stream", ctypes.c_void_p), ("attractor", ctypes.c_int32),
+        ("walls_x", ctypes.c_int32), ("walls_z", ctypes.c_int32), ("lid_velocity", ctypes.c_double * 3),
     ]
 
 
@@ -249,6 +250,9 @@ class Config:
     force: Sequence[float] = (0.0, 0.0, 0.0)
     hip_stream: Optional[int] = None
     attractor: str = "fpc"
+    walls_x: bool = False
+    walls_z: bool = False
+    lid_velocity: Sequence[float] = (0.0, 0.0, 0.0)
 
     def to_c(self) -> lbm_config:
         c = lbm_config_default()
@@ -266,6 +270,10 @@ class Config:
             c.force[d] = float(self.force[d])
         c.hip_stream = self.hip_stream
         c.attractor = ATTRACTOR[self.attractor]
+        c.walls_x = int(bool(self.walls_x))
+        c.walls_z = int(bool(self.walls_z))
+        for d in range(3):
+            c.lid_velocity[d] = float(self.lid_velocity[d])
         return c
 
 
