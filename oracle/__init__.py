@@ -180,12 +180,14 @@ def collide(f: np.ndarray, omega, force=(0.0, 0.0, 0.0), attractor: str = "fpc")
 
 
 def _walls(walls_y: bool, walls) -> int:
-    """Wall mask (reading R23): 1 = y faces, 2 = x faces, 4 = z faces.  ``walls``
-    overrides ``walls_y`` when given (a mask or a string of axes, e.g. "xyz")."""
+    """Wall mask (readings R23, R24): 1 = y faces, 2 = x faces, 4 = z faces,
+    8 = the face above y = ny - 1 is a specular symmetry plane.  ``walls``
+    overrides ``walls_y`` when given (a mask or a string: "x", "y", "z" walls,
+    "s" symmetry plane on top, e.g. "ys" for the half channel)."""
     if walls is None:
         return 1 if walls_y else 0
     if isinstance(walls, str):
-        return sum({"y": 1, "x": 2, "z": 4}[c] for c in walls)
+        return sum({"y": 1, "x": 2, "z": 4, "s": 8}[c] for c in walls)
     return int(walls)
 
 

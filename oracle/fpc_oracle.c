@@ -43,6 +43,10 @@
  *       (velocity `lid`, Sec. 4 lid-driven cavity) adds the momentum
  *       correction 2 w_a rho_w (e_a . U) / c_s^2 with rho_w = 1 to every link
  *       that crosses it, corner and edge links included.
+ *   R24 bit 3 of `walls` turns the face above y = ny-1 into the specular
+ *       (mirror) symmetry plane of the Sec. 4 half channel: a link crossing it
+ *       takes the population that left the tangentially shifted node
+ *       (x - e_x, ny-1, z - e_z) with the mirrored velocity (e_x, -e_y, e_z).
  *   R22 the comparison model with Maxwellian equilibria (MCM-LBM, Sec. 4, the
  *       doubly periodic shear layer and crossing shear wave studies) relaxes
  *       every non-conserved central moment to the discrete Maxwellian's,
@@ -442,6 +446,15 @@ static void pull_node(int nx, int ny, int nz, int walls, const double* lid, cons
     const int outx = (walls & 2) && (xs < 0 || xs >= nx);
     const int outy = (walls & 1) && (ys < 0 || ys >= ny);
     const int outz = (walls & 4) && (zs < 0 || zs >= nz);
+    if (outy && (walls & 8) && ys >= ny && !outx && !outz) {
+      /* specular reflection at the symmetry plane (reading R24) */
+      const int xm = (xs % nx + nx) % nx, zm = (zs % nz + nz) % nz;
+      int am = 0;
+      for (int b = 0; b < Q; ++b)
+        if (EX[b] == EX[a] && EY[b] == -EY[a] && EZ[b] == EZ[a]) am = b;
+      fi[a] = g[am * N + (xm + (int64_t)nx * (y + (int64_t)ny * zm))];
+      continue;
+    }
     if (outx || outy || outz) {
       double v = g[OPP[a] * N + i];
       if (lid && (walls & 1) && ys >= ny)

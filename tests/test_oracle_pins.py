@@ -549,3 +549,22 @@ def test_lid_driven_cavity_rotates_with_the_lid_direction():
     np.testing.assert_allclose(uz[2], sw(ux[0]), rtol=0, atol=1e-15)
     np.testing.assert_allclose(uz[0], sw(ux[2]), rtol=0, atol=1e-15)
     np.testing.assert_allclose(uz[1], sw(ux[1]), rtol=0, atol=1e-15)
+
+
+def test_specular_symmetry_plane_reproduces_the_lower_half_of_the_full_channel():
+    """Sec. 4 half channel (reading R24): a wall below y = 0 and a specular
+    symmetry plane above y = H - 1 evolve exactly like the lower half of the
+    full channel of height 2H with walls on both sides, started from a state
+    that is mirror-symmetric about the mid-plane (equivariance of the
+    collision under the y mirror, exact to rounding)."""
+    nx, H, nz = 6, 5, 4
+    e, _, _ = O.lattice()
+    mir = np.array([np.where((e[:, 0] == a[0]) & (e[:, 1] == -a[1]) & (e[:, 2] == a[2]))[0][0] for a in e])
+    half = O.feq(1.0, (0.0, 0.0, 0.0))[:, None, None, None] * W.random_factors((27, nz, H, nx), seed=8, amplitude=0.2)
+    full = np.concatenate([half, half[mir][:, :, ::-1, :]], axis=2)
+    om = O.omega_table(0.03)
+    F = (2e-5, 0.0, 1e-5)
+    gh = O.run(half, om, F, walls="ys", steps=6)
+    gf = O.run(full, om, F, walls="y", steps=6)
+    np.testing.assert_allclose(gh, gf[:, :, :H, :], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(gf[:, :, H:, :], gf[mir][:, :, H - 1::-1, :], rtol=0, atol=1e-15)
