@@ -52,19 +52,19 @@ def _load():
     if _lib is None:
         build()
         lib = ctypes.CDLL(_LIB_PATH)
-        lib.orc_collide_node.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
+        lib.orc_collide_node.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_double]
         lib.orc_feq.argtypes = [ctypes.c_double, _dp, _dp]
         lib.orc_lattice.argtypes = [_ip, _ip, _ip, _ip, _ip]
         lib.orc_matrices.argtypes = [_dp, _dp, _dp, _dp, _dp]
         lib.orc_attractor.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
         lib.orc_attractor.restype = ctypes.c_double
         lib.orc_init.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, _dp]
-        lib.orc_collide.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, _dp, _dp, ctypes.c_int]
+        lib.orc_collide.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
         lib.orc_stream.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp]
-        lib.orc_run.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int]
+        lib.orc_run.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
         lib.orc_run.restype = ctypes.c_int
         lib.orc_num_threads.restype = ctypes.c_int
-        lib.orc_step_nodes.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, _dp, _i64p, ctypes.c_int64, _dp, ctypes.c_int]
+        lib.orc_step_nodes.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, _dp, _i64p, ctypes.c_int64, _dp, ctypes.c_int, _dp]
         _lib = lib
     return _lib
 
@@ -142,12 +142,15 @@ def _model(attractor: str) -> int:
     return {"fpc": 0, "maxwell": 1}[attractor]
 
 
-def collide_node(f, omega, force=(0.0, 0.0, 0.0), return_moments: bool = False, attractor: str = "fpc"):
-    """Appendix D Steps 1-5 at one node (27 populations in, 27 out)."""
+def collide_node(f, omega, force=(0.0, 0.0, 0.0), return_moments: bool = False, attractor: str = "fpc",
+                 les_cd: float = 0.0):
+    """Appendix D Steps 1-5 at one node (27 populations in, 27 out).  les_cd:
+    the Smagorinsky factor C D of reading R25 at this node (0: no LES)."""
     lib = _load()
     f = _f64(f)
     ft, kpre, kpost = np.zeros(Q), np.zeros(Q), np.zeros(Q)
-    lib.orc_collide_node(_d(f), _d(_f64(omega)), _d(_f64(force)), _d(ft), _d(kpre), _d(kpost), _model(attractor))
+    lib.orc_collide_node(_d(f), _d(_f64(omega)), _d(_f64(force)), _d(ft), _d(kpre), _d(kpost), _model(attractor),
+                         float(les_cd))
     return (ft, kpre, kpost) if return_moments else ft
 
 
@@ -170,12 +173,19 @@ def init(rho: np.ndarray, u: np.ndarray) -> np.ndarray:
     return f
 
 
-def collide(f: np.ndarray, omega, force=(0.0, 0.0, 0.0), attractor: str = "fpc") -> np.ndarray:
+def _les(les):
+    """les = (C_s, u_tau / nu, A+) of reading R25, or None."""
+    return None if les is None else _f64(les)
+
+
+def collide(f: np.ndarray, omega, force=(0.0, 0.0, 0.0), attractor: str = "fpc", walls_y: bool = False,
+            walls=None, les=None) -> np.ndarray:
     lib = _load()
     f = _f64(f)
     _, nz, ny, nx = f.shape
     g = np.zeros_like(f)
-    lib.orc_collide(nx, ny, nz, _d(f), _d(g), _d(_f64(omega)), _d(_f64(force)), _model(attractor))
+    lib.orc_collide(nx, ny, nz, _d(f), _d(g), _d(_f64(omega)), _d(_f64(force)), _model(attractor),
+                    _walls(walls_y, walls), _d(_les(les)))
     return g
 
 
@@ -205,20 +215,20 @@ def stream(g: np.ndarray, walls_y: bool = False, walls=None, lid=None) -> np.nda
 
 
 def run(g: np.ndarray, omega, force=(0.0, 0.0, 0.0), walls_y: bool = False, steps: int = 1,
-        attractor: str = "fpc", walls=None, lid=None) -> np.ndarray:
+        attractor: str = "fpc", walls=None, lid=None, les=None) -> np.ndarray:
     """``steps`` full time steps (stream, then collide) from a post-collision state."""
     lib = _load()
     g = _f64(g).copy()
     _, nz, ny, nx = g.shape
     rc = lib.orc_run(nx, ny, nz, _walls(walls_y, walls), _d(_lid(lid)), _d(_f64(omega)), _d(_f64(force)), _d(g),
-                     int(steps), _model(attractor))
+                     int(steps), _model(attractor), _d(_les(les)))
     if rc != 0:
         raise MemoryError("oracle run failed")
     return g
 
 
 def step_nodes(g: np.ndarray, sel, omega, force=(0.0, 0.0, 0.0), walls_y: bool = False,
-               attractor: str = "fpc", walls=None, lid=None) -> np.ndarray:
+               attractor: str = "fpc", walls=None, lid=None, les=None) -> np.ndarray:
     """One step evaluated at the flat node indices ``sel`` only; returns [27, len(sel)]."""
     lib = _load()
     g = _f64(g)
@@ -226,7 +236,7 @@ def step_nodes(g: np.ndarray, sel, omega, force=(0.0, 0.0, 0.0), walls_y: bool =
     sel = np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
     out = np.zeros((Q, sel.size))
     lib.orc_step_nodes(nx, ny, nz, _walls(walls_y, walls), _d(_lid(lid)), _d(_f64(omega)), _d(_f64(force)), _d(g),
-                       sel.ctypes.data_as(_i64p), sel.size, _d(out), _model(attractor))
+                       sel.ctypes.data_as(_i64p), sel.size, _d(out), _model(attractor), _d(_les(les)))
     return out
 
 

@@ -47,6 +47,15 @@
  *       (mirror) symmetry plane of the Sec. 4 half channel: a link crossing it
  *       takes the population that left the tangentially shifted node
  *       (x - e_x, ny-1, z - e_z) with the mirrored velocity (e_x, -e_y, e_z).
+ *   R25 the LES of the Sec. 4 half channel (Smagorinsky with van Driest
+ *       damping): per node nu_t = (C D)^2 |S|, D = 1 - exp(-y+ / 26), y+ the
+ *       distance to the nearest wall in wall units; |S| = sqrt(2 S_ij S_ij)
+ *       from the deviatoric non-equilibrium second-order central moments
+ *       before collision, S = -omega Pi_dev / (2 rho c_s^2), so
+ *       |S| = 3 sqrt(2) Q / (2 rho tau) with Q = |Pi_dev| (Frobenius); the
+ *       relaxation time tau = 1/omega of the shear groups (omega_4,5,6,8,9) is
+ *       the positive root of tau^2 - tau_0 tau - 9 sqrt(2) (C D)^2 Q / (2 rho);
+ *       bulk and higher rates are unchanged.
  *   R22 the comparison model with Maxwellian equilibria (MCM-LBM, Sec. 4, the
  *       doubly periodic shear layer and crossing shear wave studies) relaxes
  *       every non-conserved central moment to the discrete Maxwellian's,
@@ -211,8 +220,8 @@ static double relax(double k, double kmv, double w, double s) {
  * F: body force; model: 0 = FPC (Markovian attractors), 1 = Maxwellian
  * attractors (MCM, reading R22).  Writes f~ and optionally the pre/post
  * central moments. */
-void orc_collide_node(const double* f, const double* omega, const double* F, double* ft,
-                      double* kappa_pre, double* kappa_post, int model) {
+void orc_collide_node(const double* f, const double* omega_in, const double* F, double* ft,
+                      double* kappa_pre, double* kappa_post, int model, double les_cd) {
   setup();
   /* Step 7 definitions: rho = sum f, rho u = sum f e + F/2. */
   double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -232,6 +241,19 @@ void orc_collide_node(const double* f, const double* omega, const double* F, dou
   frame_matrix(u, Fu);
   matvec(Fu, m, k);
   if (kappa_pre) memcpy(kappa_pre, k, sizeof k);
+
+  /* LES (reading R25): shear rates from the local deviatoric stress */
+  double omega[Q];
+  memcpy(omega, omega_in, sizeof omega);
+  if (les_cd > 0.0) {
+    const double tr = (k[K200] + k[K020] + k[K002]) / 3.0;
+    const double dxx = k[K200] - tr, dyy = k[K020] - tr, dzz = k[K002] - tr;
+    const double Qs = sqrt(dxx * dxx + dyy * dyy + dzz * dzz +
+                           2.0 * (k[K110] * k[K110] + k[K101] * k[K101] + k[K011] * k[K011]));
+    const double tau0 = 1.0 / omega_in[4];
+    const double tau = 0.5 * (tau0 + sqrt(tau0 * tau0 + 18.0 * sqrt(2.0) * les_cd * les_cd * Qs / rho));
+    omega[4] = omega[5] = omega[6] = omega[8] = omega[9] = 1.0 / tau;
+  }
 
   /* Step 3 -- sources sigma_mnp, Eq. (cmupdatesourceD3Q27), reading R8. */
   double ks[Q];
@@ -411,15 +433,30 @@ void orc_init(int nx, int ny, int nz, const double* rho, const double* u, double
 }
 
 /* Collision at every node (Steps 1-5); g may alias nothing. */
+/* C D of reading R25 at layer y: les = {C_s, u_tau / nu (0: no damping), A+}
+ * or NULL; the wall distance is that to the nearest y wall (walls bit 0),
+ * the symmetry plane (bit 3) excluded. */
+static double les_cd(const double* les, int walls, int ny, int y) {
+  if (!les || les[0] <= 0.0) return 0.0;
+  double d = 1.0;
+  if ((walls & 1) && les[1] > 0.0) {
+    double yw = y + 0.5;
+    if (!(walls & 8) && ny - 0.5 - y < yw) yw = ny - 0.5 - y;
+    d = 1.0 - exp(-yw * les[1] / les[2]);
+  }
+  return les[0] * d;
+}
+
 void orc_collide(int nx, int ny, int nz, const double* f, double* g, const double* omega,
-                 const double* F, int model) {
+                 const double* F, int model, int walls, const double* les) {
   setup();
   const int64_t N = (int64_t)nx * ny * nz;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i) {
     double fi[Q], fo[Q];
     for (int a = 0; a < Q; ++a) fi[a] = f[a * N + i];
-    orc_collide_node(fi, omega, F, fo, NULL, NULL, model);
+    const int y = (int)((i / nx) % ny);
+    orc_collide_node(fi, omega, F, fo, NULL, NULL, model, les_cd(les, walls, ny, y));
     for (int a = 0; a < Q; ++a) g[a * N + i] = fo[a];
   }
 }
@@ -485,14 +522,14 @@ void orc_stream(int nx, int ny, int nz, int walls, const double* lid, const doub
  * seen from the post-collision state).  g holds the post-collision state on
  * entry and on exit. */
 int orc_run(int nx, int ny, int nz, int walls, const double* lid, const double* omega, const double* F, double* g,
-            int nsteps, int model) {
+            int nsteps, int model, const double* les) {
   setup();
   const int64_t N = (int64_t)nx * ny * nz;
   double* f = (double*)malloc(sizeof(double) * Q * N);
   if (!f) return -1;
   for (int s = 0; s < nsteps; ++s) {
     orc_stream(nx, ny, nz, walls, lid, g, f);
-    orc_collide(nx, ny, nz, f, g, omega, F, model);
+    orc_collide(nx, ny, nz, f, g, omega, F, model, walls, les);
   }
   free(f);
   return 0;
@@ -501,14 +538,15 @@ int orc_run(int nx, int ny, int nz, int walls, const double* lid, const double* 
 /* One step (stream then collide) evaluated only at the listed nodes, reading
  * the full post-collision state g; out is [27][nsel]. */
 void orc_step_nodes(int nx, int ny, int nz, int walls, const double* lid, const double* omega, const double* F,
-                    const double* g, const int64_t* sel, int64_t nsel, double* out, int model) {
+                    const double* g, const int64_t* sel, int64_t nsel, double* out, int model, const double* les) {
   setup();
   setup_wrest();
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < nsel; ++s) {
     double fi[Q], fo[Q];
     pull_node(nx, ny, nz, walls, lid, g, sel[s], fi);
-    orc_collide_node(fi, omega, F, fo, NULL, NULL, model);
+    const int y = (int)((sel[s] / nx) % ny);
+    orc_collide_node(fi, omega, F, fo, NULL, NULL, model, les_cd(les, walls, ny, y));
     for (int a = 0; a < Q; ++a) out[a * nsel + s] = fo[a];
   }
 }

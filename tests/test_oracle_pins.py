@@ -568,3 +568,31 @@ def test_specular_symmetry_plane_reproduces_the_lower_half_of_the_full_channel()
     gf = O.run(full, om, F, walls="y", steps=6)
     np.testing.assert_allclose(gh, gf[:, :, :H, :], rtol=0, atol=1e-15)
     np.testing.assert_allclose(gf[:, :, H:, :], gf[mir][:, :, H - 1::-1, :], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("damping", [False, True])
+def test_smagorinsky_les_gives_the_model_eddy_viscosity_in_channel_flow(damping):
+    """Reading R25 (Sec. 4 LES): in steady force-driven channel flow the shear
+    stress balances the force, (nu + nu_t) du/dy = F (y_c - y), and the eddy
+    viscosity the scheme develops is the model's nu_t = (C D)^2 |du/dy| with
+    the van Driest factor D = 1 - exp(-y+ / 26), y+ counted from the wall half
+    a link outside the first layer.  Checked away from the centre line (where
+    du/dy -> 0): to 3 % without damping; to 10 % with it, where D changes by a
+    factor 2 across the few layers of this 16-layer channel (a y+ offset of
+    half a layer either way is off by 15-90 %)."""
+    nx, ny, nz, nu = 2, 16, 2, 0.05
+    F = 8 * nu * 0.05 / ny ** 2
+    C, scale = 0.6, (6.0 if damping else 0.0)
+    g = O.init(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
+    g = O.run(g, O.omega_table(nu), (F, 0, 0), walls="y", steps=int(8 * ny * ny / nu), les=(C, scale, 26.0))
+    _, u = O.macroscopic(g, force=(F, 0, 0))
+    ux = u[0, 0, :, 0]
+    j = np.arange(1, ny - 1)
+    gam = (ux[2:] - ux[:-2]) / 2
+    yw = np.minimum(j + 0.5, ny - 0.5 - j)
+    D = 1 - np.exp(-yw * scale / 26.0) if damping else np.ones_like(yw)
+    nut_model = (C * D) ** 2 * np.abs(gam)
+    nut_seen = F * ((ny - 1) / 2 - j) / gam - nu
+    far = np.abs(j - (ny - 1) / 2) > ny / 4
+    assert nut_model[far].max() > 0.01 * nu
+    np.testing.assert_allclose(nut_seen[far], nut_model[far], rtol=0.10 if damping else 0.03)
