@@ -120,6 +120,14 @@ typedef struct {
                         /* Sec. 4 lid-driven cavity): every link through it gets */
                         /* the momentum correction 2 w_a (e_a . U) / c_s^2;      */
                         /* zeros = resting wall.  Not with the learned closure.  */
+  int32_t sym_top;      /* 1: the face above y = ny-1 is a specular symmetry     */
+                        /* plane (Sec. 4 half channel; needs walls_y for the     */
+                        /* wall below y = 0, no lid)                            */
+  double les_cs;        /* Smagorinsky constant C (Sec. 4 channel LES); 0 = off */
+  double les_wall_units;/* u_tau / nu for the van Driest damping                */
+                        /* D = 1 - exp(-y+ / les_aplus), y+ from the nearest y   */
+                        /* wall half a link outside; 0 = no damping (D = 1)     */
+  double les_aplus;     /* van Driest constant A+ (default 26)                  */
 } lbm_config;
 
 typedef struct {
@@ -140,7 +148,8 @@ typedef struct lbm_ctx lbm_ctx;
 
 /* Fills cfg with defaults: 0 sizes, LBM_F32, periodic, LBM_OMEGA_PAPER,
  * nu = 1/6, omega_bulk = omega_higher = 1, zero force, NULL stream,
- * LBM_ATTRACTOR_FPC, no x/z walls, resting walls. */
+ * LBM_ATTRACTOR_FPC, no x/z walls, resting walls, no symmetry plane, no LES
+ * (les_aplus = 26). */
 void lbm_config_default(lbm_config* cfg);
 
 /* Host-only: the 27 rates the configuration implies (no GPU needed).

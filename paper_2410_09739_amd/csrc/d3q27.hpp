@@ -21,6 +21,8 @@ constexpr int alpha_of(int ex, int ey, int ez) {
   return -1;
 }
 constexpr int opposite(int a) { return alpha_of(-EX[a], -EY[a], -EZ[a]); }
+// the velocity mirrored in y (specular reflection at a y = const plane)
+constexpr int mirror_y(int a) { return alpha_of(EX[a], -EY[a], EZ[a]); }
 
 // Per-axis factors of the lattice weights: w_alpha = W1[ex+1] W1[ey+1] W1[ez+1]
 // (1/6, 2/3, 1/6); with them w = 8/27, 2/27, 1/54, 1/216 by speed class.

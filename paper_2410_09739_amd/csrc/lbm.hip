@@ -36,10 +36,12 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>:
   T v[3][3][3];
   if (BC == 2) pull_box<ST>(src, A.g, A.box, x, y, z, v);
   else pull<ST, BC == 1>(src, A.g, x, y, z, v);
-  const T ws[6] = {A.r.w[4], A.r.w[5], A.r.w[6], A.r.w[7], A.r.w[8], A.r.w[9]};
-  const T cs[6] = {A.r.c[4], A.r.c[5], A.r.c[6], A.r.c[7], A.r.c[8], A.r.c[9]};
-  T rho, ux, uy, uz;
-  collide<T, FORCE, MAXWELL>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rho, ux, uy, uz);
+  T ws[6] = {A.r.w[4], A.r.w[5], A.r.w[6], A.r.w[7], A.r.w[8], A.r.w[9]};
+  T cs[6] = {A.r.c[4], A.r.c[5], A.r.c[6], A.r.c[7], A.r.c[8], A.r.c[9]};
+  T rhop, rho, ux, uy, uz;
+  pre_collision<T, FORCE>(v, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
+  if (BC == 2 && A.box.les_on) les_rates(v, rho, A.box, A.r, y, A.g.ny, ws, cs);  // uniform branch
+  relax<T, FORCE, MAXWELL>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
   push<ST>(dst, A.g, x, y, z, v, A.step);
 }
 
@@ -211,10 +213,10 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_nodes(const typename Stor
     acc[P_NONFIN] += finite ? 0.0 : 1.0;
     acc[P_MAXU] = fmax(acc[P_MAXU], sqrt(s2));
     acc[P_MINRHO] = fmin(acc[P_MINRHO], r);
-    if (walls) {
+    if (walls & 1) {
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
-        if ((EY[a] == -1 && y == 0) || (EY[a] == 1 && y == g.ny - 1)) {
+        if ((EY[a] == -1 && y == 0) || (EY[a] == 1 && y == g.ny - 1 && !(walls & 8))) {
           const double fa = weight(a) + d[a];
           acc[P_WX] += 2.0 * fa * EX[a];
           acc[P_WY] += 2.0 * fa * EY[a];
@@ -242,7 +244,9 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_enstrophy(const double* _
     int yp = y == ny - 1 ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
     double sxp = 1.0, sxm = 1.0, syp = 1.0, sym = 1.0, szp = 1.0, szm = 1.0;
     if (walls & 1) {
-      if (y == ny - 1) { yp = y; syp = -1.0; }
+      // wall: antisymmetric ghost; symmetry plane on top (walls & 8): the
+      // tangential components u_x, u_z (the only ones differentiated in y) mirror
+      if (y == ny - 1) { yp = y; syp = (walls & 8) ? 1.0 : -1.0; }
       if (y == 0) { ym = y; sym = -1.0; }
     }
     if (walls & 2) {
@@ -332,6 +336,7 @@ extern "C" void lbm_config_default(lbm_config* cfg) {
   cfg->nu = 1.0 / 6.0;
   cfg->omega_bulk = 1.0;
   cfg->omega_higher = 1.0;
+  cfg->les_aplus = 26.0;
 }
 
 // Eq. (transportcoeff3DFPCLBM): nu = c_s^2 (1/omega - 1/2), c_s^2 = 1/3.
@@ -396,6 +401,12 @@ extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     if (!std::isfinite(cfg->lid_velocity[d])) return set_err(nullptr, LBM_EINVAL, "lbm_create: non-finite lid velocity");
   if ((cfg->lid_velocity[0] != 0.0 || cfg->lid_velocity[1] != 0.0 || cfg->lid_velocity[2] != 0.0) && !cfg->walls_y)
     return set_err(nullptr, LBM_EINVAL, "lbm_create: a moving lid needs walls_y = 1");
+  if (cfg->sym_top != 0 && cfg->sym_top != 1) return set_err(nullptr, LBM_EINVAL, "lbm_create: sym_top must be 0 or 1");
+  if (cfg->sym_top && (!cfg->walls_y || cfg->lid_velocity[0] != 0.0 || cfg->lid_velocity[1] != 0.0 || cfg->lid_velocity[2] != 0.0))
+    return set_err(nullptr, LBM_EINVAL, "lbm_create: a symmetry plane needs walls_y = 1 (the wall below) and no lid");
+  if (!(cfg->les_cs >= 0.0) || !std::isfinite(cfg->les_cs) || !(cfg->les_wall_units >= 0.0) ||
+      !std::isfinite(cfg->les_wall_units) || (cfg->les_cs > 0.0 && !(cfg->les_aplus > 0.0)))
+    return set_err(nullptr, LBM_EINVAL, "lbm_create: LES needs les_cs >= 0, les_wall_units >= 0, les_aplus > 0");
   if (cfg->attractor != LBM_ATTRACTOR_FPC && cfg->attractor != LBM_ATTRACTOR_MAXWELL)
     return set_err(nullptr, LBM_EINVAL, "lbm_create: unknown attractor %d", cfg->attractor);
   for (int d = 0; d < 3; ++d)
@@ -655,7 +666,7 @@ extern "C" int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
   double* dout = part_ens + DIAG_BLOCKS;
   DISPATCH_ST(c->cfg.storage,
               k_diag_nodes<ST><<<DIAG_BLOCKS, DIAG_THREADS, 0, c->stream>>>(
-                  (const typename Stor<ST>::S*)c->buf[c->cur], c->scratch, part, g, c->cfg.walls_y, F[0], F[1], F[2]));
+                  (const typename Stor<ST>::S*)c->buf[c->cur], c->scratch, part, g, wall_mask(c), F[0], F[1], F[2]));
   LAUNCHCHK(c);
   k_diag_enstrophy<<<DIAG_BLOCKS, DIAG_THREADS, 0, c->stream>>>(c->scratch, part_ens, g, wall_mask(c));
   LAUNCHCHK(c);

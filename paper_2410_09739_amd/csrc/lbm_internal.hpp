@@ -151,6 +151,11 @@ struct Box {
   int wx, wy, wz;  // halfway bounce-back walls across x / y / z
   int lid_on;      // the wall above y = ny - 1 moves with lid[]
   T lid6[3];       // 6 U = 2 U / c_s^2 (momentum correction per unit weight)
+  int sym;         // the face above y = ny - 1 is a specular symmetry plane
+  int les_on;      // Smagorinsky LES with van Driest damping
+  T les_c;         // Smagorinsky constant C
+  T les_s;         // u_tau / nu (0: no damping)
+  T les_ia;        // 1 / A+
 };
 
 template <typename T>
@@ -246,19 +251,49 @@ __device__ __forceinline__ void pull_box(const typename Stor<ST>::S* __restrict_
     const int ex = EX[a], ey = EY[a], ez = EZ[a];
     const int o = opposite(a);
     const bool top = ey == -1 && y == ny - 1;
-    const bool bby = b.wy && ((ey == 1 && y == 0) || top);
+    const bool bby = b.wy && ((ey == 1 && y == 0) || (top && !b.sym));
     const bool bbz = b.wz && ((ez == 1 && z == 0) || (ez == -1 && z == nz - 1));
+    const bool xwall = b.wx && ex != 0 && ((ex == 1 && x == 0) || (ex == -1 && x == nx - 1));  // per lane
     T val;
-    if (bby || bbz) {  // uniform
+    if (b.sym && top && !bbz) {  // uniform: specular reflection at the symmetry plane
+      // the population that left (x - e_x, ny - 1, z - e_z) with (e_x, +1, e_z)
+      val = SS::dec(*(const S*)(sb + r0 + (uint64_t)mirror_y(a) * dirb + dz[ez + 1] + xo[ex + 1]), a);
+      if (xwall) val = SS::dec(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
+    } else if (bby || bbz) {  // uniform
       val = SS::dec(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
       if (b.lid_on && b.wy && top) val += T(weight(a)) * (ex * b.lid6[0] + ey * b.lid6[1] + ez * b.lid6[2]);
     } else {
       val = SS::dec(*(const S*)(sb + r0 + (uint64_t)a * dirb + (dy[ey + 1] + dz[ez + 1]) + xo[ex + 1]), a);
-      if (b.wx && ex != 0 && ((ex == 1 && x == 0) || (ex == -1 && x == nx - 1)))  // per lane
-        val = SS::dec(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
+      if (xwall) val = SS::dec(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
     }
     v[ez + 1][ey + 1][ex + 1] = val;
   }
+}
+
+// Smagorinsky LES with van Driest damping (the Sec. 4 channel): the shear
+// rates omega_4,5,6,8,9 of this node from its deviatoric pre-collision stress
+// Pi (v holds kappa' after pre_collision; the rest state has no deviatoric
+// part).  |S| = sqrt(2 S:S) with S = -Pi / (2 rho c_s^2 tau), so the
+// relaxation time tau = tau_0 + 3 nu_t, nu_t = (C D)^2 |S|, is the positive root
+// of tau^2 - tau_0 tau - 9 sqrt(2) (C D)^2 |Pi| / (2 rho) = 0.  D uses the
+// distance to the nearest y wall half a link outside (uniform per wavefront).
+template <typename T>
+__device__ __forceinline__ void les_rates(const T (&v)[3][3][3], T rho, const Box<T>& b, const Rates<T>& R, int y,
+                                          int ny, T (&ws)[6], T (&cs)[6]) {
+  const T k200 = v[0][0][2], k020 = v[0][2][0], k002 = v[2][0][0];
+  const T k110 = v[0][1][1], k101 = v[1][0][1], k011 = v[1][1][0];
+  const T tr = (k200 + k020 + k002) * T(1.0 / 3.0);
+  const T dxx = k200 - tr, dyy = k020 - tr, dzz = k002 - tr;
+  const T q = sqrt(dxx * dxx + dyy * dyy + dzz * dzz + T(2) * (k110 * k110 + k101 * k101 + k011 * k011));
+  T yw = T(y) + T(0.5);
+  if (!b.sym && T(ny) - T(0.5) - T(y) < yw) yw = T(ny) - T(0.5) - T(y);
+  const T d = b.les_s > T(0) ? T(1) - exp(-yw * b.les_s * b.les_ia) : T(1);
+  const T cd = b.les_c * d;
+  const T tau0 = recip(R.w[4]);
+  const T tau = T(0.5) * (tau0 + sqrt(tau0 * tau0 + T(18.0 * 1.4142135623730951) * cd * cd * q * recip(rho)));
+  const T w = recip(tau);
+  ws[0] = ws[1] = ws[2] = ws[4] = ws[5] = w;
+  cs[0] = cs[1] = cs[2] = cs[4] = cs[5] = T(1) - w;
 }
 
 // store the post-collision cube (deviations times 2^inv_shift) of node
@@ -318,7 +353,7 @@ inline bool has_lid(const lbm_ctx* c) {
 }
 // boundary kernel: 0 periodic, 1 walls across y only, 2 walls on any faces / moving lid
 inline int bc_kind(const lbm_ctx* c) {
-  if (c->cfg.walls_x || c->cfg.walls_z || has_lid(c)) return 2;
+  if (c->cfg.walls_x || c->cfg.walls_z || has_lid(c) || c->cfg.sym_top || c->cfg.les_cs > 0.0) return 2;
   return c->cfg.walls_y ? 1 : 0;
 }
 template <typename T>
@@ -329,10 +364,17 @@ inline Box<T> box_args(const lbm_ctx* c) {
   b.wz = c->cfg.walls_z;
   b.lid_on = has_lid(c) ? 1 : 0;
   for (int d = 0; d < 3; ++d) b.lid6[d] = (T)(6.0 * c->cfg.lid_velocity[d]);
+  b.sym = c->cfg.sym_top;
+  b.les_on = c->cfg.les_cs > 0.0 ? 1 : 0;
+  b.les_c = (T)c->cfg.les_cs;
+  b.les_s = (T)c->cfg.les_wall_units;
+  b.les_ia = (T)(1.0 / c->cfg.les_aplus);
   return b;
 }
-// wall mask of the diagnostics: 1 = y, 2 = x, 4 = z
-inline int wall_mask(const lbm_ctx* c) { return (c->cfg.walls_y ? 1 : 0) | (c->cfg.walls_x ? 2 : 0) | (c->cfg.walls_z ? 4 : 0); }
+// wall mask of the diagnostics: 1 = y, 2 = x, 4 = z, 8 = symmetry plane on top
+inline int wall_mask(const lbm_ctx* c) {
+  return (c->cfg.walls_y ? 1 : 0) | (c->cfg.walls_x ? 2 : 0) | (c->cfg.walls_z ? 4 : 0) | (c->cfg.sym_top ? 8 : 0);
+}
 // wavefront -> (x segment, row) for the step kernels: 1D blocks of 64 W
 // threads, W = min(4, nxs) wavefronts on consecutive x segments of one row,
 // grid (ceil(nxs / W), ny, nz); y and z come straight from the block index

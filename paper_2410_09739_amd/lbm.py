@@ -40,6 +40,8 @@ class lbm_config(ctypes.Structure):
         ("omega", ctypes.c_double * Q), ("force", ctypes.c_double * 3),
         ("hip_stream", ctypes.c_void_p), ("attractor", ctypes.c_int32),
         ("walls_x", ctypes.c_int32), ("walls_z", ctypes.c_int32), ("lid_velocity", ctypes.c_double * 3),
+        ("sym_top", ctypes.c_int32), ("les_cs", ctypes.c_double), ("les_wall_units", ctypes.c_double),
+        ("les_aplus", ctypes.c_double),
     ]
 
 
@@ -253,6 +255,10 @@ class Config:
     walls_x: bool = False
     walls_z: bool = False
     lid_velocity: Sequence[float] = (0.0, 0.0, 0.0)
+    sym_top: bool = False
+    les_cs: float = 0.0
+    les_wall_units: float = 0.0
+    les_aplus: float = 26.0
 
     def to_c(self) -> lbm_config:
         c = lbm_config_default()
@@ -274,6 +280,10 @@ class Config:
         c.walls_z = int(bool(self.walls_z))
         for d in range(3):
             c.lid_velocity[d] = float(self.lid_velocity[d])
+        c.sym_top = int(bool(self.sym_top))
+        c.les_cs = float(self.les_cs)
+        c.les_wall_units = float(self.les_wall_units)
+        c.les_aplus = float(self.les_aplus)
         return c
 
 

@@ -91,6 +91,13 @@ def test_moving_lid_needs_y_walls_and_finite_velocity():
         h = ctypes.c_void_p()
         assert lib.lbm_create(ctypes.byref(c), ctypes.byref(h)) == L.LBM_EINVAL
         assert h.value is None
+    bad = [dict(sym_top=True), dict(walls_y=True, sym_top=True, lid_velocity=(0.01, 0, 0)),
+           dict(les_cs=-0.1), dict(les_cs=0.1, les_aplus=0.0), dict(les_cs=0.1, les_wall_units=float("nan"))]
+    for kw in bad:
+        c = L.Config(8, 8, 8, nu=0.01, **kw).to_c()
+        h = ctypes.c_void_p()
+        assert lib.lbm_create(ctypes.byref(c), ctypes.byref(h)) == L.LBM_EINVAL
+        assert h.value is None
 
 
 def test_explicit_rates_are_checked():

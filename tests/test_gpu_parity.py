@@ -394,3 +394,37 @@ def test_closure_rejects_box_walls():
     with L.Lattice(L.Config(64, 4, 4, storage="f32", walls_y=True, walls_x=True)) as lat:
         with pytest.raises(L.LBMError):
             L.lbm_set_closure(lat.ctx, np.zeros(L.CLOSURE_NPARAM, dtype=np.float32))
+
+
+# ------------------------------------------------------------------ half channel: symmetry plane, LES
+@pytest.mark.parametrize("shape,walls,les", [
+    ((13, 10, 9), "ys", None),
+    ((128, 8, 3), "ys", None),                 # row blocks
+    ((70, 9, 5), "xys", None),                 # x walls meeting the symmetry plane
+    ((64, 12, 4), "ys", (0.3, 4.0, 26.0)),     # Smagorinsky with van Driest damping
+    ((13, 10, 9), "y", (0.5, 0.0, 26.0)),      # LES without damping between two walls
+])
+def test_symmetry_plane_and_les_match_oracle(shape, walls, les):
+    """The Sec. 4 half channel (readings R24, R25): a wall below y = 0, a
+    specular symmetry plane above y = ny - 1, body force, and the per-node
+    Smagorinsky rates; FP64 to 1e-12 and FP32 to the per-step bound."""
+    nx, ny, nz = shape
+    g0 = _state(shape, seed=120 + nx, amp=0.05)
+    om = O.omega_table(0.005)
+    force = (2e-5, 0.0, 0.0)
+    steps = 5
+    ref = O.run(g0, om, force, walls=walls, steps=steps, les=les)
+    kw = dict(walls_y=True, walls_x="x" in walls, sym_top="s" in walls, force=force)
+    if les is not None:
+        kw.update(les_cs=les[0], les_wall_units=les[1], les_aplus=les[2])
+    for storage in ("f64", "f32"):
+        with L.Lattice(L.Config(nx, ny, nz, storage=storage, nu=0.005, **kw)) as lat:
+            lat.set_f(g0)
+            lat.step(steps)
+            got = lat.get_f()
+        if storage == "f64":
+            assert _rel(got, ref) <= 1e-12, storage
+        else:
+            assert np.all(np.abs(got - ref) <= _tol("f32", steps, ref))
+    if les is not None:  # the model acts on this state
+        assert _rel(O.run(g0, om, force, walls=walls, steps=steps), ref) > 1e-6
