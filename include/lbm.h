@@ -193,8 +193,12 @@ int lbm_diagnostics(lbm_ctx* c, lbm_diag* out);
 int lbm_get_f(lbm_ctx* c, double* f);
 int lbm_set_f(lbm_ctx* c, const double* f);
 
-/* Bit-exact checkpoint of the raw storage (27 * N values of the storage type,
- * deviations, SoA).  nbytes must equal lbm_state_bytes(c).  Synchronous. */
+/* Bit-exact checkpoint of the raw storage: one state buffer as the library
+ * keeps it in device memory (deviations f - w in the storage type, FP16/BF16
+ * scaled; blocked by 64-node x segments, each holding its 27 directions, nx
+ * padded to a multiple of 64, padding zero).  Opaque apart from its size;
+ * restore it into a context created with the same configuration.  nbytes must
+ * equal lbm_state_bytes(c).  Synchronous. */
 int64_t lbm_state_bytes(const lbm_ctx* c);
 int lbm_get_raw(lbm_ctx* c, void* host, int64_t nbytes);
 int lbm_set_raw(lbm_ctx* c, const void* host, int64_t nbytes);
