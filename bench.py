@@ -133,7 +133,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--forms", default="f32,f64,f16dev,bf16dev")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--closure-steps", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (for scaling rocprofv3 byte counters)")

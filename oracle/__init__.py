@@ -61,6 +61,7 @@ def _load():
         lib.orc_init.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, _dp]
         lib.orc_collide.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
         lib.orc_stream.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp]
+        lib.orc_stream_push.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp]
         lib.orc_run.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
         lib.orc_run.restype = ctypes.c_int
         lib.orc_num_threads.restype = ctypes.c_int
@@ -211,6 +212,16 @@ def stream(g: np.ndarray, walls_y: bool = False, walls=None, lid=None) -> np.nda
     _, nz, ny, nx = g.shape
     f = np.zeros_like(g)
     lib.orc_stream(nx, ny, nz, _walls(walls_y, walls), _d(_lid(lid)), _d(g), _d(f))
+    return f
+
+
+def stream_push(g: np.ndarray, walls_y: bool = False, walls=None, lid=None) -> np.ndarray:
+    """Streaming in push form (cross-check of ``stream``)."""
+    lib = _load()
+    g = _f64(g)
+    _, nz, ny, nx = g.shape
+    f = np.zeros_like(g)
+    lib.orc_stream_push(nx, ny, nz, _walls(walls_y, walls), _d(_lid(lid)), _d(g), _d(f))
     return f
 
 

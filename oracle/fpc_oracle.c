@@ -518,6 +518,49 @@ void orc_stream(int nx, int ny, int nz, int walls, const double* lid, const doub
   }
 }
 
+/* The same streaming written in push form, as a cross-check of the pull
+ * form: every node sends g_a(x) to x + e_a; a population whose destination
+ * lies beyond a walled face returns to x as the opposite velocity (with the
+ * lid correction when it crosses the moving lid), and one crossing the
+ * symmetry plane lands on (x + e_x, ny-1, z + e_z) with the mirrored
+ * velocity. */
+void orc_stream_push(int nx, int ny, int nz, int walls, const double* lid, const double* g, double* f) {
+  setup();
+  setup_wrest();
+  const int64_t N = (int64_t)nx * ny * nz;
+  for (int64_t i = 0; i < N; ++i) {
+    const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+    for (int a = 0; a < Q; ++a) {
+      const double val = g[a * N + i];
+      int xd = x + EX[a], yd = y + EY[a], zd = z + EZ[a];
+      const int outx = (walls & 2) && (xd < 0 || xd >= nx);
+      const int outy = (walls & 1) && (yd < 0 || yd >= ny);
+      const int outz = (walls & 4) && (zd < 0 || zd >= nz);
+      if (outy && (walls & 8) && yd >= ny && !outx && !outz) {
+        int am = 0;
+        for (int b = 0; b < Q; ++b)
+          if (EX[b] == EX[a] && EY[b] == -EY[a] && EZ[b] == EZ[a]) am = b;
+        xd = (xd % nx + nx) % nx;
+        zd = (zd % nz + nz) % nz;
+        f[am * N + (xd + (int64_t)nx * (y + (int64_t)ny * zd))] = val;
+        continue;
+      }
+      if (outx || outy || outz) {
+        double v = val;
+        /* arrives as OPP[a]; crossed the lid if it left through the top */
+        if (lid && (walls & 1) && yd >= ny)
+          v += 2.0 * WREST[OPP[a]] * (EX[OPP[a]] * lid[0] + EY[OPP[a]] * lid[1] + EZ[OPP[a]] * lid[2]) / CS2;
+        f[OPP[a] * N + i] = v;
+        continue;
+      }
+      xd = (xd % nx + nx) % nx;
+      yd = (yd % ny + ny) % ny;
+      zd = (zd % nz + nz) % nz;
+      f[a * N + (xd + (int64_t)nx * (yd + (int64_t)ny * zd))] = val;
+    }
+  }
+}
+
 /* nsteps of: stream, then collide (one full time step in the paper's order,
  * seen from the post-collision state).  g holds the post-collision state on
  * entry and on exit. */

@@ -596,3 +596,29 @@ def test_smagorinsky_les_gives_the_model_eddy_viscosity_in_channel_flow(damping)
     far = np.abs(j - (ny - 1) / 2) > ny / 4
     assert nut_model[far].max() > 0.01 * nu
     np.testing.assert_allclose(nut_seen[far], nut_model[far], rtol=0.10 if damping else 0.03)
+
+
+@pytest.mark.parametrize("walls,lid", [("", None), ("y", None), ("xyz", (0.03, 0.0, 0.01)), ("ys", None),
+                                       ("xys", None), ("yz", (0.0, 0.0, 0.02))])
+def test_pull_and_push_streaming_agree(walls, lid):
+    """The pull gather the kernels use and the push scatter give the same
+    populations for every boundary set (both written out independently)."""
+    g = O.feq(1.0, (0.0, 0.0, 0.0))[:, None, None, None] * W.random_factors((27, 5, 6, 7), seed=4, amplitude=0.3)
+    np.testing.assert_array_equal(O.stream(g, walls=walls, lid=lid), O.stream_push(g, walls=walls, lid=lid))
+
+
+def test_streaming_in_place_without_double_buffer_is_caught():
+    """Negative control for the A/B buffers: streaming that overwrites the
+    state it reads (a single buffer, nodes visited in order) differs from the
+    double-buffered step far beyond any parity tolerance."""
+    g = O.feq(1.0, (0.0, 0.0, 0.0))[:, None, None, None] * W.random_factors((27, 4, 5, 6), seed=5, amplitude=0.3)
+    e, _, _ = O.lattice()
+    _, nz, ny, nx = g.shape
+    f = g.copy()  # planted mistake: read and write the same array
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                for a in range(27):
+                    f[a, z, y, x] = f[a, (z - e[a, 2]) % nz, (y - e[a, 1]) % ny, (x - e[a, 0]) % nx]
+    good = O.stream(g)
+    assert np.abs(f - good).max() > 1e-3 * np.abs(good).max()
