@@ -428,3 +428,25 @@ def test_symmetry_plane_and_les_match_oracle(shape, walls, les):
             assert np.all(np.abs(got - ref) <= _tol("f32", steps, ref))
     if les is not None:  # the model acts on this state
         assert _rel(O.run(g0, om, force, walls=walls, steps=steps), ref) > 1e-6
+
+
+def test_forced_channel_500_steps_f64():
+    """A small forced channel (walls in y, body force) over 500 steps in FP64:
+    populations within 1e-12 of the oracle, rho - 1 within 1e-12 absolute, and
+    u within 1e-12 of its largest value."""
+    shape = (16, 12, 8)
+    nx, ny, nz = shape
+    F = (3e-6, 0.0, 1e-6)
+    rho, u = W.channel_turbulent_start(nx, ny, nz, u_bulk=0.03, amp=0.2, seed=9, kmax=2)
+    g0 = O.init(rho, u)
+    om = O.omega_table(0.01)
+    ref = O.run(g0, om, F, walls_y=True, steps=500)
+    with L.Lattice(L.Config(nx, ny, nz, storage="f64", walls_y=True, nu=0.01, force=F)) as lat:
+        lat.set_f(g0)
+        lat.step(500)
+        got = lat.get_f()
+        r_gpu, u_gpu = lat.moments()
+    assert _rel(got, ref) <= 1e-12
+    r_ref, u_ref = O.macroscopic(ref, force=F)
+    assert np.abs(r_gpu - r_ref).max() <= 1e-12
+    assert np.abs(u_gpu - u_ref).max() <= 1e-12 * np.abs(u_ref).max()
