@@ -2,8 +2,8 @@
  * lbm.h -- C ABI of the MI355X (gfx950) D3Q27 Fokker-Planck central-moment
  * lattice Boltzmann library (FPC-LBM, Schupbach & Premnath, arXiv 2410.09739).
  *
- * The library advances a periodic box (optionally bounded by two walls normal
- * to y) with the fused stream-and-collide update of the paper:
+ * The library advances a box, periodic or bounded by walls on any faces, with
+ * the fused stream-and-collide update of the paper:
  *   - collision of Appendix D Steps 1-5: raw moments (Step 1), central moments
  *     (Step 2, Eq. rmcm), relaxation of each central moment towards its
  *     Markovian attractor (Step 3, Eqs. Mvcmattractor3D and
@@ -11,7 +11,11 @@
  *     body-force sources of Eq. (cmupdatesourceD3Q27), and the maps back
  *     (Steps 4 and 5);
  *   - streaming, Eq. (LBMsteps-stream) / Appendix D Step 6, with halfway
- *     bounce-back at the walls (Sec. 4, 3D cavity: stationary walls only);
+ *     bounce-back at the walls, the moving-lid correction and the specular
+ *     symmetry plane of the Sec. 4 cavity and half-channel studies;
+ *   - options used by those studies: the central-moment scheme with Maxwellian
+ *     attractors that Sec. 4 compares against (lbm_config.attractor) and
+ *     Smagorinsky LES with van Driest damping (lbm_config.les_*);
  *   - macroscopic fields of Appendix D Step 7: rho = sum f,
  *     rho u = sum f e + F/2, P = rho c_s^2, c_s^2 = 1/3.
  *
@@ -26,8 +30,10 @@
  *   (Steps 1-5) to f~(t+1).  lbm_moments reports the Step 7 fields of the
  *   pre-collision state at t: rho = sum f~, rho u = sum f~ e - F/2 (the
  *   collision adds exactly F to sum f e).
- * Walls: walls_y = 1 puts stationary no-slip walls half a link below y = 0 and
- *   half a link above y = ny - 1; x and z stay periodic.
+ * Walls: walls_y = 1 puts no-slip walls half a link below y = 0 and half a
+ *   link above y = ny - 1 (walls_x, walls_z likewise across x and z); faces
+ *   without walls are periodic.  The wall above y = ny - 1 may move
+ *   (lid_velocity) or be replaced by a symmetry plane (sym_top).
  * Storage forms: the distributions are held as deviations f - w_alpha from the
  *   D3Q27 lattice weights (8/27, 2/27, 1/54, 1/216), in FP64, FP32, FP16 or
  *   BF16.  FP16 and BF16 values carry an exact power-of-two scale per weight
