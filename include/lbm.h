@@ -41,6 +41,9 @@
  *   arithmetic is FP64 for LBM_F64 and FP32 otherwise.  lbm_init, lbm_set_f
  *   round to nearest even.
  * Streams: every device operation is enqueued on the configured HIP stream.
+ *   Device memory the caller passes in must be ready on that stream: data
+ *   written on another stream must be synchronised first (or the work ordered
+ *   with an event) by the caller.
  * Errors: functions return LBM_OK (0) or a negative code; lbm_last_error gives
  *   a text.  No entry point throws, aborts or exits.
  * Ownership: the library owns the device memory it allocates (two state
@@ -163,8 +166,9 @@ void lbm_config_default(lbm_config* cfg);
 int lbm_omega_table(const lbm_config* cfg, double omega_out[LBM_Q]);
 
 /* Validates cfg, allocates the two device state buffers and scratch on the
- * current HIP device.  *out receives the context (NULL on error; the error text
- * is then available from lbm_last_error(NULL)). */
+ * current HIP device and clears the buffers on the context's stream; returns
+ * once that clear has finished.  *out receives the context (NULL on error; the
+ * error text is then available from lbm_last_error(NULL)). */
 int lbm_create(const lbm_config* cfg, lbm_ctx** out);
 
 /* Stores f~(0) = f^eq(rho, u) at every node, where f^eq has the equilibrium

@@ -783,11 +783,14 @@ extern "C" int lbm_mlp_create(uint64_t seed, void* hip_stream, lbm_mlp** out) {
   for (int i = 0; i < NH * NH; ++i) p[OFF_W2 + i] = (float)(uni(OFF_W2 + i) * std::sqrt(6.0 / NH));
   for (int i = 0; i < NOUT * NH; ++i) p[OFF_W3 + i] = (float)(uni(OFF_W3 + i) * std::sqrt(6.0 / NH));
   std::vector<float> zeros(NIN, 0.0f), ones(NIN, 1.0f);
-  e = hipMemcpy(m->P, p.data(), sizeof(float) * NPARAM, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(m->M, 0, sizeof(float) * NPARAM);
-  if (e == hipSuccess) e = hipMemset(m->V, 0, sizeof(float) * NPARAM);
-  if (e == hipSuccess) e = hipMemcpy(m->mu, zeros.data(), sizeof(float) * NIN, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(m->isig, ones.data(), sizeof(float) * NIN, hipMemcpyHostToDevice);
+  // on the object's own stream (the null stream is not ordered with a
+  // non-blocking one), complete before create returns: the host vectors die here
+  e = hipMemcpyAsync(m->P, p.data(), sizeof(float) * NPARAM, hipMemcpyHostToDevice, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->M, 0, sizeof(float) * NPARAM, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->V, 0, sizeof(float) * NPARAM, m->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->mu, zeros.data(), sizeof(float) * NIN, hipMemcpyHostToDevice, m->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->isig, ones.data(), sizeof(float) * NIN, hipMemcpyHostToDevice, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) {
     mlp_err(nullptr, LBM_EHIP, "lbm_mlp_create: %s", hipGetErrorString(e));
     lbm_mlp_destroy(m);
@@ -855,7 +858,7 @@ extern "C" int lbm_mlp_fit_normalisation(lbm_mlp* m, const float* x_dev, const f
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   // sum of squares of the targets: mean about zero of one 6n-long column
   double zero = 0.0;
-  if (e == hipSuccess) e = hipMemcpy(res + 2 * NIN, &zero, sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpyAsync(res + 2 * NIN, &zero, sizeof(double), hipMemcpyHostToDevice, m->stream);
   if (e == hipSuccess) {
     k_colstats<<<RB, 256, 0, m->stream>>>(y_dev, 6 * n, 1, res + 2 * NIN, part);
     k_colreduce<<<1, 256, 0, m->stream>>>(part, 1, (double)(6 * n), res);

@@ -425,14 +425,6 @@ extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   c->elem = es;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) {
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&c->buf[b], (size_t)c->values * es);
-    // the padding lanes of the x segments (nx not a multiple of 64) are never
-    // written by the kernels: zero them once so that the raw state is defined
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMemset(c->buf[b], 0, (size_t)c->values * es);
-  }
-  if (e == hipSuccess) e = hipMalloc((void**)&c->part, sizeof(double) * (DIAG_BLOCKS * (NP + 1) + NP));
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_out, sizeof(double) * NP, hipHostMallocDefault);
-  if (e == hipSuccess) {
     if (cfg->hip_stream) {
       c->stream = (hipStream_t)cfg->hip_stream;
     } else {
@@ -440,6 +432,16 @@ extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
       c->own_stream = (e == hipSuccess);
     }
   }
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&c->buf[b], (size_t)c->values * es);
+  // The padding lanes of the x segments (nx not a multiple of 64) are never
+  // written by the kernels: zero them once so that the raw state is defined.
+  // The clear goes on the library's stream and completes before create
+  // returns: a plain hipMemset would run on the null stream, unordered with
+  // the (non-blocking) library stream, and could land after a following init.
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMemsetAsync(c->buf[b], 0, (size_t)c->values * es, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->part, sizeof(double) * (DIAG_BLOCKS * (NP + 1) + NP));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_out, sizeof(double) * NP, hipHostMallocDefault);
   if (e != hipSuccess) {
     int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? LBM_ENOMEM : LBM_EHIP;
     set_err(nullptr, code, "lbm_create: %s", hipGetErrorString(e));

@@ -131,6 +131,30 @@ def test_training_reduces_the_loss():
     m.close()
 
 
+def test_mlp_create_is_ordered_before_training():
+    """lbm_mlp_create writes the initial parameters and clears the Adam moments
+    on the object's own stream before it returns: work queued on the null stream
+    at create changes nothing in what the training then computes."""
+    rng = np.random.default_rng(17)
+    n = 2048
+    X = rng.standard_normal((n, 27)).astype(np.float32)
+    Y = np.abs(rng.standard_normal((n, 6))).astype(np.float32)
+    xd, yd = _dev(X), _dev(Y)
+    out = []
+    for busy in (False, True):
+        if busy:
+            big = torch.ones(1 << 27, device="cuda")
+            for _ in range(100):
+                big.mul_(1.0)
+        m = L.MLP(seed=9)
+        m.fit_normalisation(xd.data_ptr(), yd.data_ptr(), n)
+        m.train(xd.data_ptr(), yd.data_ptr(), n, 256, 5, 1e-3, 2)
+        out.append(m.get_params())
+        m.close()
+        torch.cuda.synchronize()
+    assert np.array_equal(out[0], out[1])
+
+
 def _state(shape, seed, amp=0.05):
     nx, ny, nz = shape
     rho, u = W.random_fields(nx, ny, nz, seed=seed, u_amp=0.05)

@@ -234,6 +234,40 @@ def test_errors_are_reported_not_raised_on_device():
         assert ei.value.code == L.LBM_EUNSTABLE
 
 
+def _queue_null_stream_work(iters=100):
+    """Queue some tens of milliseconds of work on torch's current stream (the
+    null stream) without waiting for it; returns the buffer to keep alive."""
+    torch = pytest.importorskip("torch")
+    big = torch.ones(1 << 27, device="cuda")
+    for _ in range(iters):
+        big.mul_(1.0)
+    return big
+
+
+@pytest.mark.parametrize("source", ["host", "device"])
+def test_create_clear_is_ordered_before_init(source):
+    """lbm_create clears the state buffers on the context's stream and waits for
+    the clear: with work still queued on the null stream at create, the clear
+    cannot land after the following init (which would leave the fluid at rest)."""
+    torch = pytest.importorskip("torch")
+    shape = (70, 9, 6)  # ragged: one full and one partial x segment
+    rho, u = W.random_fields(*shape, seed=41, u_amp=0.05)
+    rd = torch.tensor(rho.reshape(-1), device="cuda")
+    ud = torch.tensor(u.reshape(-1), device="cuda")
+    torch.cuda.synchronize()
+    busy = _queue_null_stream_work()
+    with L.Lattice(L.Config(*shape, storage="f32", nu=0.02)) as lat:
+        if source == "host":
+            lat.init(rho, u)
+        else:
+            L.lbm_init_device(lat.ctx, rd.data_ptr(), ud.data_ptr())
+        torch.cuda.synchronize()  # everything queued on the null stream has now run
+        r, v = lat.moments()
+    del busy
+    np.testing.assert_allclose(r, rho, rtol=1e-6)
+    np.testing.assert_allclose(v, u, rtol=0, atol=1e-6)
+
+
 # ------------------------------------------------------------------ full size, sampled
 def test_channel_256x128x128_sampled_nodes_f32():
     """The 256 x 128 x 128 body-force channel in FP32 storage, in the launch
