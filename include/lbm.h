@@ -262,21 +262,29 @@ int lbm_closure_eval(const float* params, const float* x_dev, float* nu_dev, int
  * coarse grid (nx/2, ny/2, nz/2), caller device memory, FP64:
  * rho_dev [Nc] (mean density), u_dev [3][Nc] (Favre velocity avg(rho u)/avg(rho)),
  * tau_dev [6][Nc] (sub-filter stress avg(rho u_i u_j) - rho u_i u_j; xx, yy, zz,
- * xy, xz, yz).  Fine rho, u are the Step 7 fields.  Enqueued on the stream. */
-int lbm_coarsen(lbm_ctx* c, double* rho_dev, double* u_dev, double* tau_dev);
+ * xy, xz, yz), and, unless sbar_dev is NULL, sbar_dev [6][Nc] (Favre-filtered
+ * fine strain rate in coarse lattice units, 2 avg(rho S) / avg(rho), S the
+ * centred-difference strain of the fine velocity as in lbm_closure_targets;
+ * periodic and y-wall lattices only, else LBM_EINVAL).  Fine rho, u are the
+ * Step 7 fields.  Enqueued on the stream. */
+int lbm_coarsen(lbm_ctx* c, double* rho_dev, double* u_dev, double* tau_dev, double* sbar_dev);
 
 /* lbm_init from device fields rho_dev [N], u_dev [3][N] (FP64).  Synchronous. */
 int lbm_init_device(lbm_ctx* c, const double* rho_dev, const double* u_dev);
 
 /* Eddy-viscosity targets on the grid of c from filtered fields (as written by
  * lbm_coarsen): per node y_dev[i][6] (float) =
- * max(0, -tau_j S_j / (2 rho (S_j^2 + eps^2))) for the groups 110, 101, 011,
- * 2d1, 2d2 (tau_j, S_j: xy, xz, yz, xx-yy, xx-zz) and 0 for 2s1; S is the
- * strain rate of u by centred differences (periodic, or an antisymmetric ghost
- * across the walls); eps = eps_rel * rms(S), rms over the 3 N entries of
- * S_ii^2 + 2 S_ij^2.  Synchronous. */
+ * max(0, S_j (nu_j (Sbar_j - S_j) - tau_j / (2 rho)) / (S_j^2 + eps^2)) for the
+ * groups 110, 101, 011 (tau_j, S_j, Sbar_j: the xy, xz, yz entries;
+ * nu_j = (1/omega_{4+j} - 1/2) / 3, the viscosity of c for the group), and 0 for
+ * 2s1, 2d1, 2d2: the eddy viscosity that makes the coarse node carry the
+ * filtered fine stress (sub-filter plus viscous) in the least-squares sense.
+ * S is the strain rate of u by centred differences (periodic, or an
+ * antisymmetric ghost across the walls); eps = eps_rel * rms(S), rms over the
+ * 3 N entries of S_ii^2 + 2 S_ij^2.  Periodic and y-wall lattices only.
+ * Synchronous. */
 int lbm_closure_targets(lbm_ctx* c, const double* rho_dev, const double* u_dev, const double* tau_dev,
-                        double eps_rel, float* y_dev);
+                        const double* sbar_dev, double eps_rel, float* y_dev);
 
 /* Training of the closure network on the GPU (FP32 forward and backward
  * kernels, Adam).  Inputs are standardised, (x - mu) / sigma (sigma = 0 drops a

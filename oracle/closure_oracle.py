@@ -22,12 +22,20 @@ omega_7, omega_8, omega_9), applied as 1/omega_j,eff = 1/omega_j + 3 max(nu_t,j,
 through Eq. (transportcoeff3DFPCLBM) (nu = c_s^2 (1/omega - 1/2)).
 
 Targets: from a fine run box-filtered 2x2x2 (Favre: u~ = avg(rho u) / avg(rho)),
-the sub-filter stress tau_ij = avg(rho u_i u_j) - avg(rho) u~_i u~_j and the
-coarse strain S_ij of u~ (centred differences on the coarse grid, periodic x/z,
-antisymmetric ghost across half-link walls in y); per group
-nu*_j = max(0, -tau_j S_j / (2 rho~ (S_j^2 + eps^2))) with tau_j, S_j the group
-combinations (xy, xz, yz, -, xx-yy, xx-zz), eps = eps_rel * rms(S), and
-nu*_2s1 = 0 (the trace goes to pressure).
+the sub-filter stress tau_ij = avg(rho u_i u_j) - avg(rho) u~_i u~_j, the coarse
+strain S_ij of u~ (centred differences on the coarse grid, periodic x/z,
+antisymmetric ghost across half-link walls in y) and the filtered fine strain
+Sbar_ij = 2 avg(rho S^f_ij) / avg(rho) (S^f: the same stencil on the fine grid;
+the factor 2 turns fine into coarse lattice units).  The coarse node should
+carry, beyond the resolved flux rho~ u~ u~, the filtered fine flux
+tau - 2 rho~ nu Sbar; with an eddy viscosity it carries -2 rho~ (nu + nu_t) S.
+Matching the two per group in the least-squares sense gives
+nu*_j = max(0, S_j (nu_j (Sbar_j - S_j) - tau_j / (2 rho~)) / (S_j^2 + eps^2))
+for the off-diagonal groups 110, 101, 011 (xy, xz, yz), with nu_j = c_s^2
+(1/omega_j - 1/2) the group's coarse viscosity and eps = eps_rel * rms(S), and
+nu* = 0 for 2s1 (the trace goes to pressure) and for the normal-stress
+differences 2d1, 2d2 (their sub-filter anisotropy is not a dissipation aligned
+with the strain; an eddy viscosity fitted there damps the resolved turbulence).
 """
 from __future__ import annotations
 
@@ -168,6 +176,21 @@ def box_filter(rho: np.ndarray, u: np.ndarray, factor: int = 2):
     return rb, ut, tau
 
 
+def filtered_strain(rho: np.ndarray, u: np.ndarray, walls_y: bool, factor: int = 2) -> np.ndarray:
+    """Favre box filter of the fine strain rate in coarse lattice units:
+    Sbar = factor * avg(rho S^f) / avg(rho), S^f = strain(u, walls_y) on the fine
+    grid; [6, nz/f, ny/f, nx/f] in the order xx, yy, zz, xy, xz, yz."""
+    nz, ny, nx = rho.shape
+    f = factor
+
+    def avg(a):
+        return a.reshape(nz // f, f, ny // f, f, nx // f, f).mean(axis=(1, 3, 5))
+
+    Sf = strain(u, walls_y)
+    rb = avg(rho)
+    return np.stack([f * avg(rho * Sf[k]) / rb for k in range(6)])
+
+
 def strain(u: np.ndarray, walls_y: bool) -> np.ndarray:
     """S_ij = (d_i u_j + d_j u_i)/2 by centred differences; order xx, yy, zz, xy, xz, yz.
     Periodic in x and z; in y periodic or an antisymmetric ghost across the walls."""
@@ -190,15 +213,17 @@ def group(a6: np.ndarray) -> np.ndarray:
     return np.stack([xy, xz, yz, xx + yy + zz, xx - yy, xx - zz])
 
 
-def targets(rho_t: np.ndarray, tau: np.ndarray, S: np.ndarray, eps_rel: float = 0.1) -> np.ndarray:
-    """nu*_j per coarse node, [6, ...]; see the module docstring."""
-    tg = group(tau)
-    sg = group(S)
-    eps = eps_rel * np.sqrt(np.mean(S[:3] ** 2 + 2 * S[3:] ** 2))
-    nu = -tg * sg / (2.0 * rho_t[None] * (sg * sg + eps * eps))
-    nu = np.maximum(nu, 0.0)
-    nu[3] = 0.0
-    return nu
+def targets(rho_t: np.ndarray, tau: np.ndarray, S: np.ndarray, Sbar: np.ndarray, nu, eps_rel: float = 0.1,
+            clip: bool = True) -> np.ndarray:
+    """nu*_j per coarse node, [6, ...]; see the module docstring.  nu: the coarse
+    viscosities of the groups 110, 101, 011 (three values, or one for all)."""
+    nu3 = np.broadcast_to(np.asarray(nu, dtype=np.float64), (3,))
+    tg, sg, sb = group(tau), group(S), group(Sbar)
+    eps2 = eps_rel ** 2 * np.mean(S[:3] ** 2 + 2 * S[3:] ** 2)
+    out = np.zeros_like(sg)
+    for j in range(3):
+        out[j] = sg[j] * (nu3[j] * (sb[j] - sg[j]) - tg[j] / (2.0 * rho_t)) / (sg[j] * sg[j] + eps2)
+    return np.maximum(out, 0.0) if clip else out
 
 
 # ------------------------------------------------------------------ reduced-precision inference

@@ -7,7 +7,10 @@
 // the 27 features of a node's pre-collision central moments to six eddy
 // viscosities nu_t,j for the second-order groups relaxed with omega_4..omega_9,
 // applied through Eq. (transportcoeff3DFPCLBM) as
-// 1/omega_j,eff = 1/omega_j + 3 clamp(nu_t,j, 0, 1/3).
+// 1/omega_j,eff = 1/omega_j + 3 clamp(nu_t,j, 0, 1/3).  Training targets make
+// a coarse node carry the box-filtered stress of a fine run (sub-filter stress
+// plus the filtered fine viscous stress) on the off-diagonal groups; the
+// trained network leaves the other three at zero.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -276,10 +279,40 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
   if (threadIdx.x == 0) *out = t;
 }
 
-// nu*_j = max(0, -tau_j S_j / (2 rho (S_j^2 + eps^2))) for the groups
-// 110, 101, 011, (2s1: 0), 2d1, 2d2; eps^2 = eps_rel^2 * sum / (3 n).
+// Favre box filter of the fine strain rate, in coarse lattice units: per coarse
+// node, 2 * sum(rho S) / sum(rho) over its eight fine nodes, with S the centred
+// strain of the fine velocity (rho, u: fine fields, u as [3][N]).
+__global__ __launch_bounds__(256) void k_filtered_strain(const double* __restrict__ rho, const double* __restrict__ u,
+                                                         Geom g, int walls, double* __restrict__ sb) {
+  const int cx = g.nx / 2, cy = g.ny / 2, cz = g.nz / 2;
+  const int64_t nc = (int64_t)cx * cy * cz;
+  const int64_t ic = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ic >= nc) return;
+  const int X = (int)(ic % cx), Y = (int)((ic / cx) % cy), Z = (int)(ic / ((int64_t)cx * cy));
+  double R = 0.0, A[6] = {0, 0, 0, 0, 0, 0};
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int64_t i = ((int64_t)(2 * Z + dz) * g.ny + (2 * Y + dy)) * g.nx + (2 * X + dx);
+        double S[6];
+        strain_at(u, g, walls, i, S);
+        const double r = rho[i];
+        R += r;
+        for (int k = 0; k < 6; ++k) A[k] += r * S[k];
+      }
+  for (int k = 0; k < 6; ++k) sb[k * nc + ic] = 2.0 * A[k] / R;
+}
+
+// nu*_j = max(0, S_j (nu_j (Sbar_j - S_j) - tau_j / (2 rho)) / (S_j^2 + eps^2))
+// for the groups 110, 101, 011 (xy, xz, yz) and 0 for 2s1, 2d1, 2d2;
+// eps^2 = eps_rel^2 * sum / (3 n).
+struct TargetNu {
+  double nu[3];  // coarse viscosities of the groups 110, 101, 011
+};
+
 __global__ __launch_bounds__(256) void k_targets(const double* __restrict__ rho, const double* __restrict__ u,
-                                                 const double* __restrict__ tau, Geom g, int walls, double eps_rel,
+                                                 const double* __restrict__ tau, const double* __restrict__ sbar,
+                                                 Geom g, int walls, double eps_rel, TargetNu V,
                                                  const double* __restrict__ ssum, float* __restrict__ y) {
   const int64_t n = (int64_t)g.nx * g.ny * g.nz;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -287,16 +320,13 @@ __global__ __launch_bounds__(256) void k_targets(const double* __restrict__ rho,
   const double eps2 = eps_rel * eps_rel * (*ssum) / (3.0 * (double)n);
   double S[6];
   strain_at(u, g, walls, i, S);
-  double t[6];
-  for (int k = 0; k < 6; ++k) t[k] = tau[k * n + i];
-  const double tg[6] = {t[3], t[4], t[5], t[0] + t[1] + t[2], t[0] - t[1], t[0] - t[2]};
-  const double sg[6] = {S[3], S[4], S[5], S[0] + S[1] + S[2], S[0] - S[1], S[0] - S[2]};
   const double r = rho[i];
-  for (int k = 0; k < 6; ++k) {
-    double nu = -tg[k] * sg[k] / (2.0 * r * (sg[k] * sg[k] + eps2));
+  for (int k = 0; k < 3; ++k) {
+    const double sg = S[3 + k], tg = tau[(3 + k) * n + i], sb = sbar[(3 + k) * n + i];
+    double nu = sg * (V.nu[k] * (sb - sg) - tg / (2.0 * r)) / (sg * sg + eps2);
     nu = nu > 0.0 ? nu : 0.0;
-    if (k == 3) nu = 0.0;
     y[i * 6 + k] = (float)nu;
+    y[i * 6 + 3 + k] = 0.0f;
   }
 }
 
@@ -661,11 +691,13 @@ extern "C" int lbm_init_device(lbm_ctx* c, const double* rho_dev, const double* 
   return LBM_OK;
 }
 
-extern "C" int lbm_coarsen(lbm_ctx* c, double* rho_dev, double* u_dev, double* tau_dev) {
+extern "C" int lbm_coarsen(lbm_ctx* c, double* rho_dev, double* u_dev, double* tau_dev, double* sbar_dev) {
   if (!c || !rho_dev || !u_dev || !tau_dev) return LBM_EINVAL;
   if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_coarsen: state not initialised");
   if (c->cfg.nx % 2 || c->cfg.ny % 2 || c->cfg.nz % 2)
     return set_err(c, LBM_EINVAL, "lbm_coarsen: nx, ny, nz must be even");
+  if (sbar_dev && bc_kind(c) == 2)
+    return set_err(c, LBM_EINVAL, "lbm_coarsen: the filtered strain needs a periodic or y-wall lattice");
   HIPCHK(c, hipSetDevice(c->device));
   const Geom g = geom(c);
   const int64_t nc = c->n / 8;
@@ -674,14 +706,27 @@ extern "C" int lbm_coarsen(lbm_ctx* c, double* rho_dev, double* u_dev, double* t
               k_coarsen<ST><<<nblocks(nc, 256), 256, 0, c->stream>>>((const typename Stor<ST>::S*)c->buf[c->cur], g,
                                                                       F[0], F[1], F[2], rho_dev, u_dev, tau_dev));
   LAUNCHCHK(c);
+  if (sbar_dev) {
+    int rc = alloc_scratch(c);
+    if (rc) return rc;
+    rc = lbm_moments_device(c, c->scratch, c->scratch + c->n, 1);  // fine Step 7 fields, same stream
+    if (rc) return rc;
+    k_filtered_strain<<<nblocks(nc, 256), 256, 0, c->stream>>>(c->scratch, c->scratch + c->n, g, c->cfg.walls_y,
+                                                                sbar_dev);
+    LAUNCHCHK(c);
+  }
   return LBM_OK;
 }
 
 extern "C" int lbm_closure_targets(lbm_ctx* c, const double* rho_dev, const double* u_dev, const double* tau_dev,
-                                   double eps_rel, float* y_dev) {
-  if (!c || !rho_dev || !u_dev || !tau_dev || !y_dev || !(eps_rel >= 0.0)) return LBM_EINVAL;
+                                   const double* sbar_dev, double eps_rel, float* y_dev) {
+  if (!c || !rho_dev || !u_dev || !tau_dev || !sbar_dev || !y_dev || !(eps_rel >= 0.0)) return LBM_EINVAL;
+  if (bc_kind(c) == 2)
+    return set_err(c, LBM_EINVAL, "lbm_closure_targets: periodic and y-wall lattices only");
   HIPCHK(c, hipSetDevice(c->device));
   const Geom g = geom(c);
+  TargetNu V;
+  for (int k = 0; k < 3; ++k) V.nu[k] = (1.0 / c->omega[4 + k] - 0.5) / 3.0;
   double* part = nullptr;
   HIPCHK(c, hipMalloc((void**)&part, sizeof(double) * (RB + 1)));
   k_strain_sq<<<RB, 256, 0, c->stream>>>(u_dev, g, c->cfg.walls_y, part);
@@ -691,7 +736,8 @@ extern "C" int lbm_closure_targets(lbm_ctx* c, const double* rho_dev, const doub
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    k_targets<<<nblocks(c->n, 256), 256, 0, c->stream>>>(rho_dev, u_dev, tau_dev, g, c->cfg.walls_y, eps_rel, part + RB, y_dev);
+    k_targets<<<nblocks(c->n, 256), 256, 0, c->stream>>>(rho_dev, u_dev, tau_dev, sbar_dev, g, c->cfg.walls_y, eps_rel, V,
+                                                         part + RB, y_dev);
     e = hipGetLastError();
   }
   hipError_t e2 = hipStreamSynchronize(c->stream);

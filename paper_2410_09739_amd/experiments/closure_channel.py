@@ -2,16 +2,18 @@
 (384 x 192 x 192, half-width h = 96, u_tau = 0.0025, nu_f = u_tau h / 180,
 F_f = rho u_tau^2 / h) gives box-filtered snapshots on the 192 x 96 x 96 grid;
 the per-node MLP closure is trained on them on the GPU and drives coarse runs
-(acoustic scaling: nu_c = nu_f / 2, F_c = 2 F_f).  Reports mean and RMS
-velocity profiles of the plain coarse run, the closure run and the filtered
-fine run, the wall friction velocity of each, the wall time of each, and the
-trained parameters (saved as .npy).
+(acoustic scaling: nu_c = nu_f / 2, F_c = 2 F_f).  Reports, over a statistically
+steady window, the bulk velocity and the mean and RMS velocity profiles of the
+plain coarse run, the closure run and the filtered fine run, the wall friction
+velocity of each, the wall time of each, and the trained parameters (.npy).
 
-    python -m paper_2410_09739_amd.experiments.closure_channel [--tstar-transient 6] [--tstar-stats 4]
+    python -m paper_2410_09739_amd.experiments.closure_channel [--tstar-transient 6] [--tstar-stats 6]
 
-Time unit T* = h / u_tau (38,400 fine steps).  The coarse runs start from the
-filtered fine state at the end of the fine transient and cover the same
-physical time as the fine statistics window.
+Time unit T* = h / u_tau (38,400 fine steps).  The fine run gives a snapshot
+every T*/2 of its statistics window (the last one held out of training).  The
+coarse runs start from the filtered fine state at the end of the fine transient
+and run --coarse-run T*; their statistics cover the last --coarse-stats T*, by
+when the bulk velocity of the coarse grid has settled.
 """
 from __future__ import annotations
 
@@ -62,7 +64,8 @@ def friction_velocity(d: dict, nx: int, nz: int) -> float:
     return float(np.sqrt(max(tau_w, 0.0)))
 
 
-def run_window(L, torch, lat, steps: int, every: int, stats: ProfileStats | None, tag: str, on_sample=None):
+def run_window(L, torch, lat, steps: int, every: int, stats: ProfileStats | None, tag: str, on_sample=None,
+               u_bulk: list | None = None):
     done = 0
     t_run = 0.0
     while done < steps:
@@ -78,6 +81,8 @@ def run_window(L, torch, lat, steps: int, every: int, stats: ProfileStats | None
         if on_sample is not None:
             on_sample(done)
         d = lat.diagnostics()
+        if u_bulk is not None:
+            u_bulk.append(d["momentum"][0] / d["mass"])
         log(f"{tag} step {lat.steps}: u_bulk {d['momentum'][0] / d['mass']:.5f} "
             f"u_tau {friction_velocity(d, lat.cfg.nx, lat.cfg.nz):.5f} max|u| {d['max_speed']:.4f}")
     return t_run
@@ -88,6 +93,15 @@ def coarse_profile_of_fine(p: dict) -> dict:
     return {k: (0.5 * (v[0::2] + v[1::2]) if isinstance(v, np.ndarray) else v) for k, v in p.items()}
 
 
+def scaled_output(params: np.ndarray, gain: float) -> np.ndarray:
+    """Parameters whose network output is gain times the given one: the output
+    layer is linear, so W3 and b3 scale (and the kernel's clamp at zero commutes
+    with a positive gain)."""
+    p = np.array(params, dtype=np.float32, copy=True)
+    p[-(6 * 64 + 6):] *= gain
+    return p
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--shape", default="384,192,192")
@@ -95,14 +109,18 @@ def main():
     ap.add_argument("--re-tau", type=float, default=180.0)
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--tstar-transient", type=float, default=6.0)
-    ap.add_argument("--tstar-stats", type=float, default=4.0)
+    ap.add_argument("--tstar-stats", type=float, default=6.0)
+    ap.add_argument("--coarse-run", type=float, default=16.0)
+    ap.add_argument("--coarse-stats", type=float, default=8.0)
     ap.add_argument("--samples-per-tstar", type=int, default=4)
-    ap.add_argument("--snapshots", type=int, default=8)
-    ap.add_argument("--train-steps", type=int, default=3000)
-    ap.add_argument("--batch", type=int, default=2048)
+    ap.add_argument("--snapshots-per-tstar", type=int, default=2)
+    ap.add_argument("--train-steps", type=int, default=5000)
+    ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eps-rel", type=float, default=0.1)
     ap.add_argument("--perturbation", type=float, default=0.3)
+    ap.add_argument("--seeds", type=int, default=1, help="networks trained from different initialisations")
+    ap.add_argument("--gains", default="1", help="comma list: multipliers of the network output (a-posteriori scale)")
     ap.add_argument("--save-params", default="gpurun_out/closure_params.npy")
     args = ap.parse_args()
     import torch
@@ -122,13 +140,16 @@ def main():
                        f"F={F_f:.6e}; closure grid {cshape[0]}x{cshape[1]}x{cshape[2]}",
            "tstar_steps": tstar, "args": vars(args)}
 
+    def dev(*shape, dtype=torch.float64):
+        return torch.zeros(shape, dtype=dtype, device="cuda")
+
     # ---- fine run: transient, then statistics and training snapshots
     u_bulk0 = 15.7 * ut  # bulk velocity of the turbulent state at Re_tau = 180 (u_b / u_tau ~ 15.7)
     rho0, u0 = W.channel_turbulent_start(nx, ny, nz, u_bulk=u_bulk0, amp=args.perturbation, seed=1234)
     fcfg = L.Config(nx, ny, nz, storage=args.storage, walls_y=True, nu=nu_f, force=(F_f, 0, 0))
     every = max(1, tstar // args.samples_per_tstar)
+    snap_every = max(every, tstar // args.snapshots_per_tstar)
     n_trans, n_stats = int(args.tstar_transient * tstar), int(args.tstar_stats * tstar)
-    snap_every = max(every, n_stats // args.snapshots)
     xs, ys = [], []
     with L.Lattice(fcfg) as fine:
         fine.init(rho0, u0)
@@ -136,9 +157,7 @@ def main():
         log(f"fine transient {n_trans} steps")
         t_fine = run_window(L, torch, fine, n_trans, every, None, "fine")
         # filtered state at the end of the transient: start of every coarse run
-        rc0 = torch.zeros(nc, dtype=torch.float64, device="cuda")
-        uc0 = torch.zeros(3 * nc, dtype=torch.float64, device="cuda")
-        tc0 = torch.zeros(6 * nc, dtype=torch.float64, device="cuda")
+        rc0, uc0, tc0 = dev(nc), dev(3 * nc), dev(6 * nc)
         torch.cuda.synchronize()
         L.lbm_coarsen(fine.ctx, rc0.data_ptr(), uc0.data_ptr(), tc0.data_ptr())
         fine.synchronize()
@@ -148,83 +167,106 @@ def main():
         def snapshot(done):
             if done % snap_every:
                 return
-            rd = torch.zeros(nc, dtype=torch.float64, device="cuda")
-            ud = torch.zeros(3 * nc, dtype=torch.float64, device="cuda")
-            td = torch.zeros(6 * nc, dtype=torch.float64, device="cuda")
-            xd = torch.zeros((nc, 27), dtype=torch.float32, device="cuda")
-            yd = torch.zeros((nc, 6), dtype=torch.float32, device="cuda")
+            rd, ud, td, sd = dev(nc), dev(3 * nc), dev(6 * nc), dev(6 * nc)
+            xd, yd = dev(nc, 27, dtype=torch.float32), dev(nc, 6, dtype=torch.float32)
             torch.cuda.synchronize()
-            L.lbm_coarsen(fine.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr())
+            L.lbm_coarsen(fine.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), sd.data_ptr())
             fine.synchronize()
             L.lbm_init_device(feat_lat.ctx, rd.data_ptr(), ud.data_ptr())
             L.lbm_closure_features(feat_lat.ctx, xd.data_ptr())
-            L.lbm_closure_targets(feat_lat.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), args.eps_rel,
-                                  yd.data_ptr())
+            L.lbm_closure_targets(feat_lat.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), sd.data_ptr(),
+                                  args.eps_rel, yd.data_ptr())
             feat_lat.synchronize()
             xs.append(xd)
             ys.append(yd)
-            log(f"snapshot {len(xs)}: mean target nu_t {yd.mean(dim=0).cpu().numpy()}")
+            log(f"snapshot {len(xs)}: mean target nu_t / nu_c {(yd[:, :3].mean(dim=0) / (nu_f / 2)).cpu().numpy()}")
 
         fstats = ProfileStats(torch, ny)
+        f_ub = []
         log(f"fine statistics {n_stats} steps, snapshot every {snap_every}")
-        t_fine += run_window(L, torch, fine, n_stats, every, fstats, "fine", snapshot)
+        t_fine += run_window(L, torch, fine, n_stats, every, fstats, "fine", snapshot, f_ub)
         dfin = fine.diagnostics()
         feat_lat.close()
     fine_prof = fstats.result()
     out["fine"] = {"wall_s": t_fine, "steps": n_trans + n_stats, "u_tau_end": friction_velocity(dfin, nx, nz),
-                   "u_bulk_end": dfin["momentum"][0] / dfin["mass"]}
+                   "u_bulk_over_u_tau": float(np.mean(f_ub) / ut), "u_bulk_std_over_u_tau": float(np.std(f_ub) / ut)}
     filt = coarse_profile_of_fine(fine_prof)
 
     # ---- training on all snapshots but the last; the last is held out
     X = torch.cat(xs[:-1]) if len(xs) > 1 else xs[0]
     Y = torch.cat(ys[:-1]) if len(ys) > 1 else ys[0]
     Xh, Yh = xs[-1], ys[-1]
-    ntr = X.shape[0]
-    m = L.MLP(seed=11)
-    m.fit_normalisation(X.data_ptr(), Y.data_ptr(), ntr)
-    l0, _ = m.loss_grad(X.data_ptr(), Y.data_ptr(), ntr)
-    lh0, _ = m.loss_grad(Xh.data_ptr(), Yh.data_ptr(), Xh.shape[0])
-    t0 = time.perf_counter()
-    hist = m.train(X.data_ptr(), Y.data_ptr(), ntr, args.batch, args.train_steps, args.lr, 5)
     torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    l1, _ = m.loss_grad(X.data_ptr(), Y.data_ptr(), ntr)
-    lh1, _ = m.loss_grad(Xh.data_ptr(), Yh.data_ptr(), Xh.shape[0])
-    params = m.export()
-    m.close()
-    np.save(args.save_params, params)
-    out["training"] = {"samples": int(ntr), "held_out": int(Xh.shape[0]), "loss_train_before": l0,
-                       "loss_train_after": l1, "loss_heldout_before": lh0, "loss_heldout_after": lh1,
-                       "wall_s": t_train, "steps": args.train_steps, "batch": args.batch,
-                       "loss_history_every_100": [float(v) for v in hist[::100]]}
-    log(f"training: loss {l0:.4e} -> {l1:.4e}, held-out {lh0:.4e} -> {lh1:.4e}, {t_train:.1f} s")
+    ntr = X.shape[0]
+    gains = [float(g) for g in args.gains.split(",")]
+    nets = []
+    out["training"] = []
+    for k in range(args.seeds):
+        m = L.MLP(seed=11 + k)
+        m.fit_normalisation(X.data_ptr(), Y.data_ptr(), ntr)
+        l0, _ = m.loss_grad(X.data_ptr(), Y.data_ptr(), ntr)
+        lh0, _ = m.loss_grad(Xh.data_ptr(), Yh.data_ptr(), Xh.shape[0])
+        t0 = time.perf_counter()
+        hist = m.train(X.data_ptr(), Y.data_ptr(), ntr, args.batch, args.train_steps, args.lr, 5 + k)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        l1, _ = m.loss_grad(X.data_ptr(), Y.data_ptr(), ntr)
+        lh1, _ = m.loss_grad(Xh.data_ptr(), Yh.data_ptr(), Xh.shape[0])
+        nets.append(m.export())
+        m.close()
+        out["training"].append({"seed": 11 + k, "samples": int(ntr), "held_out": int(Xh.shape[0]),
+                                "loss_train_before": l0, "loss_train_after": l1, "loss_heldout_before": lh0,
+                                "loss_heldout_after": lh1, "wall_s": t_train, "steps": args.train_steps,
+                                "batch": args.batch, "loss_history_every_100": [float(v) for v in hist[::100]]})
+        log(f"training {k}: loss {l0:.4e} -> {l1:.4e}, held-out {lh0:.4e} -> {lh1:.4e}, {t_train:.1f} s")
+    np.save(args.save_params, scaled_output(nets[0], gains[0]))
     del X, Y, xs, ys
 
     # ---- coarse runs from the filtered fine state
-    ctrans, cstats = n_trans // 2, n_stats // 2  # same physical time (dt_c = 2 dt_f)
+    ctstar = tstar // 2  # dt_c = 2 dt_f
     cevery = max(1, every // 2)
+    c_settle = int((args.coarse_run - args.coarse_stats) * ctstar)
+    c_stats = int(args.coarse_stats * ctstar)
     res = {}
-    for name, p in (("plain", None), ("closure", params)):
+    runs = [("plain", None)] + [(f"closure_s{k}_g{g:g}", scaled_output(p, g)) for g in gains for k, p in enumerate(nets)]
+    for name, p in runs:
         with L.Lattice(ccfg) as c:
             L.lbm_init_device(c.ctx, rc0.data_ptr(), uc0.data_ptr())
             if p is not None:
                 L.lbm_set_closure(c.ctx, p)
+            t_c = run_window(L, torch, c, c_settle, cevery, None, f"coarse {name}")
             cs = ProfileStats(torch, cshape[1])
-            t_c = run_window(L, torch, c, cstats, cevery, cs, f"coarse {name}")
+            c_ub = []
+            t_c += run_window(L, torch, c, c_stats, cevery, cs, f"coarse {name}", None, c_ub)
             dc = c.diagnostics()
         pr = cs.result()
-        res[name] = {"wall_s": t_c, "steps": cstats, "u_tau_end": friction_velocity(dc, cshape[0], cshape[2]),
-                     "u_bulk_end": dc["momentum"][0] / dc["mass"], "profile": pr}
+        res[name] = {"wall_s": t_c, "steps": c_settle + c_stats, "stats_steps": c_stats,
+                     "u_tau_end": friction_velocity(dc, cshape[0], cshape[2]),
+                     "u_bulk_over_u_tau": float(np.mean(c_ub) / ut), "u_bulk_std_over_u_tau": float(np.std(c_ub) / ut),
+                     "profile": pr}
+    ub_f = out["fine"]["u_bulk_over_u_tau"]
     for name in res:
         pr = res[name].pop("profile")
+        res[name]["u_bulk_rel_err_vs_fine"] = abs(res[name]["u_bulk_over_u_tau"] - ub_f) / ub_f
         res[name]["rel_l2_U_vs_filtered_fine"] = float(np.sqrt(np.sum((pr["U"] - filt["U"]) ** 2) /
                                                                np.sum(filt["U"] ** 2)))
         for q in ("u_rms", "v_rms", "w_rms"):
             res[name][f"rel_l2_{q}_vs_filtered_fine"] = float(np.sqrt(np.sum((pr[q] - filt[q]) ** 2) /
                                                                       np.sum(filt[q] ** 2)))
         res[name]["U_over_u_tau"] = [round(float(v) / ut, 4) for v in pr["U"][: cshape[1] // 2]]
-        log(f"coarse {name}: U rel L2 {res[name]['rel_l2_U_vs_filtered_fine']:.4f}, u_tau {res[name]['u_tau_end']:.5f}")
+        log(f"coarse {name}: U_b/u_tau {res[name]['u_bulk_over_u_tau']:.3f} (fine {ub_f:.3f}), "
+            f"U rel L2 {res[name]['rel_l2_U_vs_filtered_fine']:.4f}, "
+            f"u_rms {res[name]['rel_l2_u_rms_vs_filtered_fine']:.4f}, v_rms {res[name]['rel_l2_v_rms_vs_filtered_fine']:.4f}")
+    summary = {}
+    for g in gains:
+        names = [f"closure_s{k}_g{g:g}" for k in range(args.seeds)]
+        summary[f"gain {g:g}"] = {q: [float(np.mean([res[n][q] for n in names])), float(np.std([res[n][q] for n in names]))]
+                                  for q in ("u_bulk_over_u_tau", "u_bulk_rel_err_vs_fine", "rel_l2_U_vs_filtered_fine",
+                                            "rel_l2_u_rms_vs_filtered_fine", "rel_l2_v_rms_vs_filtered_fine",
+                                            "rel_l2_w_rms_vs_filtered_fine")}
+        log(f"gain {g:g} over {args.seeds} networks (mean, std): {summary[f'gain {g:g}']}")
     out["coarse"] = res
+    out["closure_summary"] = summary
     out["coarse_start_after_fine_steps"] = n_trans
     out["filtered_fine_U_over_u_tau"] = [round(float(v) / ut, 4) for v in filt["U"][: cshape[1] // 2]]
     out["filtered_fine_rms_over_u_tau"] = {q: [round(float(v) / ut, 4) for v in filt[q][: cshape[1] // 2]]

@@ -91,9 +91,9 @@ SIGNATURES = {
     "lbm_set_closure": (ctypes.c_int, [_ctx, _fp]),
     "lbm_closure_features": (ctypes.c_int, [_ctx, _vp]),
     "lbm_closure_eval": (ctypes.c_int, [_fp, _vp, _vp, ctypes.c_int64, _vp]),
-    "lbm_coarsen": (ctypes.c_int, [_ctx, _vp, _vp, _vp]),
+    "lbm_coarsen": (ctypes.c_int, [_ctx, _vp, _vp, _vp, _vp]),
     "lbm_init_device": (ctypes.c_int, [_ctx, _vp, _vp]),
-    "lbm_closure_targets": (ctypes.c_int, [_ctx, _vp, _vp, _vp, ctypes.c_double, _vp]),
+    "lbm_closure_targets": (ctypes.c_int, [_ctx, _vp, _vp, _vp, _vp, ctypes.c_double, _vp]),
     "lbm_mlp_create": (ctypes.c_int, [ctypes.c_uint64, _vp, ctypes.POINTER(_mlp)]),
     "lbm_mlp_set_params": (ctypes.c_int, [_mlp, _fp]),
     "lbm_mlp_get_params": (ctypes.c_int, [_mlp, _fp]),
@@ -398,16 +398,16 @@ def lbm_closure_eval(params: np.ndarray, x_ptr: int, nu_ptr: int, n: int, stream
     _check_mlp(load().lbm_closure_eval(_f32(p), x_ptr, nu_ptr, int(n), stream))
 
 
-def lbm_coarsen(ctx, rho_ptr: int, u_ptr: int, tau_ptr: int):
-    _check(load().lbm_coarsen(ctx, rho_ptr, u_ptr, tau_ptr), ctx)
+def lbm_coarsen(ctx, rho_ptr: int, u_ptr: int, tau_ptr: int, sbar_ptr: Optional[int] = None):
+    _check(load().lbm_coarsen(ctx, rho_ptr, u_ptr, tau_ptr, sbar_ptr), ctx)
 
 
 def lbm_init_device(ctx, rho_ptr: int, u_ptr: int):
     _check(load().lbm_init_device(ctx, rho_ptr, u_ptr), ctx)
 
 
-def lbm_closure_targets(ctx, rho_ptr: int, u_ptr: int, tau_ptr: int, eps_rel: float, y_ptr: int):
-    _check(load().lbm_closure_targets(ctx, rho_ptr, u_ptr, tau_ptr, float(eps_rel), y_ptr), ctx)
+def lbm_closure_targets(ctx, rho_ptr: int, u_ptr: int, tau_ptr: int, sbar_ptr: int, eps_rel: float, y_ptr: int):
+    _check(load().lbm_closure_targets(ctx, rho_ptr, u_ptr, tau_ptr, sbar_ptr, float(eps_rel), y_ptr), ctx)
 
 
 class MLP:

@@ -128,13 +128,113 @@ def test_strain_of_a_shear_wave_is_the_centred_difference():
 
 
 def test_targets_recover_an_exact_eddy_viscosity():
+    """A sub-filter stress that is exactly -2 rho nu0 S, with the filtered fine
+    strain equal to the coarse one, is nu0 on the off-diagonal groups; the trace
+    and the normal-stress differences get no eddy viscosity."""
     rng = np.random.default_rng(2)
     S = rng.standard_normal((6, 3, 4, 5))
     rho = 1 + 0.01 * rng.standard_normal((3, 4, 5))
     nu0 = 2.5e-4
     tau = -2 * rho[None] * nu0 * S
-    nu = C.targets(rho, tau, S, eps_rel=0.0)
-    np.testing.assert_allclose(nu[[0, 1, 2, 4, 5]], nu0, rtol=1e-12)
-    np.testing.assert_array_equal(nu[3], 0.0)
+    nu = C.targets(rho, tau, S, S, 1e-3, eps_rel=0.0)
+    np.testing.assert_allclose(nu[[0, 1, 2]], nu0, rtol=1e-12)
+    np.testing.assert_array_equal(nu[3:], 0.0)
     # anti-diffusive stress is clipped to zero viscosity
-    assert np.all(C.targets(rho, -tau, S, eps_rel=0.0) == 0.0)
+    assert np.all(C.targets(rho, -tau, S, S, 1e-3, eps_rel=0.0) == 0.0)
+    np.testing.assert_allclose(C.targets(rho, -tau, S, S, 1e-3, eps_rel=0.0, clip=False)[:3], -nu0, rtol=1e-12)
+
+
+def test_targets_recover_the_missing_viscous_stress():
+    """No sub-filter stress, but the filtered fine strain is (1 + a) times the
+    coarse strain: the coarse node needs the viscosity nu (1 + a), so
+    nu* = a nu per group (each group with its own nu)."""
+    rng = np.random.default_rng(3)
+    S = rng.standard_normal((6, 2, 3, 4))
+    rho = 1 + 0.01 * rng.standard_normal((2, 3, 4))
+    a = np.array([0.3, 0.1, 0.25])
+    Sbar = S.copy()
+    Sbar[3:] *= (1 + a)[:, None, None, None]
+    nus = np.array([4e-4, 5e-4, 6e-4])
+    nu = C.targets(rho, np.zeros_like(S), S, Sbar, nus, eps_rel=0.0)
+    for j in range(3):
+        np.testing.assert_allclose(nu[j], a[j] * nus[j], rtol=1e-12)
+    # with eps > 0 the least-squares fit shrinks by S^2 / (S^2 + eps^2)
+    nu_e = C.targets(rho, np.zeros_like(S), S, Sbar, nus, eps_rel=0.5)
+    eps2 = 0.25 * np.mean(S[:3] ** 2 + 2 * S[3:] ** 2)
+    np.testing.assert_allclose(nu_e[0], a[0] * nus[0] * S[3] ** 2 / (S[3] ** 2 + eps2), rtol=1e-12)
+
+
+def _profile_field(ny, fn):
+    """u_x = fn(y) on fine rows y = 0..ny-1, uniform in x and z; rho = 1."""
+    y = np.arange(ny, dtype=np.float64)
+    u = np.zeros((3, 4, ny, 4))
+    u[0] = fn(y)[None, :, None]
+    return np.ones((4, ny, 4)), u
+
+
+def test_filtered_strain_of_polynomial_profiles():
+    """Centred differences are exact for quadratics, so for u_x = A y + B y^2 the
+    filtered fine strain equals the coarse strain of the filtered velocity away
+    from the walls; for u_x = C y^3 both stencils are off by a known amount and
+    Sbar_xy - S_xy = -3 C on every interior coarse row (worked by hand: fine
+    S_xy = C (3 y^2 + 1) / 2, filtered and doubled C (12 k^2 + 6 k + 5/2); the
+    filtered velocity C (16 k^3 + 12 k^2 + 6 k + 1) / 2 gives
+    S_xy = C (12 k^2 + 6 k + 11/2))."""
+    ny = 12
+    rows = slice(1, ny // 2 - 1)  # coarse rows whose stencils stay off the walls
+    for walls in (False, True):
+        rho, u = _profile_field(ny, lambda y: 0.01 * y + 0.002 * y * y)
+        rb, ut, _ = C.box_filter(rho, u)
+        Sb = C.filtered_strain(rho, u, walls)
+        Sc = C.strain(ut, walls)
+        np.testing.assert_allclose(Sb[3][:, rows], Sc[3][:, rows], rtol=1e-13)
+        k = np.arange(ny // 2)[rows]
+        np.testing.assert_allclose(Sb[3][0, rows, 0], 0.01 + 0.002 * (4 * k + 1), rtol=1e-13)
+        Cc = 1e-4
+        rho, u = _profile_field(ny, lambda y: Cc * y ** 3)
+        rb, ut, _ = C.box_filter(rho, u)
+        Sb = C.filtered_strain(rho, u, walls)
+        Sc = C.strain(ut, walls)
+        np.testing.assert_allclose(Sb[3][0, rows, 0], Cc * (12 * k * k + 6 * k + 2.5), rtol=1e-13)
+        np.testing.assert_allclose(Sc[3][0, rows, 0], Cc * (12 * k * k + 6 * k + 5.5), rtol=1e-13)
+        np.testing.assert_allclose((Sb[3] - Sc[3])[:, rows], -3 * Cc, rtol=1e-12)
+        np.testing.assert_allclose(Sb[[0, 1, 2, 4, 5]], 0.0, atol=1e-18)
+
+
+def test_filtered_strain_matches_a_loop_over_boxes():
+    """Brute force on a tiny grid with varying density: for every coarse node,
+    loop over its eight fine nodes, difference u by explicit neighbour indices
+    (periodic, or the mirrored value with flipped sign across a y wall), weight
+    by rho, average, and double."""
+    rng = np.random.default_rng(9)
+    nz, ny, nx = 4, 6, 4
+    rho = 1 + 0.05 * rng.standard_normal((nz, ny, nx))
+    u = 0.03 * rng.standard_normal((3, nz, ny, nx))
+    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    for walls in (False, True):
+        def uval(c, z, y, x):
+            x %= nx
+            z %= nz
+            if walls and (y < 0 or y >= ny):
+                return -u[c, z, min(max(y, 0), ny - 1), x]
+            return u[c, z, y % ny, x]
+
+        ref = np.zeros((6, nz // 2, ny // 2, nx // 2))
+        for Z in range(nz // 2):
+            for Y in range(ny // 2):
+                for X in range(nx // 2):
+                    acc = np.zeros(6)
+                    rsum = 0.0
+                    for z in (2 * Z, 2 * Z + 1):
+                        for y in (2 * Y, 2 * Y + 1):
+                            for x in (2 * X, 2 * X + 1):
+                                g = np.zeros((3, 3))  # g[i][j] = d_i u_j
+                                for c in range(3):
+                                    g[0][c] = 0.5 * (uval(c, z, y, x + 1) - uval(c, z, y, x - 1))
+                                    g[1][c] = 0.5 * (uval(c, z, y + 1, x) - uval(c, z, y - 1, x))
+                                    g[2][c] = 0.5 * (uval(c, z + 1, y, x) - uval(c, z - 1, y, x))
+                                for k, (i, j) in enumerate(pairs):
+                                    acc[k] += rho[z, y, x] * 0.5 * (g[i][j] + g[j][i])
+                                rsum += rho[z, y, x]
+                    ref[:, Z, Y, X] = 2.0 * acc / rsum
+        np.testing.assert_allclose(C.filtered_strain(rho, u, walls), ref, rtol=1e-12, atol=1e-16)

@@ -174,20 +174,27 @@ def test_coarsen_and_targets_match_oracle(walls):
         rd = torch.zeros(nc, dtype=torch.float64, device="cuda")
         ud = torch.zeros(3 * nc, dtype=torch.float64, device="cuda")
         td = torch.zeros(6 * nc, dtype=torch.float64, device="cuda")
+        sd = torch.zeros(6 * nc, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
-        L.lbm_coarsen(fine.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr())
+        L.lbm_coarsen(fine.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), sd.data_ptr())
         fine.synchronize()
     rho, u = O.macroscopic(g, F)
     rb, ut, tau = C.box_filter(rho, u)
+    sbar = C.filtered_strain(rho, u, walls)
     cshape = (shape[0] // 2, shape[1] // 2, shape[2] // 2)
     np.testing.assert_allclose(rd.cpu().numpy().reshape(rb.shape), rb, rtol=1e-13)
     np.testing.assert_allclose(ud.cpu().numpy().reshape(ut.shape), ut, rtol=1e-11, atol=1e-15)
     np.testing.assert_allclose(td.cpu().numpy().reshape(tau.shape), tau, rtol=1e-9, atol=1e-15)
-    with L.Lattice(L.Config(*cshape, storage="f64", walls_y=walls, nu=0.01)) as coarse:
+    np.testing.assert_allclose(sd.cpu().numpy().reshape(sbar.shape), sbar, rtol=1e-10,
+                               atol=1e-12 * np.abs(sbar).max())
+    nu_c = 0.01
+    with L.Lattice(L.Config(*cshape, storage="f64", walls_y=walls, nu=nu_c)) as coarse:
         yd = torch.zeros((nc, 6), dtype=torch.float32, device="cuda")
         torch.cuda.synchronize()
-        L.lbm_closure_targets(coarse.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), 0.1, yd.data_ptr())
-    ref = C.targets(rb, tau, C.strain(ut, walls), eps_rel=0.1)
+        L.lbm_closure_targets(coarse.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), sd.data_ptr(), 0.1,
+                              yd.data_ptr())
+    ref = C.targets(rb, tau, C.strain(ut, walls), sbar, nu_c, eps_rel=0.1)
+    assert np.abs(ref[:3]).max() > 0
     got = np.moveaxis(yd.cpu().numpy().reshape(cshape[::-1] + (6,)), -1, 0)
     np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max() + 1e-30)
 
@@ -288,8 +295,9 @@ def test_closure_pipeline_end_to_end():
         rd = torch.zeros(nc, dtype=torch.float64, device="cuda")
         ud = torch.zeros(3 * nc, dtype=torch.float64, device="cuda")
         td = torch.zeros(6 * nc, dtype=torch.float64, device="cuda")
+        sd = torch.zeros(6 * nc, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
-        L.lbm_coarsen(fine.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr())
+        L.lbm_coarsen(fine.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), sd.data_ptr())
         fine.synchronize()
     cshape = tuple(s // 2 for s in fine_shape)
     ccfg = L.Config(*cshape, storage="f32", walls_y=True, nu=nu_f / 2, force=(2 * F_f, 0, 0))
@@ -299,10 +307,12 @@ def test_closure_pipeline_end_to_end():
     with L.Lattice(ccfg) as coarse:
         L.lbm_init_device(coarse.ctx, rd.data_ptr(), ud.data_ptr())
         L.lbm_closure_features(coarse.ctx, xd.data_ptr())
-        L.lbm_closure_targets(coarse.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), 0.1, yd.data_ptr())
+        L.lbm_closure_targets(coarse.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), sd.data_ptr(), 0.1,
+                              yd.data_ptr())
         coarse.synchronize()
     y = yd.cpu().numpy()
-    assert np.all(np.isfinite(xd.cpu().numpy())) and np.all(y >= 0) and y.max() > 0
+    assert np.all(np.isfinite(xd.cpu().numpy())) and np.all(y >= 0) and y[:, :3].max() > 0
+    assert np.all(y[:, 3:] == 0)
     m = L.MLP(seed=1)
     m.fit_normalisation(xd.data_ptr(), yd.data_ptr(), nc)
     l0, _ = m.loss_grad(xd.data_ptr(), yd.data_ptr(), nc)
