@@ -69,9 +69,9 @@ struct Rates {
 // W * (1, 0, 1/3).
 template <typename T, int WNUM_IS_ZERO>
 __host__ __device__ __forceinline__ void fwd3(T& a0, T& a1, T& a2, T u, T W) {
-  const T s0 = a0 + a1 + a2;
-  const T d1 = a2 - a0;
   const T sp = a2 + a0;
+  const T s0 = sp + a1;
+  const T d1 = a2 - a0;
   const T S = WNUM_IS_ZERO ? s0 : s0 + W;
   a0 = s0;
   a1 = d1 - u * S;
@@ -163,20 +163,24 @@ __host__ __device__ __forceinline__ void inverse_all(T (&v)[3][3][3], T ux, T uy
 }
 
 // Macroscopic fields from the deviation cube: rho' = sum delta, j = sum delta e.
+// The sums are the line sums and differences of the forward sweeps, in the
+// same order, so the compiler computes them once for both.
 template <typename T>
 __host__ __device__ __forceinline__ void density_momentum(const T (&v)[3][3][3], T& rhop, T& jx, T& jy, T& jz) {
-  T s[3][3];
+  T s[3][3], p[3];
   jx = T(0);
 #pragma unroll
   for (int iz = 0; iz < 3; ++iz)
 #pragma unroll
     for (int iy = 0; iy < 3; ++iy) {
-      s[iz][iy] = v[iz][iy][0] + v[iz][iy][1] + v[iz][iy][2];
+      s[iz][iy] = (v[iz][iy][2] + v[iz][iy][0]) + v[iz][iy][1];
       jx += v[iz][iy][2] - v[iz][iy][0];
     }
+#pragma unroll
+  for (int iz = 0; iz < 3; ++iz) p[iz] = (s[iz][2] + s[iz][0]) + s[iz][1];
   jy = (s[0][2] - s[0][0]) + (s[1][2] - s[1][0]) + (s[2][2] - s[2][0]);
-  jz = (s[2][0] - s[0][0]) + (s[2][1] - s[0][1]) + (s[2][2] - s[0][2]);
-  rhop = (s[0][0] + s[0][1] + s[0][2]) + (s[1][0] + s[1][1] + s[1][2]) + (s[2][0] + s[2][1] + s[2][2]);
+  jz = p[2] - p[0];
+  rhop = (p[2] + p[0]) + p[1];
 }
 
 // ---------------------------------------------------------------------------
