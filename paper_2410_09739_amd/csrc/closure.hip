@@ -123,15 +123,14 @@ __global__ __launch_bounds__(256, 3) void k_stream_collide_closure(const typenam
 }
 
 // Features of the next collision at every node (no collision, no store):
-// x[i][27], i = x + nx (y + ny z).  Block (64, 4): one x segment of one row
-// per wavefront, as pull() requires.
+// x[i][27], i = x + nx (y + ny z).  Launched like the step kernel: one x
+// segment of one row per wavefront, as pull() requires.
 template <int ST, bool WALLS, bool FORCE>
 __global__ __launch_bounds__(256) void k_closure_features(const typename Stor<ST>::S* __restrict__ src,
                                                           StepArgs<typename Stor<ST>::R> A, float* __restrict__ out) {
   using T = typename Stor<ST>::R;
   int x, y, z;
-  wave_segment(x, y, z);
-  if (x >= A.g.nx) return;
+  if (!wave_segment(A.g, x, y, z) || x >= A.g.nx) return;
   T v[3][3][3];
   pull<ST, WALLS>(src, A.g, x, y, z, v);
   T rhop, rho, ux, uy, uz;

@@ -31,8 +31,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>:
                                                         StepArgs<typename Stor<ST>::R> A) {
   using T = typename Stor<ST>::R;
   int x, y, z;
-  wave_segment(x, y, z);
-  if (x >= A.g.nx) return;
+  if (!wave_segment(A.g, x, y, z) || x >= A.g.nx) return;
   T v[3][3][3];
   if (BC == 2) pull_box<ST>(src, A.g, A.box, x, y, z, v);
   else pull<ST, BC == 1>(src, A.g, x, y, z, v);
@@ -298,11 +297,24 @@ size_t elem_size(int st);
 // Launch shape of the step kernels: 1D blocks of up to 4 wavefronts, each
 // one 64-node x segment of one row (wave_segment); for nx = 256 a block is one
 // row.
+// Every block full either way: one block row per (y, z) when the row splits
+// into whole blocks (nxs <= 4 or a multiple of 4), else the flat grid.
+static bool flat_grid(int nx, int ny, int nz) {
+  const int nxs = (nx + SEG - 1) / SEG;
+  return !(nxs <= SEGS_PER_BLOCK || nxs % SEGS_PER_BLOCK == 0) || ny > 65535 || nz > 65535;
+}
+
 void step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid) {
   const int nxs = (nx + SEG - 1) / SEG;
-  const int w = nxs < 4 ? nxs : 4;
-  block = dim3(SEG * w, 1, 1);
-  grid = dim3((nxs + w - 1) / w, ny, nz);
+  if (flat_grid(nx, ny, nz)) {
+    const int64_t nseg = (int64_t)nxs * ny * nz;  // below 2^31 (lbm_create)
+    block = dim3(SEG * SEGS_PER_BLOCK, 1, 1);
+    grid = dim3((unsigned)((nseg + SEGS_PER_BLOCK - 1) / SEGS_PER_BLOCK), 1, 1);
+  } else {
+    const int w = nxs < SEGS_PER_BLOCK ? nxs : SEGS_PER_BLOCK;
+    block = dim3(SEG * w, 1, 1);
+    grid = dim3((nxs + w - 1) / w, ny, nz);
+  }
 }
 
 // storage layout of a configuration (see lbm_internal.hpp)
@@ -314,6 +326,9 @@ static Geom make_geom(const lbm_config* cfg) {
   g.nxs = (cfg->nx + SEG - 1) / SEG;
   g.nxp = g.nxs * SEG;
   g.rowlen = (int64_t)LBM_Q * g.nxp;
+  g.by_nxs = make_div31((uint32_t)g.nxs);
+  g.by_ny = make_div31((uint32_t)g.ny);
+  g.flat = flat_grid(g.nx, g.ny, g.nz) ? 1 : 0;
   return g;
 }
 
@@ -390,8 +405,6 @@ extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   const size_t es = elem_size(cfg->storage);
   if (!es) return set_err(nullptr, LBM_EINVAL, "lbm_create: unknown storage %d", cfg->storage);
   const Geom geo = make_geom(cfg);
-  if (cfg->ny > 65535 || cfg->nz > 65535)
-    return set_err(nullptr, LBM_EINVAL, "lbm_create: ny and nz must be <= 65535 (launch grid)");
   if ((uint64_t)geo.rowlen * es >= ((uint64_t)1 << 32))
     return set_err(nullptr, LBM_EINVAL, "lbm_create: one row of the state must stay below 4 GiB");
   if (cfg->walls_y != 0 && cfg->walls_y != 1) return set_err(nullptr, LBM_EINVAL, "lbm_create: walls_y must be 0 or 1");

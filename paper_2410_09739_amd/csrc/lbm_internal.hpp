@@ -119,11 +119,30 @@ __device__ __forceinline__ uint32_t node_hash(uint32_t node, uint32_t step) {
 // direction arrays: FP32 +11 %, FP64 +5 %, BF16 +7 %, FP16 +2 %.
 constexpr int SEG = 64;
 
+// Division of numerators below 2^31 by an invariant d >= 1 as a multiply and
+// a shift (Granlund and Montgomery, 1994): with l = ceil(log2 d) and
+// m = ceil(2^(31+l) / d) < 2^32, floor(n / d) = (n m) >> (31 + l).
+struct Div31 {
+  uint32_t m;
+  uint32_t shift;  // 31 + l
+  __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    return (uint32_t)(((uint64_t)n * m) >> shift);
+  }
+};
+inline Div31 make_div31(uint32_t d) {
+  uint32_t l = 0;
+  while (((uint64_t)1 << l) < d) ++l;
+  const uint64_t p = (uint64_t)1 << (31 + l);
+  return Div31{(uint32_t)((p + d - 1) / d), 31 + l};
+}
+
 struct Geom {
   int nx, ny, nz;
   int nxs;         // x segments per row, ceil(nx / SEG)
   int nxp;         // nx rounded up to a multiple of SEG
   int64_t rowlen;  // values per (y, z) row: 27 nxp
+  Div31 by_nxs, by_ny;  // wavefront -> (segment, row) of the step kernels (flat grid)
+  int flat;             // 1: flat grid over all row segments; 0: one block row per (y, z)
 };
 
 // position of x inside a row, in values
@@ -375,13 +394,31 @@ inline Box<T> box_args(const lbm_ctx* c) {
 inline int wall_mask(const lbm_ctx* c) {
   return (c->cfg.walls_y ? 1 : 0) | (c->cfg.walls_x ? 2 : 0) | (c->cfg.walls_z ? 4 : 0) | (c->cfg.sym_top ? 8 : 0);
 }
-// wavefront -> (x segment, row) for the step kernels: 1D blocks of 64 W
-// threads, W = min(4, nxs) wavefronts on consecutive x segments of one row,
-// grid (ceil(nxs / W), ny, nz); y and z come straight from the block index
-__device__ __forceinline__ void wave_segment(int& x, int& y, int& z) {
-  x = blockIdx.x * blockDim.x + threadIdx.x;
-  y = blockIdx.y;
-  z = blockIdx.z;
+// wavefront -> (x segment, row) for the step kernels.  The grid is 1D over
+// the nxs ny nz row segments in row-major order (x segment fastest), four
+// wavefronts of one segment each per block, so every block but the last is
+// full whatever nxs is.  The hardware hands consecutive blocks to the eight
+// XCDs in turn: with one block per row and a partial last block (nxs = 5..7)
+// every partial block would land on the same four XCDs and the other four
+// would carry up to 4/nxs of the work.  Each wavefront keeps one segment of
+// one row (y, z uniform, as pull() needs).  false: a wavefront past the end.
+constexpr int SEGS_PER_BLOCK = 4;
+__device__ __forceinline__ bool wave_segment(const Geom& g, int& x, int& y, int& z) {
+  if (!g.flat) {  // grid (ceil(nxs / W), ny, nz), blocks of W = min(4, nxs) segments
+    x = blockIdx.x * blockDim.x + threadIdx.x;
+    y = blockIdx.y;
+    z = blockIdx.z;
+    return true;
+  }
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t s = blockIdx.x * (uint32_t)SEGS_PER_BLOCK + w;  // below 2^31
+  const uint32_t row = g.by_nxs.div(s);
+  if (row >= (uint32_t)g.ny * (uint32_t)g.nz) return false;
+  const uint32_t zz = g.by_ny.div(row);
+  y = (int)(row - zz * (uint32_t)g.ny);
+  z = (int)zz;
+  x = (int)(s - row * (uint32_t)g.nxs) * SEG + (int)(threadIdx.x & 63);
+  return true;
 }
 size_t elem_size(int st);
 int alloc_scratch(lbm_ctx* c);

@@ -315,6 +315,34 @@ def test_small_force_momentum_is_kept_by_stochastic_rounding(storage, tol):
     assert gain == pytest.approx(400 * n * F[0], rel=tol)
 
 
+# ------------------------------------------------------------------ launch grids
+@pytest.mark.parametrize("shape,storage,kw", [
+    ((320, 3, 2), "f64", dict(walls_y=True, force=(3e-5, -2e-5, 1e-5))),    # 5 segments per row
+    ((400, 2, 3), "f64", dict(force=(1e-4, 0.0, 0.0))),                       # 7, the last one ragged
+    ((384, 3, 3), "f64", dict(walls_y=True, walls_x=True, walls_z=True, lid_velocity=(0.03, 0.0, 0.0))),
+    ((320, 3, 2), "f16dev", dict(walls_y=True, force=(3e-5, 0.0, 0.0))),
+])
+def test_flat_launch_grid_matches_oracle(shape, storage, kw):
+    """Rows of 5 to 7 x segments run on the flat grid, whose blocks span rows
+    (every block full): FP64 equals the oracle to 1e-12, FP16 deviation storage
+    stays within its per-step bound, with walls, a lid and a ragged last segment."""
+    g0 = _state(shape, seed=31 + shape[0], amp=0.05)
+    om = O.omega_table(0.02)
+    steps = 4
+    walls = ("x" if kw.get("walls_x") else "") + ("y" if kw.get("walls_y") else "") + ("z" if kw.get("walls_z") else "")
+    lid = kw.get("lid_velocity")
+    ref = O.run(g0, om, kw.get("force", (0.0, 0.0, 0.0)), walls=walls, lid=lid, steps=steps)
+    nx, ny, nz = shape
+    with L.Lattice(L.Config(nx, ny, nz, storage=storage, nu=0.02, **kw)) as lat:
+        lat.set_f(g0)
+        lat.step(steps)
+        got = lat.get_f()
+    if storage == "f64":
+        assert _rel(got, ref) <= 1e-12
+    else:
+        assert np.all(np.abs(got - ref) <= _tol(storage, steps, ref))
+
+
 # ------------------------------------------------------------------ Maxwellian comparison model
 @pytest.mark.parametrize("shape,walls,force", [((13, 10, 9), False, (0, 0, 0)), ((32, 8, 5), True, (3e-5, -2e-5, 1e-5)),
                                                ((256, 6, 3), True, (1e-5, 0, 0))])
