@@ -194,7 +194,8 @@ def main():
     if args.closure_steps > 0:
         cshape = (192, 96, 96)
         params = closure_params()
-        for st, use in [("f32", False), ("f16dev", False), ("f32", True), ("f16dev", True)]:
+        for st, use in [("f32", False), ("f16dev", False), ("bf16dev", False), ("f32", True), ("f16dev", True),
+                        ("bf16dev", True)]:
             key = st + ("+closure" if use else "")
             closure[key] = run_closure_form(L, torch, st, cshape, nu / 2, 2 * F, args.closure_steps, 20,
                                             params if use else None)

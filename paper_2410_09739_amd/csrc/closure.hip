@@ -79,8 +79,7 @@ __device__ __forceinline__ void closure_rates(const float (&nu)[NOUT], const flo
 
 struct ClosureArgs {
   float inv_w[6];  // 1 / omega_4..omega_9
-  int nxs;         // 64-node segments per x row
-  int64_t nseg;    // segments in the grid
+  uint32_t nseg;   // segments in the grid (below 2^31)
 };
 
 // Fused stream + collide with the closure.  Each wavefront takes one 64-node
@@ -103,11 +102,10 @@ __global__ __launch_bounds__(256, 3) void k_stream_collide_closure(const typenam
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   __bf16* xs = lx + wave * XTILE;
-  for (int64_t s = (int64_t)blockIdx.x * 4 + wave; s < C.nseg; s += (int64_t)gridDim.x * 4) {
-    const int xseg = (int)(s % C.nxs);
-    const int64_t row = s / C.nxs;
-    const int y = (int)(row % A.g.ny), z = (int)(row / A.g.ny);
-    const int x = xseg * 64 + lane;
+  for (uint32_t s = blockIdx.x * 4u + (uint32_t)wave; s < C.nseg; s += gridDim.x * 4u) {
+    const uint32_t row = A.g.by_nxs.div(s), zz = A.g.by_ny.div(row);
+    const int y = (int)(row - zz * (uint32_t)A.g.ny), z = (int)zz;
+    const int x = (int)(s - row * (uint32_t)A.g.nxs) * 64 + lane;
     T v[3][3][3];
     pull<ST, WALLS>(src, A.g, x, y, z, v);
     T rhop, rho, ux, uy, uz;
@@ -555,8 +553,7 @@ static int closure_steps(lbm_ctx* c, int64_t nsteps) {
   const StepArgs<T> A = step_args<T>(c);
   ClosureArgs C;
   for (int k = 0; k < 6; ++k) C.inv_w[k] = c->closure_inv_w[k];
-  C.nxs = c->cfg.nx / 64;
-  C.nseg = (int64_t)C.nxs * c->cfg.ny * c->cfg.nz;
+  C.nseg = (uint32_t)((int64_t)(c->cfg.nx / 64) * c->cfg.ny * c->cfg.nz);  // below 2^31 (lbm_create)
   // persistent grid: as many blocks as stay resident, then trimmed so that
   // every wavefront runs the same number of segments
   int resident = 0;
