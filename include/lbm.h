@@ -49,7 +49,9 @@
  * Ownership: the library owns the device memory it allocates (two state
  *   buffers of 27 * N values plus small scratch); every pointer the caller
  *   passes stays the caller's and is never retained past the call.
- * Threads: one context must not be used by two host threads at once.
+ * Threads: one context must not be used by two host threads at once.  The
+ *   error text of a call without a context (lbm_last_error(NULL),
+ *   lbm_mlp_last_error(NULL)) is kept per host thread.
  */
 #ifndef LBM_H
 #define LBM_H

@@ -555,17 +555,20 @@ static int closure_steps(lbm_ctx* c, int64_t nsteps) {
   for (int k = 0; k < 6; ++k) C.inv_w[k] = c->closure_inv_w[k];
   C.nseg = (uint32_t)((int64_t)(c->cfg.nx / 64) * c->cfg.ny * c->cfg.nz);  // below 2^31 (lbm_create)
   // persistent grid: as many blocks as stay resident, then trimmed so that
-  // every wavefront runs the same number of segments
-  int resident = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, (const void*)k_stream_collide_closure<ST, true, true>, 256,
-                                                   0) != hipSuccess || resident < 1)
-    resident = 1;
-  int cus = 0;
-  HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-  const int64_t want = (C.nseg + 3) / 4;
-  const int64_t slots = (int64_t)resident * (cus > 0 ? cus : 1);
-  const int64_t rounds = (want + slots - 1) / slots;
-  const int grid = (int)((want + rounds - 1) / rounds);
+  // every wavefront runs the same number of segments (sized on first use)
+  if (!c->closure_grid) {
+    int resident = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, (const void*)k_stream_collide_closure<ST, true, true>,
+                                                     256, 0) != hipSuccess || resident < 1)
+      resident = 1;
+    int cus = 0;
+    HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    const int64_t want = (C.nseg + 3) / 4;
+    const int64_t slots = (int64_t)resident * (cus > 0 ? cus : 1);
+    const int64_t rounds = (want + slots - 1) / slots;
+    c->closure_grid = (int)((want + rounds - 1) / rounds);
+  }
+  const int grid = c->closure_grid;
   const bool walls = c->cfg.walls_y != 0;
   const bool force = c->cfg.force[0] != 0.0 || c->cfg.force[1] != 0.0 || c->cfg.force[2] != 0.0;
   StepArgs<T> As = A;
@@ -646,7 +649,8 @@ extern "C" int lbm_closure_features(lbm_ctx* c, float* x_dev) {
   return LBM_OK;
 }
 
-static char g_closure_err[512] = "";
+// error text of calls without a training object, one per host thread
+static thread_local char g_closure_err[512] = "";
 
 extern "C" int lbm_closure_eval(const float* params, const float* x_dev, float* nu_dev, int64_t n, void* hip_stream) {
   if (!params || !x_dev || !nu_dev || n < 0) {

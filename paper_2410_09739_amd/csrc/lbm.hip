@@ -290,7 +290,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_final(const double* __res
 // ===========================================================================
 // host side
 
-static char g_create_err[512] = "";
+// error text of calls without a context (create), one per host thread
+static thread_local char g_create_err[512] = "";
 
 size_t elem_size(int st);
 

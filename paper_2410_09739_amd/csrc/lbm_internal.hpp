@@ -362,6 +362,7 @@ struct lbm_ctx {
   // learned closure (closure.hip): packed BF16 parameters on the device, NULL = plain method
   char* closure = nullptr;
   float closure_inv_w[6] = {0, 0, 0, 0, 0, 0};  // 1 / omega_4..9
+  int closure_grid = 0;                          // blocks of the persistent closure step (0: not sized yet)
 };
 
 int set_err(lbm_ctx* c, int code, const char* fmt, ...);
