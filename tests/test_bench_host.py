@@ -1,0 +1,43 @@
+"""Host-side checks of the benchmark contract and of the committed profile
+summaries (no GPU needed)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from paper_2410_09739_amd import profiling as P  # noqa: E402
+
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_stream_collide_channel_256x128x128.md")
+TRACE = os.path.join(ROOT, "profiles", "stream_collide_channel_256x128x128_kernel_trace.md")
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_bench_refuses_more_than_one_gpu(n):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert r.stdout.strip() == ""  # no JSON line for a multi-GPU request
+    assert "one GPU" in r.stderr + r.stdout
+
+
+def test_traffic_summary_matches_the_kernel_sources():
+    """The HBM byte counts the benchmark reports as roofline.traffic were taken
+    with the stream-collide sources as they are now (else the benchmark reports
+    null): a kernel change must come with a new measurement."""
+    t = P.read_traffic_md(TRAFFIC)
+    assert t is not None
+    assert t["kernel_source_sha"] == P.kernel_source_hash()
+    for form, algo in (("f32", 216), ("f64", 432), ("f16dev", 108), ("bf16dev", 108)):
+        f = t["forms"][form]
+        assert f["algorithmic_bytes_per_launch"] == algo * 256 * 128 * 128
+        assert 0.99 < f["traffic_over_algorithmic"] < 1.05
+
+
+def test_kernel_trace_summary_covers_the_timed_kernel():
+    text = open(TRACE).read()
+    assert "rocprofv3 --kernel-trace --stats" in text
+    assert "k_stream_collide<1, 1, true, false>" in text  # FP32, y walls, force: the benchmark's kernel
