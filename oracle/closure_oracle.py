@@ -10,9 +10,13 @@ Network (per node): x in R^27 -> h1 = relu(W1 x + b1) (64) -> h2 = relu(W2 h1 + 
 W1[64][27], b1[64], W2[64][64], b2[64], W3[6][64], b3[6] (6342 values).
 
 Features (27): from the pre-collision central moments kappa_abc (Appendix D
-Step 2) and rho: x_000 = rho - 1; otherwise (kappa_abc - rho E_abc) / rho with
-E_abc = C1[a] C1[b] C1[c], C1 = (1, 0, c_s^2), times 3^{(a+b+c)/2} (= 1/c_s^order),
-in the paper's moment order.  For training the inputs are standardised,
+Step 2) and rho: x_000 = rho - 1; x_100 = x_010 = x_001 = 0 (about the velocity
+of Step 7, which carries F/2, the first-order central moments are -F/2 whatever
+the node's state: they hold no information, and computed in FP32 from 27
+populations they are pure rounding noise that standardisation would blow up);
+otherwise (kappa_abc - rho E_abc) / rho with E_abc = C1[a] C1[b] C1[c],
+C1 = (1, 0, c_s^2), times 3^{(a+b+c)/2} (= 1/c_s^order), in the paper's moment
+order.  For training the inputs are standardised,
 (x - mu) / sigma, and the outputs scaled, o = nu_t / s_y; both are folded into
 W1, b1, W3, b3 for inference.
 
@@ -143,6 +147,7 @@ def features(kappa: np.ndarray, rho: np.ndarray) -> np.ndarray:
     shape = (27,) + (1,) * rho.ndim
     x = (kappa - rho[None] * E_REST.reshape(shape)) / rho[None] * NORM.reshape(shape)
     x[0] = rho - 1.0
+    x[1:4] = 0.0
     return np.moveaxis(x, 0, -1)
 
 

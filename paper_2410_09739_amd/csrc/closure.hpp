@@ -56,8 +56,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // features from the primed pre-collision cube (v[c][b][a] = kappa'_abc):
-// x_000 = rho - 1, x_abc = (kappa'_abc - rho' E_abc) / rho * 3^((a+b+c)/2),
-// listed in the paper's moment order.
+// x_000 = rho - 1, x_100 = x_010 = x_001 = 0 (the first-order central moments
+// are -F/2 at every node: no information, only FP32 rounding noise),
+// x_abc = (kappa'_abc - rho' E_abc) / rho * 3^((a+b+c)/2), in the paper's
+// moment order.
 template <typename T>
 __device__ __forceinline__ void features(const T (&v)[3][3][3], T rhop, T rho, float (&x)[NIN]) {
   constexpr int MM[NIN][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1},
@@ -66,8 +68,9 @@ __device__ __forceinline__ void features(const T (&v)[3][3][3], T rhop, T rho, f
                               {1, 2, 1}, {1, 1, 2}, {1, 2, 2}, {2, 1, 2}, {2, 2, 1}, {2, 2, 2}};
   const T ir = recip(rho);
   x[0] = (float)rhop;
+  x[1] = x[2] = x[3] = 0.0f;
 #pragma unroll
-  for (int k = 1; k < NIN; ++k) {
+  for (int k = 4; k < NIN; ++k) {
     const int a = MM[k][0], b = MM[k][1], c = MM[k][2];
     const double E = C1[a] * C1[b] * C1[c];
     const T kap = v[c][b][a];

@@ -90,6 +90,23 @@ def test_features_vanish_at_equilibrium_except_density():
         np.testing.assert_allclose(x[1:], 0.0, atol=1e-14)
 
 
+def test_first_order_central_moments_are_minus_half_the_force():
+    """About the Step 7 velocity (rho u = sum f e + F/2) the first-order central
+    moments of any state are -F/2: they carry nothing about the node, which is
+    why the feature map sets x_100 = x_010 = x_001 = 0."""
+    rng = np.random.default_rng(4)
+    e, _, _ = O.lattice()
+    F = np.array([3e-5, -2e-5, 1e-5])
+    f = O.feq(1.0, [0, 0, 0])[:, None] * (1 + 0.2 * rng.standard_normal((27, 50)))
+    rho, u = O.macroscopic(f, tuple(F), post_collision=False)
+    kap = C.central_moments(f, u, e)
+    for d in range(3):
+        np.testing.assert_allclose(kap[1 + d], -0.5 * F[d], rtol=0, atol=1e-16)
+    x = C.features(kap, rho)
+    assert np.all(x[:, 1:4] == 0.0)
+    assert np.all(np.abs(x[:, 4:]) > 0)
+
+
 def test_box_filter_conserves_mass_momentum_and_stress_is_a_covariance():
     rng = np.random.default_rng(1)
     rho = 1 + 0.01 * rng.standard_normal((4, 6, 8))

@@ -269,12 +269,15 @@ def test_create_clear_is_ordered_before_init(source):
 
 
 # ------------------------------------------------------------------ full size, sampled
-def test_channel_256x128x128_sampled_nodes_f32():
-    """The 256 x 128 x 128 body-force channel in FP32 storage, in the launch
-    configuration the benchmark times: after a few steps from a perturbed state,
-    the update at sampled nodes (walls, corners, interior) matches the oracle's
-    single-node evaluation of the same step from the GPU's own previous state."""
-    nx, ny, nz = 256, 128, 128
+@pytest.mark.parametrize("shape", [(256, 128, 128), (384, 192, 192)])
+def test_channel_sampled_nodes_f32(shape):
+    """The body-force channels in FP32 storage at full size: 256 x 128 x 128 in
+    the launch configuration the benchmark times (one block per row), and the
+    turbulent-channel grid 384 x 192 x 192 (six segments per row: the flat
+    grid).  After a few steps from a perturbed state, the update at sampled
+    nodes (walls, corners, interior) matches the oracle's single-node
+    evaluation of the same step from the GPU's own previous state."""
+    nx, ny, nz = shape
     nu = 0.01
     F = (8 * nu * 0.05 / ny ** 2, 0.0, 0.0)
     rho, u = W.channel_turbulent_start(nx, ny, nz, u_bulk=0.03, amp=0.1, seed=1234, kmax=2)
