@@ -208,9 +208,8 @@ def _oracle_pre_collision(g, F, walls):
     return f, rho, u, kap
 
 
-@pytest.mark.parametrize("walls", [False, True])
-def test_features_match_oracle(walls):
-    shape = (64, 5, 4)
+@pytest.mark.parametrize("walls,shape", [(False, (64, 5, 4)), (True, (64, 5, 4)), (True, (320, 3, 2))])
+def test_features_match_oracle(walls, shape):
     F = (1e-5, -2e-5, 0.0)
     g0 = _state(shape, 17)
     with L.Lattice(L.Config(*shape, storage="f64", walls_y=walls, nu=0.02, force=F)) as lat:
@@ -231,11 +230,12 @@ def test_features_match_oracle(walls):
 # hidden activation one bf16 ulp apart moves nu_t by ~1e-3 of itself, omega_j,eff
 # by ~omega^2 * 3 dnu and the populations by that times the second-order
 # non-equilibrium moments (~1e-3 here): well below 1e-6 w_alpha.
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-6), ("f32", 2e-6)])
-def test_fused_closure_step_matches_oracle(storage, tol):
+@pytest.mark.parametrize("storage,tol,shape", [("f64", 1e-6, (64, 6, 3)), ("f32", 2e-6, (64, 6, 3)),
+                                               ("f64", 1e-6, (320, 3, 2))])
+def test_fused_closure_step_matches_oracle(storage, tol, shape):
     """One fused step with the closure: the oracle streams, computes features,
-    evaluates the bf16-quantised network, sets omega_4..9 per node and collides."""
-    shape = (64, 6, 3)
+    evaluates the bf16-quantised network, sets omega_4..9 per node and collides
+    (320 wide: five segments per row, the persistent loop's row mapping)."""
     F = (1e-5, 0.0, -1e-5)
     walls = True
     nu = 0.005
