@@ -56,7 +56,10 @@ struct StorF16 {
   static __device__ __forceinline__ S enc(R r, int a, double f = 1.0, uint32_t rnd = 0) {
     const float x = r * (float)(dev_scale(a) * f);
     if (SR) {
-      f16x2_t h = {};
+      // the conversion writes the low half and keeps the high one, which is
+      // never stored: seed it with x's own bits (x is dead afterwards), so
+      // no register has to be cleared first
+      f16x2_t h = __builtin_bit_cast(f16x2_t, x);
       h = __builtin_amdgcn_cvt_sr_f16_f32(h, x, rnd, false);
       return h[0];
     }
@@ -78,7 +81,7 @@ struct StorBF16 {
   static __device__ __forceinline__ S enc(R r, int a, double f = 1.0, uint32_t rnd = 0) {
     const float x = r * (float)(dev_scale(a) * f);
     if (SR) {
-      bf16x2_t h = {};
+      bf16x2_t h = __builtin_bit_cast(bf16x2_t, x);  // high half never stored (see StorF16)
       h = __builtin_amdgcn_cvt_sr_bf16_f32(h, x, rnd, false);
       return __builtin_bit_cast(uint16_t, h[0]);
     }
