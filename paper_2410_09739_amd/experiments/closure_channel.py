@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eps-rel", type=float, default=0.1)
     ap.add_argument("--perturbation", type=float, default=0.3)
+    ap.add_argument("--flow-seed", type=int, default=1234, help="seed of the initial perturbation")
     ap.add_argument("--seeds", type=int, default=1, help="networks trained from different initialisations")
     ap.add_argument("--gains", default="1", help="comma list: multipliers of the network output (a-posteriori scale)")
     ap.add_argument("--save-params", default="gpurun_out/closure_params.npy")
@@ -145,7 +146,7 @@ def main():
 
     # ---- fine run: transient, then statistics and training snapshots
     u_bulk0 = 15.7 * ut  # bulk velocity of the turbulent state at Re_tau = 180 (u_b / u_tau ~ 15.7)
-    rho0, u0 = W.channel_turbulent_start(nx, ny, nz, u_bulk=u_bulk0, amp=args.perturbation, seed=1234)
+    rho0, u0 = W.channel_turbulent_start(nx, ny, nz, u_bulk=u_bulk0, amp=args.perturbation, seed=args.flow_seed)
     fcfg = L.Config(nx, ny, nz, storage=args.storage, walls_y=True, nu=nu_f, force=(F_f, 0, 0))
     every = max(1, tstar // args.samples_per_tstar)
     snap_every = max(every, tstar // args.snapshots_per_tstar)
