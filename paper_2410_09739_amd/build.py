@@ -39,6 +39,25 @@ def build_host_check() -> str:
     return HOST_CHECK_OUT
 
 
+C_ABI_CHECK_SRC = os.path.join(os.path.dirname(HERE), "tests", "native", "c_abi_channel.c")
+C_ABI_CHECK_OUT = os.path.join(os.path.dirname(HERE), "tests", "native", "c_abi_channel")
+
+
+def build_c_abi_check() -> str:
+    """A plain C99 program linked against liblbm.so through include/lbm.h only
+    (a GPU test runs it): the boundary is usable without Python."""
+    tmp = C_ABI_CHECK_OUT + ".tmp"
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", inc, "-o", tmp,
+           C_ABI_CHECK_SRC, "-L", HERE, "-llbm", "-Wl,-rpath,$ORIGIN/../../paper_2410_09739_amd"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("gcc failed for " + C_ABI_CHECK_SRC)
+    os.replace(tmp, C_ABI_CHECK_OUT)
+    return C_ABI_CHECK_OUT
+
+
 def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     cmd = [HIPCC, *FLAGS, "-o", tmp, *SRCS]
@@ -56,3 +75,5 @@ if __name__ == "__main__":
     print(build(verbose=True))
     if os.path.exists(HOST_CHECK_SRC):
         print(build_host_check())
+    if os.path.exists(C_ABI_CHECK_SRC):
+        print(build_c_abi_check())

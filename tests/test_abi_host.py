@@ -114,3 +114,17 @@ def test_null_arguments_are_rejected():
     assert lib.lbm_moments(None, None, None) == L.LBM_EINVAL
     assert lib.lbm_state_bytes(None) == -1
     lib.lbm_destroy(None)  # no-op
+
+
+def test_header_is_plain_c99_and_cxx(tmp_path):
+    """include/lbm.h compiles as pedantic C99 and as C++ (no torch or HIP types
+    in the signatures), and every entry point it declares is callable from C."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "h.c"
+    src.write_text('#include "lbm.h"\nint main(void) { lbm_config c; lbm_config_default(&c); return c.nx > 0 ? 0 : 1; }\n')
+    for cc, std in (("gcc", "-std=c99"), ("g++", "-std=c++17")):
+        r = subprocess.run([cc, std, "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(root, "include"),
+                            "-x", "c" if cc == "gcc" else "c++", "-c", str(src), "-o", str(tmp_path / "h.o")],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
