@@ -139,8 +139,8 @@ def main():
                     help="only run a plain copy of known size (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU slab decomposition is designed, not built)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch

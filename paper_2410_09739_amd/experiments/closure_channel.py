@@ -122,7 +122,7 @@ def main():
     ap.add_argument("--flow-seed", type=int, default=1234, help="seed of the initial perturbation")
     ap.add_argument("--seeds", type=int, default=1, help="networks trained from different initialisations")
     ap.add_argument("--gains", default="1", help="comma list: multipliers of the network output (a-posteriori scale)")
-    ap.add_argument("--save-params", default="gpurun_out/closure_params.npy")
+    ap.add_argument("--save-params", default="closure_params.npy")
     args = ap.parse_args()
     import torch
 
