@@ -239,8 +239,9 @@ const char* lbm_last_error(const lbm_ctx* c);
  * viscosities nu_t,j of the six second-order groups relaxed with omega_4..9
  * (110, 101, 011, 2s1, 2d1, 2d2), applied through Eq. (transportcoeff3DFPCLBM)
  * as 1/omega_j,eff = 1/omega_j + 3 clamp(nu_t,j, 0, 1/3).
- * Features: x_000 = rho - 1; for the other 26 moments, in the paper's order,
- * (kappa_abc - rho c_a c_b c_c) / rho * 3^((a+b+c)/2).
+ * Features: x_000 = rho - 1; x_100 = x_010 = x_001 = 0 (the first-order central
+ * moments are -F/2 at every node); for the other 23 moments, in the paper's
+ * order, (kappa_abc - rho c_a c_b c_c) / rho * 3^((a+b+c)/2).
  * Parameters: LBM_CLOSURE_NPARAM floats W1[64][27] b1[64] W2[64][64] b2[64]
  * W3[6][64] b3[6] (row-major, W[out][in]) acting on raw features.  The fused
  * kernel rounds weights and activations to BF16 and accumulates in FP32 on
