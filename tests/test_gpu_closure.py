@@ -231,7 +231,8 @@ def test_features_match_oracle(walls, shape):
 # by ~omega^2 * 3 dnu and the populations by that times the second-order
 # non-equilibrium moments (~1e-3 here): well below 1e-6 w_alpha.
 @pytest.mark.parametrize("storage,tol,shape", [("f64", 1e-6, (64, 6, 3)), ("f32", 2e-6, (64, 6, 3)),
-                                               ("f64", 1e-6, (320, 3, 2))])
+                                               ("f64", 1e-6, (320, 3, 2)), ("f16dev", 2e-6, (64, 6, 3)),
+                                               ("bf16dev", 2e-6, (64, 6, 3))])
 def test_fused_closure_step_matches_oracle(storage, tol, shape):
     """One fused step with the closure: the oracle streams, computes features,
     evaluates the bf16-quantised network, sets omega_4..9 per node and collides
@@ -262,8 +263,12 @@ def test_fused_closure_step_matches_oracle(storage, tol, shape):
         w = om.copy()
         w[4:10] = wf[i]
         ref[:, i] = O.collide_node(ff[:, i], w, F)
-    err = np.abs(got.reshape(27, -1) - ref) / W_ALPHA[:, None]
-    assert err.max() <= tol, err.max()
+    # 16-bit storage: one unit in the last place of the stored deviation on top
+    # (the stored value is rounded once, stochastically, after the collision)
+    ulp = {"f16dev": 2.0 ** -10, "bf16dev": 2.0 ** -7}.get(storage, 0.0)
+    bound = tol * W_ALPHA[:, None] + ulp * np.abs(ref - W_ALPHA[:, None]).max()
+    err = np.abs(got.reshape(27, -1) - ref)
+    assert np.all(err <= bound), float((err / bound).max())
     assert np.any(np.clip(nu_t, 0, None) > 1e-3)  # the closure was active
 
 
