@@ -205,6 +205,13 @@ int lbm_diagnostics(lbm_ctx* c, lbm_diag* out);
 int lbm_get_f(lbm_ctx* c, double* f);
 int lbm_set_f(lbm_ctx* c, const double* f);
 
+/* The stored post-collision populations of listed nodes only (probe points,
+ * or parity checks of grids too large to copy whole): nodes[count] flat
+ * indices i = x + nx (y + ny z), host; f host FP64 [27][count], the values
+ * lbm_get_f would give at those nodes.  count = 0 does nothing; an index
+ * outside [0, N) is LBM_EINVAL.  Synchronous. */
+int lbm_get_f_nodes(lbm_ctx* c, const int64_t* nodes, int64_t count, double* f);
+
 /* Bit-exact checkpoint of the raw storage: one state buffer as the library
  * keeps it in device memory (deviations f - w in the storage type, FP16/BF16
  * scaled; blocked by 64-node x segments, each holding its 27 directions, nx

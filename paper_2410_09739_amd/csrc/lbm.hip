@@ -94,6 +94,19 @@ __global__ __launch_bounds__(256) void k_get_f(const typename Stor<ST>::S* __res
   for (int a = 0; a < Q; ++a) f[a * n + i] = weight(a) + (double)Stor<ST>::dec(src[pop_index(g, a, x, y, z)], a);
 }
 
+// the populations of listed nodes only (flat indices checked on the host)
+template <int ST>
+__global__ __launch_bounds__(256) void k_get_f_nodes(const typename Stor<ST>::S* __restrict__ src,
+                                                     const int64_t* __restrict__ nodes, int64_t count,
+                                                     double* __restrict__ f, Geom g) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  int x, y, z;
+  node_xyz(g, nodes[k], x, y, z);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) f[a * count + k] = weight(a) + (double)Stor<ST>::dec(src[pop_index(g, a, x, y, z)], a);
+}
+
 // Step 7 fields from the stored post-collision state: rho = 1 + sum delta,
 // rho u = sum delta e - F/2.
 template <int ST, typename OUT>
@@ -624,6 +637,35 @@ extern "C" int lbm_get_f(lbm_ctx* c, double* f) {
   if (e == hipSuccess) e = e2;
   if (e == hipSuccess) e = e3;
   if (e != hipSuccess) return set_err(c, LBM_EHIP, "lbm_get_f: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_f_nodes(lbm_ctx* c, const int64_t* nodes, int64_t count, double* f) {
+  if (!c || count < 0 || (count > 0 && (!nodes || !f))) return set_err(c, LBM_EINVAL, "lbm_get_f_nodes: bad arguments");
+  if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_get_f_nodes: state not initialised");
+  for (int64_t k = 0; k < count; ++k)
+    if (nodes[k] < 0 || nodes[k] >= c->n)
+      return set_err(c, LBM_EINVAL, "lbm_get_f_nodes: node %lld outside [0, %lld)", (long long)nodes[k], (long long)c->n);
+  if (count == 0) return LBM_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  char* tmp = nullptr;
+  const size_t nb = sizeof(int64_t) * count, fb = sizeof(double) * LBM_Q * count;
+  HIPCHK(c, hipMalloc((void**)&tmp, nb + fb));
+  int64_t* dn = (int64_t*)tmp;
+  double* df = (double*)(tmp + nb);
+  hipError_t e = hipMemcpyAsync(dn, nodes, nb, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) {
+    DISPATCH_ST(c->cfg.storage,
+                k_get_f_nodes<ST><<<nblocks(count, 256), 256, 0, c->stream>>>((const typename Stor<ST>::S*)c->buf[c->cur], dn,
+                                                                              count, df, geom(c)));
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(f, df, fb, hipMemcpyDeviceToHost, c->stream);
+  hipError_t e3 = hipStreamSynchronize(c->stream);
+  hipError_t e2 = hipFree(tmp);
+  if (e == hipSuccess) e = e3;
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) return set_err(c, LBM_EHIP, "lbm_get_f_nodes: %s", hipGetErrorString(e));
   return LBM_OK;
 }
 

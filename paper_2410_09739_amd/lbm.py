@@ -79,6 +79,7 @@ SIGNATURES = {
     "lbm_diagnostics": (ctypes.c_int, [_ctx, ctypes.POINTER(lbm_diag)]),
     "lbm_get_f": (ctypes.c_int, [_ctx, _dp]),
     "lbm_set_f": (ctypes.c_int, [_ctx, _dp]),
+    "lbm_get_f_nodes": (ctypes.c_int, [_ctx, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, _dp]),
     "lbm_state_bytes": (ctypes.c_int64, [_ctx]),
     "lbm_get_raw": (ctypes.c_int, [_ctx, _vp, ctypes.c_int64]),
     "lbm_set_raw": (ctypes.c_int, [_ctx, _vp, ctypes.c_int64]),
@@ -197,6 +198,11 @@ def lbm_diagnostics(ctx, check: bool = True) -> lbm_diag:
 
 def lbm_get_f(ctx, f: np.ndarray):
     _check(load().lbm_get_f(ctx, _dptr(f)), ctx)
+
+
+def lbm_get_f_nodes(ctx, nodes, f: np.ndarray):
+    n = np.ascontiguousarray(nodes, dtype=np.int64)
+    _check(load().lbm_get_f_nodes(ctx, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(n.size), _dptr(f)), ctx)
 
 
 def lbm_set_f(ctx, f: np.ndarray):
@@ -342,6 +348,13 @@ class Lattice:
         f = np.zeros(Q * self.n)
         lbm_get_f(self.ctx, f)
         return f.reshape((Q,) + self.shape)
+
+    def get_f_nodes(self, nodes) -> np.ndarray:
+        """Populations of the listed flat node indices, [27, len(nodes)]."""
+        nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+        f = np.zeros(Q * max(nodes.size, 1))
+        lbm_get_f_nodes(self.ctx, nodes, f)
+        return f[: Q * nodes.size].reshape(Q, nodes.size)
 
     def set_f(self, f: np.ndarray):
         lbm_set_f(self.ctx, np.ascontiguousarray(f, dtype=np.float64).reshape(Q * self.n))

@@ -300,6 +300,68 @@ def test_channel_sampled_nodes_f32(shape):
     assert ratio <= 1.0, ratio
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
+def test_get_f_nodes_equals_get_f(storage):
+    """lbm_get_f_nodes returns exactly what lbm_get_f holds at the listed nodes
+    (repeats allowed), nothing for an empty list, and rejects indices outside
+    the grid."""
+    shape = (70, 9, 6)
+    g0 = _state(shape, seed=5)
+    with L.Lattice(L.Config(*shape, storage=storage, walls_y=True, nu=0.02, force=(1e-5, 0.0, 0.0))) as lat:
+        lat.set_f(g0)
+        lat.step(2)
+        full = lat.get_f().reshape(27, -1)
+        n = full.shape[1]
+        sel = np.array([0, 5, 63, 64, 69, 70, 633, n - 1, 5])
+        assert np.array_equal(lat.get_f_nodes(sel), full[:, sel])
+        assert lat.get_f_nodes([]).shape == (27, 0)
+        for bad in ([n], [-1], [3, n + 7]):
+            with pytest.raises(L.LBMError) as ei:
+                lat.get_f_nodes(bad)
+            assert ei.value.code == L.LBM_EINVAL
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_taylor_green_512_sampled_nodes(storage):
+    """The 512^3 Taylor-Green vortex (Re 1600, u0 0.05) at full size, in the
+    storage forms its precision study compares: a few steps from the initial
+    state, then one more; at sampled nodes (random, periodic seams, segment
+    edges) the update equals the oracle's pull and collision of the GPU's own
+    previous populations, read back through lbm_get_f_nodes."""
+    torch = pytest.importorskip("torch")
+    n, u0, re = 512, 0.05, 1600.0
+    nu = u0 * (n / (2 * np.pi)) / re
+    rho, u = W.taylor_green(n, u0=u0)
+    rd = torch.tensor(rho.ravel(), device="cuda")
+    ud = torch.tensor(u.reshape(3, -1).ravel(), device="cuda")
+    del rho, u
+    torch.cuda.synchronize()
+    N = n ** 3
+    rng = np.random.default_rng(512)
+    edge = np.array([(z * n + y) * n + x for x in (0, 63, 64, 255, 256, n - 1) for y in (0, n - 1) for z in (0, n - 1)])
+    sel = np.unique(np.concatenate([rng.integers(0, N, 400), edge]))
+    x, y, z = sel % n, (sel // n) % n, sel // (n * n)
+    e, _, _ = O.lattice()
+    e = np.asarray(e)
+    nb = (((z[None] - e[:, 2:3]) % n) * n + (y[None] - e[:, 1:2]) % n) * n + (x[None] - e[:, 0:1]) % n
+    uniq, inv = np.unique(nb.ravel(), return_inverse=True)
+    with L.Lattice(L.Config(n, n, n, storage=storage, nu=nu)) as lat:
+        L.lbm_init_device(lat.ctx, rd.data_ptr(), ud.data_ptr())
+        del rd, ud
+        lat.step(3)
+        g_nb = lat.get_f_nodes(uniq)
+        lat.step(1)
+        got = lat.get_f_nodes(sel)
+    f = g_nb[np.arange(27)[:, None], inv.reshape(27, -1)]  # f_a(x) = g_a(x - e_a)
+    om = O.omega_table(nu)
+    ref = np.stack([O.collide_node(f[:, k], om, (0.0, 0.0, 0.0)) for k in range(sel.size)], axis=1)
+    w = W_ALPHA.reshape(27, 1)
+    tol = 8e-7 * w
+    if storage == "f16dev":
+        tol = tol + 2.0 ** -10 * np.abs(ref - w).max() * 2
+    assert np.all(np.abs(got - ref) <= tol), float((np.abs(got - ref) / tol).max())
+
+
 @pytest.mark.parametrize("storage,tol", [("f16dev", 0.01), ("bf16dev", 0.02), ("f32", 1e-4)])
 def test_small_force_momentum_is_kept_by_stochastic_rounding(storage, tol):
     """A body force far below half an ulp of the stored deviations: with
