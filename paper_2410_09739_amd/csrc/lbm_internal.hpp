@@ -398,14 +398,15 @@ inline Box<T> box_args(const lbm_ctx* c) {
 inline int wall_mask(const lbm_ctx* c) {
   return (c->cfg.walls_y ? 1 : 0) | (c->cfg.walls_x ? 2 : 0) | (c->cfg.walls_z ? 4 : 0) | (c->cfg.sym_top ? 8 : 0);
 }
-// wavefront -> (x segment, row) for the step kernels.  The grid is 1D over
-// the nxs ny nz row segments in row-major order (x segment fastest), four
-// wavefronts of one segment each per block, so every block but the last is
-// full whatever nxs is.  The hardware hands consecutive blocks to the eight
-// XCDs in turn: with one block per row and a partial last block (nxs = 5..7)
-// every partial block would land on the same four XCDs and the other four
-// would carry up to 4/nxs of the work.  Each wavefront keeps one segment of
-// one row (y, z uniform, as pull() needs).  false: a wavefront past the end.
+// wavefront -> (x segment, row) for the step kernels; each wavefront keeps
+// one segment of one row (y, z uniform, as pull() needs), and every block is
+// full.  Rows that split into whole blocks (nxs <= 4 or a multiple of 4) use
+// one block row per (y, z): grid (nxs / W, ny, nz), W = min(4, nxs) segments
+// per block.  Other rows (g.flat) use a 1D grid over the nxs ny nz row
+// segments in row-major order, four per block, blocks spanning rows: the
+// hardware hands consecutive blocks to the eight XCDs in turn, and a per-row
+// grid with a partial last block (nxs = 5..7) would give every partial block
+// to the same four XCDs.  false: a wavefront past the end of the flat grid.
 constexpr int SEGS_PER_BLOCK = 4;
 __device__ __forceinline__ bool wave_segment(const Geom& g, int& x, int& y, int& z) {
   if (!g.flat) {  // grid (ceil(nxs / W), ny, nz), blocks of W = min(4, nxs) segments

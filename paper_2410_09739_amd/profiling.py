@@ -36,11 +36,39 @@ FORMS = {0: ("f64", 8), 1: ("f32", 4), 2: ("f16dev", 2), 3: ("bf16dev", 2), 4: (
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without comments, whitespace runs collapsed to one space
+    (string and character literals kept as they are)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
+    """Hash of the code of the stream-collide kernel sources: comments and
+    layout do not count, so that only a change to the code itself marks a
+    traffic measurement as stale."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -41,3 +41,12 @@ def test_kernel_trace_summary_covers_the_timed_kernel():
     text = open(TRACE).read()
     assert "rocprofv3 --kernel-trace --stats" in text
     assert "k_stream_collide<1, 1, true, false>" in text  # FP32, y walls, force: the benchmark's kernel
+
+
+def test_source_hash_ignores_comments_but_not_code():
+    a = 'int f(int x) { return x + 1; } // one\n/* block\n comment */\nconst char* s = "// kept /* too */";\n'
+    b = 'int f(int x)\n{\n  return x + 1;   // another comment\n}\nconst char* s = "// kept /* too */";\n'
+    c = 'int f(int x) { return x + 2; }\nconst char* s = "// kept /* too */";\n'
+    assert P._code_only(a) == P._code_only(b)
+    assert P._code_only(a) != P._code_only(c)
+    assert '"// kept /* too */"' in P._code_only(a)
