@@ -559,8 +559,10 @@ static int closure_steps(lbm_ctx* c, int64_t nsteps) {
   if (!c->closure_grid) {
     int resident = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, (const void*)k_stream_collide_closure<ST, true, true>,
-                                                     256, 0) != hipSuccess || resident < 1)
+                                                     256, 0) != hipSuccess || resident < 1) {
       resident = 1;
+      (void)hipGetLastError();  // a failed query only shrinks the grid; no error to report later
+    }
     int cus = 0;
     HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
     const int64_t want = (C.nseg + 3) / 4;
@@ -652,6 +654,8 @@ extern "C" int lbm_closure_features(lbm_ctx* c, float* x_dev) {
 // error text of calls without a training object, one per host thread
 static thread_local char g_closure_err[512] = "";
 
+static int mlp_err(lbm_mlp* m, int code, const char* fmt, ...);
+
 extern "C" int lbm_closure_eval(const float* params, const float* x_dev, float* nu_dev, int64_t n, void* hip_stream) {
   if (!params || !x_dev || !nu_dev || n < 0) {
     snprintf(g_closure_err, sizeof g_closure_err, "lbm_closure_eval: invalid argument");
@@ -670,10 +674,7 @@ extern "C" int lbm_closure_eval(const float* params, const float* x_dev, float* 
   hipError_t e2 = hipStreamSynchronize(st);
   if (d) (void)hipFree(d);
   if (e == hipSuccess) e = e2;
-  if (e != hipSuccess) {
-    snprintf(g_closure_err, sizeof g_closure_err, "lbm_closure_eval: %s", hipGetErrorString(e));
-    return LBM_EHIP;
-  }
+  if (e != hipSuccess) return mlp_err(nullptr, LBM_EHIP, "lbm_closure_eval: %s", hipGetErrorString(e));
   return LBM_OK;
 }
 
@@ -772,6 +773,7 @@ static int mlp_err(lbm_mlp* m, int code, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(m ? m->err : g_closure_err, 512, fmt, ap);
   va_end(ap);
+  if (code == LBM_EHIP || code == LBM_ENOMEM) (void)hipGetLastError();  // reported here (see set_err)
   return code;
 }
 

@@ -352,6 +352,9 @@ int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(dst, 512, fmt, ap);
   va_end(ap);
+  // a failed runtime call also leaves HIP's per-thread last error set; it is
+  // reported here, so discard it: a later launch check must not report it again
+  if (code == LBM_EHIP || code == LBM_ENOMEM) (void)hipGetLastError();
   return code;
 }
 

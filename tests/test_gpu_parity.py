@@ -268,6 +268,19 @@ def test_create_clear_is_ordered_before_init(source):
     np.testing.assert_allclose(v, u, rtol=0, atol=1e-6)
 
 
+def test_create_reports_out_of_memory():
+    """A grid just under the node limit in FP64 needs about 900 GB: lbm_create
+    fails cleanly with LBM_ENOMEM (nothing allocated is left behind), and a
+    normal context still works afterwards."""
+    with pytest.raises(L.LBMError) as ei:
+        L.Lattice(L.Config(2048, 1024, 1000, storage="f64", nu=0.1))
+    assert ei.value.code == L.LBM_ENOMEM
+    with L.Lattice(L.Config(8, 8, 8, nu=0.1)) as lat:
+        lat.init()
+        lat.step(2)
+        assert lat.diagnostics()["mass"] == pytest.approx(512.0, rel=1e-12)
+
+
 # ------------------------------------------------------------------ full size, sampled
 @pytest.mark.parametrize("shape", [(256, 128, 128), (384, 192, 192)])
 def test_channel_sampled_nodes_f32(shape):
