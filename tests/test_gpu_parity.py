@@ -268,6 +268,41 @@ def test_create_clear_is_ordered_before_init(source):
     np.testing.assert_allclose(v, u, rtol=0, atol=1e-6)
 
 
+def test_state_and_argument_errors_are_reported():
+    """Error paths of the entry points around the step: each returns its code
+    with a text, leaves the context usable, and a later step still runs."""
+    import torch
+    shape = (64, 4, 6)
+    with L.Lattice(L.Config(*shape, storage="f32", walls_y=True, nu=0.05)) as lat:
+        for call in (lambda: lat.moments(), lambda: lat.get_f(), lambda: lat.get_f_nodes([0]),
+                     lambda: lat.get_raw()):
+            with pytest.raises(L.LBMError) as ei:  # nothing initialised yet
+                call()
+            assert ei.value.code == L.LBM_ESTATE
+        lat.init()
+        with pytest.raises(L.LBMError) as ei:  # wrong checkpoint size
+            L.lbm_set_raw(lat.ctx, np.zeros(L.lbm_state_bytes(lat.ctx) - 2, np.uint8))
+        assert ei.value.code == L.LBM_EINVAL
+        n = np.prod(shape)
+        buf = [torch.zeros(k * n // 8, dtype=torch.float64, device="cuda") for k in (1, 3, 6, 6)]
+        torch.cuda.synchronize()
+        with L.Lattice(L.Config(63, 4, 6, nu=0.05)) as odd:  # odd nx: no 2x2x2 filter
+            odd.init()
+            with pytest.raises(L.LBMError) as ei:
+                L.lbm_coarsen(odd.ctx, *(b.data_ptr() for b in buf))
+            assert ei.value.code == L.LBM_EINVAL
+        with L.Lattice(L.Config(*shape, walls_x=True, walls_y=True, nu=0.05)) as box:
+            box.init()  # the filtered strain needs periodic x and z
+            with pytest.raises(L.LBMError) as ei:
+                L.lbm_coarsen(box.ctx, *(b.data_ptr() for b in buf))
+            assert ei.value.code == L.LBM_EINVAL
+            L.lbm_coarsen(box.ctx, buf[0].data_ptr(), buf[1].data_ptr(), buf[2].data_ptr())  # without it: fine
+            box.synchronize()
+        lat.step(3)
+        d = lat.diagnostics()
+        assert d["n_nonfinite"] == 0 and d["mass"] == pytest.approx(float(n), rel=1e-6)
+
+
 def test_create_reports_out_of_memory():
     """A grid just under the node limit in FP64 needs about 900 GB: lbm_create
     fails cleanly with LBM_ENOMEM (nothing allocated is left behind), and a
