@@ -339,6 +339,30 @@ def test_fused_closure_step_full_size_sampled_nodes():
     assert np.clip(nu_t[:, :3], 0, None).max() > 1e-5  # the trained closure acts on the shear groups
 
 
+def test_mlp_rejects_bad_arguments():
+    """The training object's argument checks: empty sets, a batch or learning
+    rate that is not positive, a non-positive target scale; the object then
+    still trains."""
+    n = 256
+    xd = _dev(np.random.default_rng(1).standard_normal((n, 27)).astype(np.float32))
+    yd = _dev(np.abs(np.random.default_rng(2).standard_normal((n, 6))).astype(np.float32))
+    m = L.MLP(seed=4)
+    bad = [lambda: m.loss_grad(xd.data_ptr(), yd.data_ptr(), 0),
+           lambda: m.train(xd.data_ptr(), yd.data_ptr(), 0, 32, 5, 1e-3),
+           lambda: m.train(xd.data_ptr(), yd.data_ptr(), n, 0, 5, 1e-3),
+           lambda: m.train(xd.data_ptr(), yd.data_ptr(), n, 32, 5, 0.0),
+           lambda: m.set_normalisation(np.zeros(27), np.ones(27), 0.0),
+           lambda: m.fit_normalisation(xd.data_ptr(), yd.data_ptr(), 0)]
+    for call in bad:
+        with pytest.raises(L.LBMError) as ei:
+            call()
+        assert ei.value.code == L.LBM_EINVAL
+    m.fit_normalisation(xd.data_ptr(), yd.data_ptr(), n)
+    hist = m.train(xd.data_ptr(), yd.data_ptr(), n, 32, 5, 1e-3)
+    assert np.all(np.isfinite(hist))
+    m.close()
+
+
 def test_set_closure_validates():
     with L.Lattice(L.Config(40, 4, 4, nu=0.02)) as lat:
         with pytest.raises(L.LBMError):
