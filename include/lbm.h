@@ -306,7 +306,7 @@ typedef struct lbm_mlp lbm_mlp;
 int lbm_mlp_create(uint64_t seed, void* hip_stream, lbm_mlp** out); /* He-uniform init from seed */
 int lbm_mlp_set_params(lbm_mlp* m, const float* p);                /* host, standardised space; resets Adam */
 int lbm_mlp_get_params(lbm_mlp* m, float* p);                      /* host */
-int lbm_mlp_set_normalisation(lbm_mlp* m, const float* mu, const float* sigma, float s_y); /* host */
+int lbm_mlp_set_normalisation(lbm_mlp* m, const float* mu, const float* sigma, float s_y); /* host; finite, sigma >= 0, s_y > 0 */
 int lbm_mlp_get_normalisation(lbm_mlp* m, float* mu, float* sigma, float* s_y);             /* host */
 /* mu, sigma per feature (population std; sigma below 1e-7 of the largest -> 0)
  * and s_y = rms of all targets, computed on the device. */

@@ -866,7 +866,10 @@ extern "C" int lbm_mlp_get_params(lbm_mlp* m, float* p) {
 }
 
 extern "C" int lbm_mlp_set_normalisation(lbm_mlp* m, const float* mu, const float* sigma, float s_y) {
-  if (!m || !mu || !sigma || !(s_y > 0.0f)) return LBM_EINVAL;
+  if (!m || !mu || !sigma || !(s_y > 0.0f) || !std::isfinite(s_y)) return LBM_EINVAL;
+  for (int k = 0; k < NIN; ++k)
+    if (!std::isfinite(mu[k]) || !std::isfinite(sigma[k]) || sigma[k] < 0.0f)
+      return mlp_err(m, LBM_EINVAL, "lbm_mlp_set_normalisation: feature %d: mean and spread must be finite, spread >= 0", k);
   float is[NIN];
   for (int k = 0; k < NIN; ++k) is[k] = sigma[k] > 0.0f ? 1.0f / sigma[k] : 0.0f;
   MLPCHK(m, hipMemcpyAsync(m->mu, mu, sizeof(float) * NIN, hipMemcpyHostToDevice, m->stream));

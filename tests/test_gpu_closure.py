@@ -352,6 +352,8 @@ def test_mlp_rejects_bad_arguments():
            lambda: m.train(xd.data_ptr(), yd.data_ptr(), n, 0, 5, 1e-3),
            lambda: m.train(xd.data_ptr(), yd.data_ptr(), n, 32, 5, 0.0),
            lambda: m.set_normalisation(np.zeros(27), np.ones(27), 0.0),
+           lambda: m.set_normalisation(np.full(27, np.nan), np.ones(27), 1.0),
+           lambda: m.set_normalisation(np.zeros(27), -np.ones(27), 1.0),
            lambda: m.fit_normalisation(xd.data_ptr(), yd.data_ptr(), 0)]
     for call in bad:
         with pytest.raises(L.LBMError) as ei:
