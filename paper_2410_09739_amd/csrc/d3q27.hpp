@@ -34,14 +34,17 @@ constexpr double C1[3] = {1.0, 0.0, 1.0 / 3.0};
 constexpr double weight(int a) { return W1[EX[a] + 1] * W1[EY[a] + 1] * W1[EZ[a] + 1]; }
 
 // Exact power-of-two scale of the FP16/BF16 deviation storage, by speed class
-// (|e|^2 = 0,1,2,3): about 2^10 / w_alpha, so that relative deviations down to
-// ~6e-8 stay in FP16's normal range and up to 64 stay finite.
+// (|e|^2 = 0,1,2,3): 2^(DEV_LOG2_0 + 2 |e|^2), about 2^10 / w_alpha, so that
+// relative deviations down to ~6e-8 stay in FP16's normal range and up to 64
+// stay finite.  The factor 4 between classes is what the storage-unit sweeps
+// of fpc_collide.hpp rely on.
+constexpr int DEV_LOG2_0 = 12;
 constexpr float dev_scale(int a) {
-  return (EX[a] * EX[a] + EY[a] * EY[a] + EZ[a] * EZ[a]) == 0   ? 4096.0f
-         : (EX[a] * EX[a] + EY[a] * EY[a] + EZ[a] * EZ[a]) == 1 ? 16384.0f
-         : (EX[a] * EX[a] + EY[a] * EY[a] + EZ[a] * EZ[a]) == 2 ? 65536.0f
-                                                                  : 262144.0f;
+  return float(1u << (DEV_LOG2_0 + 2 * (EX[a] * EX[a] + EY[a] * EY[a] + EZ[a] * EZ[a])));
 }
+static_assert(dev_scale(0) == 4096.0f && dev_scale(1) == 16384.0f && dev_scale(7) == 65536.0f &&
+                  dev_scale(19) == 262144.0f,
+              "storage scales by speed class");
 
 // Moment index in the paper's order:
 // 000,100,010,001,110,101,011,200,020,002,120,102,210,012,201,021,111,220,202,022,

@@ -29,6 +29,19 @@
 // kappa_000 = rho and first-order moments taken as zero.  kappa^Mv_122 uses the
 // product kappa~_110 kappa~_012 that the general attractor formula gives.
 //
+// Storage units (SU = true, the FP16/BF16 deviation forms): the cube holds
+// each deviation times its storage scale dev_scale(alpha) = 2^(12 + 2|e|^2),
+// i.e. the stored numbers themselves, so that loading a value needs no
+// multiply.  The two outer points of every 3-point line share a scale and the
+// middle one has a quarter of it, so each sweep takes its middle value times 4
+// and its outputs carry the outer points' scale; after the three forward
+// sweeps every moment carries the one factor UNIT = 2^18.  The collision then
+// runs on moments times UNIT: constants of the rest state and the force are
+// taken times UNIT and 1/rho (where it multiplies a product of two moments)
+// times 1/UNIT.  Every such factor is an exact power of two, so the results
+// are bitwise those of the same arithmetic on plain deviations (no FP32
+// underflow or overflow is reached at these scales).
+//
 // MAXWELL = true is the comparison model with Maxwellian equilibria (the
 // MCM-LBM of Sec. 4): orders >= 4 relax to the discrete Maxwellian's central
 // moments rho c_a c_b c_c (c = 1, 0, c_s^2) instead of the Markovian
@@ -63,14 +76,25 @@ struct Rates {
   T h[Q];   // 1 - omega_j / 2
 };
 
+// Factors of the storage units (see the header).  line(k): factor carried by
+// the outputs of a forward sweep whose outer points have k + 1 non-zero
+// velocity components; U: factor carried by the moments after all three.
+template <bool SU>
+struct Units {
+  static constexpr int M = SU ? 4 : 1;  // middle point of a line, in its outer points' units
+  static constexpr double line(int k) { return SU ? double(1u << (DEV_LOG2_0 + 2 * (k + 1))) : 1.0; }
+  static constexpr double U = line(2);
+};
+
 // ---------------------------------------------------------------------------
 // 3-point sweeps.  Forward: values (dm, d0, dp) at e = -1, 0, +1, deviations
 // from W * (1/6, 2/3, 1/6)  ->  central moments (r0, r1, r2) about u, minus
 // W * (1, 0, 1/3).
-template <typename T, int WNUM_IS_ZERO>
+// M: the middle value's factor (4 in storage units, see Units).
+template <typename T, int WNUM_IS_ZERO, int M = 1>
 __host__ __device__ __forceinline__ void fwd3(T& a0, T& a1, T& a2, T u, T W) {
   const T sp = a2 + a0;
-  const T s0 = sp + a1;
+  const T s0 = sp + T(M) * a1;
   const T d1 = a2 - a0;
   const T S = WNUM_IS_ZERO ? s0 : s0 + W;
   a0 = s0;
@@ -101,31 +125,35 @@ constexpr double inv_factor(int a) { return 1.0 / double(1 << inv_shift(a)); }
 
 // Forward sweeps over the cube (x, then y, then z).  On return v[c][b][a] holds
 // kappa'_abc.  The x sweep is split so that rho and j come out of its line sums.
-template <typename T>
+template <typename T, bool SU = false>
 __host__ __device__ __forceinline__ void forward_x(T (&v)[3][3][3], T ux) {
+  using Un = Units<SU>;
 #pragma unroll
   for (int iz = 0; iz < 3; ++iz)
 #pragma unroll
     for (int iy = 0; iy < 3; ++iy)
-      fwd3<T, 0>(v[iz][iy][0], v[iz][iy][1], v[iz][iy][2], ux, T(W1[iy] * W1[iz]));
+      fwd3<T, 0, Un::M>(v[iz][iy][0], v[iz][iy][1], v[iz][iy][2], ux,
+                        T(W1[iy] * W1[iz] * Un::line((iy != 1) + (iz != 1))));
 }
 
-template <typename T>
+template <typename T, bool SU = false>
 __host__ __device__ __forceinline__ void forward_yz(T (&v)[3][3][3], T uy, T uz) {
+  using Un = Units<SU>;
 #pragma unroll
   for (int iz = 0; iz < 3; ++iz) {
-    fwd3<T, 0>(v[iz][0][0], v[iz][1][0], v[iz][2][0], uy, T(C1[0] * W1[iz]));
-    fwd3<T, 1>(v[iz][0][1], v[iz][1][1], v[iz][2][1], uy, T(0));
-    fwd3<T, 0>(v[iz][0][2], v[iz][1][2], v[iz][2][2], uy, T(C1[2] * W1[iz]));
+    const double l = Un::line(1 + (iz != 1));
+    fwd3<T, 0, Un::M>(v[iz][0][0], v[iz][1][0], v[iz][2][0], uy, T(C1[0] * W1[iz] * l));
+    fwd3<T, 1, Un::M>(v[iz][0][1], v[iz][1][1], v[iz][2][1], uy, T(0));
+    fwd3<T, 0, Un::M>(v[iz][0][2], v[iz][1][2], v[iz][2][2], uy, T(C1[2] * W1[iz] * l));
   }
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (a == 1 || b == 1)
-        fwd3<T, 1>(v[0][b][a], v[1][b][a], v[2][b][a], uz, T(0));
+        fwd3<T, 1, Un::M>(v[0][b][a], v[1][b][a], v[2][b][a], uz, T(0));
       else
-        fwd3<T, 0>(v[0][b][a], v[1][b][a], v[2][b][a], uz, T(C1[a] * C1[b]));
+        fwd3<T, 0, Un::M>(v[0][b][a], v[1][b][a], v[2][b][a], uz, T(C1[a] * C1[b] * Un::U));
     }
 }
 
@@ -133,8 +161,9 @@ __host__ __device__ __forceinline__ void forward_yz(T (&v)[3][3][3], T uy, T uz)
 // at e = +-1, so the line constants W of a later sweep are scaled by the
 // doublings its inputs already carry; on return the cube holds
 // delta_alpha * 2^inv_shift(alpha).
-template <typename T>
+template <typename T, bool SU = false>
 __host__ __device__ __forceinline__ void inverse_all(T (&v)[3][3][3], T ux, T uy, T uz) {
+  constexpr double U = Units<SU>::U;  // the line constants in the moments' units
   const T uz2 = uz * uz, uy2 = uy * uy, ux2 = ux * ux;
   const T tz = uz + uz, ty = uy + uy, tx = ux + ux;
 #pragma unroll
@@ -144,76 +173,90 @@ __host__ __device__ __forceinline__ void inverse_all(T (&v)[3][3][3], T ux, T uy
       if (a == 1 || b == 1)
         inv3<T, 1>(v[0][b][a], v[1][b][a], v[2][b][a], uz, uz2, tz, T(0));
       else
-        inv3<T, 0>(v[0][b][a], v[1][b][a], v[2][b][a], uz, uz2, tz, T(C1[a] * C1[b]));
+        inv3<T, 0>(v[0][b][a], v[1][b][a], v[2][b][a], uz, uz2, tz, T(C1[a] * C1[b] * U));
     }
 #pragma unroll
   for (int iz = 0; iz < 3; ++iz) {
     const double sz = iz == 1 ? 1.0 : 2.0;
-    inv3<T, 0>(v[iz][0][0], v[iz][1][0], v[iz][2][0], uy, uy2, ty, T(C1[0] * W1[iz] * sz));
+    inv3<T, 0>(v[iz][0][0], v[iz][1][0], v[iz][2][0], uy, uy2, ty, T(C1[0] * W1[iz] * sz * U));
     inv3<T, 1>(v[iz][0][1], v[iz][1][1], v[iz][2][1], uy, uy2, ty, T(0));
-    inv3<T, 0>(v[iz][0][2], v[iz][1][2], v[iz][2][2], uy, uy2, ty, T(C1[2] * W1[iz] * sz));
+    inv3<T, 0>(v[iz][0][2], v[iz][1][2], v[iz][2][2], uy, uy2, ty, T(C1[2] * W1[iz] * sz * U));
   }
 #pragma unroll
   for (int iz = 0; iz < 3; ++iz)
 #pragma unroll
     for (int iy = 0; iy < 3; ++iy) {
       const double syz = (iz == 1 ? 1.0 : 2.0) * (iy == 1 ? 1.0 : 2.0);
-      inv3<T, 0>(v[iz][iy][0], v[iz][iy][1], v[iz][iy][2], ux, ux2, tx, T(W1[iy] * W1[iz] * syz));
+      inv3<T, 0>(v[iz][iy][0], v[iz][iy][1], v[iz][iy][2], ux, ux2, tx, T(W1[iy] * W1[iz] * syz * U));
     }
 }
 
-// Macroscopic fields from the deviation cube: rho' = sum delta, j = sum delta e.
-// The sums are the line sums and differences of the forward sweeps, in the
-// same order, so the compiler computes them once for both.
-template <typename T>
+// Macroscopic fields from the deviation cube: rho' = sum delta, j = sum delta e
+// (in storage units: times UNIT).  The sums are the line sums and differences
+// of the forward sweeps, in the same order, so the compiler computes them once
+// for both; every 3-point combination weights its middle term by M.
+template <typename T, bool SU = false>
 __host__ __device__ __forceinline__ void density_momentum(const T (&v)[3][3][3], T& rhop, T& jx, T& jy, T& jz) {
-  T s[3][3], p[3];
-  jx = T(0);
+  constexpr int M = Units<SU>::M;
+  T s[3][3], d[3][3], p[3], q[3], r[3];
 #pragma unroll
   for (int iz = 0; iz < 3; ++iz)
 #pragma unroll
     for (int iy = 0; iy < 3; ++iy) {
-      s[iz][iy] = (v[iz][iy][2] + v[iz][iy][0]) + v[iz][iy][1];
-      jx += v[iz][iy][2] - v[iz][iy][0];
+      s[iz][iy] = (v[iz][iy][2] + v[iz][iy][0]) + T(M) * v[iz][iy][1];
+      d[iz][iy] = v[iz][iy][2] - v[iz][iy][0];
     }
 #pragma unroll
-  for (int iz = 0; iz < 3; ++iz) p[iz] = (s[iz][2] + s[iz][0]) + s[iz][1];
-  jy = (s[0][2] - s[0][0]) + (s[1][2] - s[1][0]) + (s[2][2] - s[2][0]);
+  for (int iz = 0; iz < 3; ++iz) {
+    p[iz] = (s[iz][2] + s[iz][0]) + T(M) * s[iz][1];
+    q[iz] = (d[iz][2] + d[iz][0]) + T(M) * d[iz][1];
+    r[iz] = s[iz][2] - s[iz][0];
+  }
+  jx = (q[2] + q[0]) + T(M) * q[1];
+  jy = (r[2] + r[0]) + T(M) * r[1];
   jz = p[2] - p[0];
-  rhop = (p[2] + p[0]) + p[1];
+  rhop = (p[2] + p[0]) + T(M) * p[1];
 }
 
 // ---------------------------------------------------------------------------
 // Pre-collision part of one node: Step 7 fields (rho = 1 + rho', rho u =
-// sum f e + F/2) and the forward sweeps; on return v holds kappa'.
-template <typename T, bool FORCE>
+// sum f e + F/2) and the forward sweeps; on return v holds kappa' (and rhop
+// rho', both times UNIT in storage units; rho and u are plain).
+template <typename T, bool FORCE, bool SU = false>
 __host__ __device__ __forceinline__ void pre_collision(T (&v)[3][3][3], T Fx, T Fy, T Fz, T& rhop, T& rho,
                                                        T& ux, T& uy, T& uz) {
+  constexpr double U = Units<SU>::U;
   T jx, jy, jz;
-  density_momentum(v, rhop, jx, jy, jz);
-  rho = T(1) + rhop;
-  const T ir = recip(rho);
+  density_momentum<T, SU>(v, rhop, jx, jy, jz);
+  rho = T(1) + rhop * T(1.0 / U);
+  const T iru = recip(rho) * T(1.0 / U);
   if (FORCE) {
-    jx += T(0.5) * Fx;
-    jy += T(0.5) * Fy;
-    jz += T(0.5) * Fz;
+    jx += T(0.5 * U) * Fx;
+    jy += T(0.5 * U) * Fy;
+    jz += T(0.5 * U) * Fz;
   }
-  ux = jx * ir;
-  uy = jy * ir;
-  uz = jz * ir;
-  forward_x(v, ux);
-  forward_yz(v, uy, uz);
+  ux = jx * iru;
+  uy = jy * iru;
+  uz = jz * iru;
+  forward_x<T, SU>(v, ux);
+  forward_yz<T, SU>(v, uy, uz);
 }
 
 // Step 3 on the primed moments in v (as left by pre_collision), then the
 // inverse sweeps.  ws[6], cs[6]: the second-order rates omega_4..omega_9 to use
 // at this node (the rates table, or a per-node closure) and 1 - ws.
-template <typename T, bool FORCE, bool MAXWELL = false>
+// In storage units (SU) v and rhop carry UNIT, rho and u are plain: the rest
+// state's constants are taken times UNIT (thirdU, ninthU) and a product of two
+// moments is scaled by iru = 1 / (rho UNIT).
+template <typename T, bool FORCE, bool MAXWELL = false, bool SU = false>
 __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& R, const T (&ws)[6],
                                                const T (&cs)[6], T Fx, T Fy, T Fz, T rhop, T rho, T ux,
                                                T uy, T uz) {
+  constexpr double U = Units<SU>::U;
   const T third = T(1.0 / 3.0), ninth = T(1.0 / 9.0);
+  const T thirdU = T(U / 3.0), ninthU = T(U / 9.0);
   const T ir = recip(rho);
+  const T iru = ir * T(1.0 / U);
 
   // pre-collision primed central moments (v[c][b][a] = kappa'_abc)
   const T k100 = v[0][0][1], k010 = v[0][1][0], k001 = v[1][0][0];
@@ -234,11 +277,11 @@ __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& 
   T s122 = 0, s212 = 0, s221 = 0, s222 = 0;
   if (FORCE) {
     const T gx = Fx * ir, gy = Fy * ir, gz = Fz * ir;
-    const T K200 = third + k200, K020 = third + k020, K002 = third + k002;
-    const T K220 = ninth + k220, K202 = ninth + k202, K022 = ninth + k022;
-    s100 = Fx;
-    s010 = Fy;
-    s001 = Fz;
+    const T K200 = thirdU + k200, K020 = thirdU + k020, K002 = thirdU + k002;
+    const T K220 = ninthU + k220, K202 = ninthU + k202, K022 = ninthU + k022;
+    s100 = T(U) * Fx;
+    s010 = T(U) * Fy;
+    s001 = T(U) * Fz;
     s120 = gx * K020 + T(2) * gy * k110;
     s102 = gx * K002 + T(2) * gz * k101;
     s210 = T(2) * gx * k110 + gy * K200;
@@ -290,13 +333,13 @@ __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& 
   // ---- order 4: attractors from post-collision order 2 (primed form of
   // (K200 K020 + 2 K110^2)/rho - 1/9 etc.).
   // (Maxwellian model: rho' c_s^4 and 0, the primed discrete Maxwellian.)
-  const T m220 = MAXWELL ? ninth * rhop : ((t200 + t020) * third + t200 * t020 + T(2) * t110 * t110 - ninth * rhop) * ir;
-  const T m202 = MAXWELL ? ninth * rhop : ((t200 + t002) * third + t200 * t002 + T(2) * t101 * t101 - ninth * rhop) * ir;
-  const T m022 = MAXWELL ? ninth * rhop : ((t020 + t002) * third + t020 * t002 + T(2) * t011 * t011 - ninth * rhop) * ir;
-  const T A2 = third + t200, B2 = third + t020, C2 = third + t002;  // full post-collision order 2
-  const T m211 = MAXWELL ? T(0) : (A2 * t011 + T(2) * t110 * t101) * ir;
-  const T m121 = MAXWELL ? T(0) : (B2 * t101 + T(2) * t110 * t011) * ir;
-  const T m112 = MAXWELL ? T(0) : (C2 * t110 + T(2) * t011 * t101) * ir;
+  const T m220 = MAXWELL ? ninth * rhop : ((t200 + t020) * thirdU + t200 * t020 + T(2) * t110 * t110 - ninthU * rhop) * iru;
+  const T m202 = MAXWELL ? ninth * rhop : ((t200 + t002) * thirdU + t200 * t002 + T(2) * t101 * t101 - ninthU * rhop) * iru;
+  const T m022 = MAXWELL ? ninth * rhop : ((t020 + t002) * thirdU + t020 * t002 + T(2) * t011 * t011 - ninthU * rhop) * iru;
+  const T A2 = thirdU + t200, B2 = thirdU + t020, C2 = thirdU + t002;  // full post-collision order 2
+  const T m211 = MAXWELL ? T(0) : (A2 * t011 + T(2) * t110 * t101) * iru;
+  const T m121 = MAXWELL ? T(0) : (B2 * t101 + T(2) * t110 * t011) * iru;
+  const T m112 = MAXWELL ? T(0) : (C2 * t110 + T(2) * t011 * t101) * iru;
   const T c4s1 = k220 + k202 + k022, c4d1 = k220 + k202 - k022, c4d2 = k220 - k202;
   const T t4s1 = c4s1 + R.w[17] * ((m220 + m202 + m022) - c4s1) + R.h[17] * (s220 + s202 + s022);
   const T t4d1 = c4d1 + R.w[18] * ((m220 + m202 - m022) - c4d1) + R.h[18] * (s220 + s202 - s022);
@@ -309,7 +352,7 @@ __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& 
   const T t022 = T(0.5) * (t4s1 - t4d1);
 
   // ---- order 5: attractors from post-collision orders 2 and 3.
-  const T f5 = T(0.4) * ir;  // 2 / (5 rho)
+  const T f5 = T(0.4) * iru;  // 2 / (5 rho)
   const T m122 = MAXWELL ? T(0) : f5 * (B2 * t102 + C2 * t120 + T(4) * t011 * t111 + T(2) * (t101 * t021 + t110 * t012));
   const T m212 = MAXWELL ? T(0) : f5 * (A2 * t012 + C2 * t210 + T(4) * t101 * t111 + T(2) * (t110 * t102 + t011 * t201));
   const T m221 = MAXWELL ? T(0) : f5 * (A2 * t021 + B2 * t201 + T(4) * t110 * t111 + T(2) * (t011 * t210 + t101 * t120));
@@ -318,9 +361,9 @@ __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& 
   const T t221 = k221 + R.w[25] * (m221 - k221) + R.h[25] * s221;
 
   // ---- order 6: attractor from post-collision orders 2 and 4 (primed form).
-  const T m222 = MAXWELL ? rhop * T(1.0 / 27.0) : ((t200 + t020 + t002) * ninth + (t022 + t202 + t220) * third + t200 * t022 + t020 * t202 +
+  const T m222 = MAXWELL ? rhop * T(1.0 / 27.0) : ((t200 + t020 + t002) * ninthU + (t022 + t202 + t220) * thirdU + t200 * t022 + t020 * t202 +
                   t002 * t220 + T(4) * (t110 * t112 + t101 * t121 + t011 * t211)) *
-                     (third * ir) -
+                     (third * iru) -
                  rhop * (T(1.0 / 27.0) * ir);
   const T t222 = k222 + R.w[26] * (m222 - k222) + R.h[26] * s222;
 
@@ -336,18 +379,19 @@ __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& 
   v[2][2][1] = t122; v[2][1][2] = t212; v[1][2][2] = t221;
   v[2][2][2] = t222;
 
-  inverse_all(v, ux, uy, uz);
+  inverse_all<T, SU>(v, ux, uy, uz);
 }
 
 // Whole collision of one node (Appendix D Steps 7, 1-5): deviation cube in,
-// post-collision deviations (times 2^inv_shift) out.
-template <typename T, bool FORCE, bool MAXWELL = false>
+// post-collision deviations (times 2^inv_shift) out; in storage units (SU) the
+// cube comes in as stored numbers and goes out times UNIT.
+template <typename T, bool FORCE, bool MAXWELL = false, bool SU = false>
 __host__ __device__ __forceinline__ void collide(T (&v)[3][3][3], const Rates<T>& R, const T (&ws)[6],
                                                  const T (&cs)[6], T Fx, T Fy, T Fz, T& rho, T& ux, T& uy,
                                                  T& uz) {
   T rhop;
-  pre_collision<T, FORCE>(v, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
-  relax<T, FORCE, MAXWELL>(v, R, ws, cs, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
+  pre_collision<T, FORCE, SU>(v, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
+  relax<T, FORCE, MAXWELL, SU>(v, R, ws, cs, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
 }
 
 }  // namespace fpc

@@ -30,18 +30,24 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>:
                                                         typename Stor<ST>::S* __restrict__ dst,
                                                         StepArgs<typename Stor<ST>::R> A) {
   using T = typename Stor<ST>::R;
+  // FP16/BF16: arithmetic on the stored numbers (storage units), which drops
+  // the multiply of every loaded value by its scale.  Not in the periodic
+  // FP16 kernel: its single gather path lets the compiler fold the scale into
+  // the conversions (v_fma_mix_f32) already, and storage units measured a few
+  // instructions more there.
+  constexpr bool SU = Stor<ST>::units && !(BC == 0 && (ST == LBM_F16DEV || ST == LBM_F16DEV_RNE));
   int x, y, z;
   if (!wave_segment(A.g, x, y, z) || x >= A.g.nx) return;
   T v[3][3][3];
-  if (BC == 2) pull_box<ST>(src, A.g, A.box, x, y, z, v);
-  else pull<ST, BC == 1>(src, A.g, x, y, z, v);
+  if (BC == 2) pull_box<ST, SU>(src, A.g, A.box, x, y, z, v);
+  else pull<ST, BC == 1, SU>(src, A.g, x, y, z, v);
   T ws[6] = {A.r.w[4], A.r.w[5], A.r.w[6], A.r.w[7], A.r.w[8], A.r.w[9]};
   T cs[6] = {A.r.c[4], A.r.c[5], A.r.c[6], A.r.c[7], A.r.c[8], A.r.c[9]};
   T rhop, rho, ux, uy, uz;
-  pre_collision<T, FORCE>(v, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
-  if (BC == 2 && A.box.les_on) les_rates(v, rho, A.box, A.r, y, A.g.ny, ws, cs);  // uniform branch
-  relax<T, FORCE, MAXWELL>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
-  push<ST>(dst, A.g, x, y, z, v, A.step);
+  pre_collision<T, FORCE, SU>(v, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
+  if (BC == 2 && A.box.les_on) les_rates<SU>(v, rho, A.box, A.r, y, A.g.ny, ws, cs);  // uniform branch
+  relax<T, FORCE, MAXWELL, SU>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
+  push<ST, SU>(dst, A.g, x, y, z, v, A.step);
 }
 
 // ===========================================================================

@@ -22,7 +22,9 @@ template <>
 struct Stor<LBM_F64> {
   using S = double;
   using R = double;
+  static constexpr bool units = false;  // stores plain deviations
   static __device__ __forceinline__ R dec(S s, int) { return s; }
+  static __device__ __forceinline__ R raw(S s) { return s; }
   // f: exact power of two still carried by r (see inverse_all)
   static constexpr bool stochastic = false;
   static __device__ __forceinline__ S enc(R r, int, double f = 1.0, uint32_t = 0) { return r * f; }
@@ -33,7 +35,9 @@ template <>
 struct Stor<LBM_F32> {
   using S = float;
   using R = float;
+  static constexpr bool units = false;
   static __device__ __forceinline__ R dec(S s, int) { return s; }
+  static __device__ __forceinline__ R raw(S s) { return s; }
   static constexpr bool stochastic = false;
   static __device__ __forceinline__ S enc(R r, int, double f = 1.0, uint32_t = 0) { return r * (float)f; }
   static __device__ __forceinline__ S enc_nearest(R r, int a, double f = 1.0) { return enc(r, a, f); }
@@ -52,6 +56,10 @@ struct StorF16 {
   using S = _Float16;
   using R = float;
   static constexpr bool stochastic = SR;
+  // the kernels' arithmetic runs in storage units (fpc_collide.hpp): raw()
+  // is the stored number, dec() the deviation
+  static constexpr bool units = true;
+  static __device__ __forceinline__ R raw(S s) { return (float)s; }
   static __device__ __forceinline__ R dec(S s, int a) { return (float)s * (1.0f / dev_scale(a)); }
   static __device__ __forceinline__ S enc(R r, int a, double f = 1.0, uint32_t rnd = 0) {
     const float x = r * (float)(dev_scale(a) * f);
@@ -75,6 +83,8 @@ struct StorBF16 {
   using S = uint16_t;
   using R = float;
   static constexpr bool stochastic = SR;
+  static constexpr bool units = true;
+  static __device__ __forceinline__ R raw(S s) { return __uint_as_float((uint32_t)s << 16); }
   static __device__ __forceinline__ R dec(S s, int a) {
     return __uint_as_float((uint32_t)s << 16) * (1.0f / dev_scale(a));
   }
@@ -198,7 +208,9 @@ struct StepArgs {
 // across it, so every row and direction base is a scalar 64-bit address and
 // the only per-lane address terms are the three x offsets inside a row
 // (32-bit; checked at creation).  Lanes with x >= nx must not call.
-template <int ST, bool WALLS>
+// SU: leave the stored numbers in v (storage units, fpc_collide.hpp) instead
+// of the deviations.
+template <int ST, bool WALLS, bool SU = false>
 __device__ __forceinline__ void pull(const typename Stor<ST>::S* __restrict__ src, const Geom& g, int x, int y, int z,
                                      typename Stor<ST>::R (&v)[3][3][3]) {
   using T = typename Stor<ST>::R;
@@ -208,7 +220,7 @@ __device__ __forceinline__ void pull(const typename Stor<ST>::S* __restrict__ sr
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   // rows away from the walls (all but two per plane) take the wall-free gather,
   // whose loads keep the scalar-base form; the branch is wavefront-uniform
-  if (WALLS && y > 0 && y < ny - 1) return pull<ST, false>(src, g, x, y, z, v);
+  if (WALLS && y > 0 && y < ny - 1) return pull<ST, false, SU>(src, g, x, y, z, v);
   const char* __restrict__ sb = (const char*)src;
   const int64_t rowb = g.rowlen * SZ;
   const int64_t planeb = rowb * ny;
@@ -233,7 +245,9 @@ __device__ __forceinline__ void pull(const typename Stor<ST>::S* __restrict__ sr
     const char* base = bb ? sb + r0 + (uint64_t)o * dirb : dptr + (dy[ey + 1] + dz[ez + 1]);
     const uint32_t off = bb ? xo[1] : xo[ex + 1];
     dptr += dirb;
-    v[ez + 1][ey + 1][ex + 1] = SS::dec(*(const S*)(base + off), a);  // w_opp = w_alpha, scales equal
+    // w_opp = w_alpha and the storage scales are equal
+    const S sv = *(const S*)(base + off);
+    v[ez + 1][ey + 1][ex + 1] = SU ? SS::raw(sv) : SS::dec(sv, a);
   }
 }
 
@@ -245,20 +259,21 @@ __device__ __forceinline__ void pull(const typename Stor<ST>::S* __restrict__ sr
 // wavefront-uniform; x walls touch only the first and last lane of a row, so
 // those lanes reload their own opposite population.  Wavefronts away from
 // every wall take the wall-free gather.
-template <int ST>
+template <int ST, bool SU = false>
 __device__ __forceinline__ void pull_box(const typename Stor<ST>::S* __restrict__ src, const Geom& g,
                                          const Box<typename Stor<ST>::R>& b, int x, int y, int z,
                                          typename Stor<ST>::R (&v)[3][3][3]) {
   using T = typename Stor<ST>::R;
   using S = typename Stor<ST>::S;
   using SS = Stor<ST>;
+  auto get = [](S sv, int a) -> T { return SU ? SS::raw(sv) : SS::dec(sv, a); };
   constexpr uint32_t SZ = sizeof(S);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int x0 = __builtin_amdgcn_readfirstlane(x - (x % SEG));  // first x of the segment
   const bool yin = !b.wy || (y > 0 && y < ny - 1);
   const bool zin = !b.wz || (z > 0 && z < nz - 1);
   const bool xin = !b.wx || (x0 > 0 && x0 + SEG < nx);
-  if (yin && zin && xin) return pull<ST, false>(src, g, x, y, z, v);
+  if (yin && zin && xin) return pull<ST, false, SU>(src, g, x, y, z, v);
   const char* __restrict__ sb = (const char*)src;
   const int64_t rowb = g.rowlen * SZ;
   const int64_t planeb = rowb * ny;
@@ -279,14 +294,16 @@ __device__ __forceinline__ void pull_box(const typename Stor<ST>::S* __restrict_
     T val;
     if (b.sym && top && !bbz) {  // uniform: specular reflection at the symmetry plane
       // the population that left (x - e_x, ny - 1, z - e_z) with (e_x, +1, e_z)
-      val = SS::dec(*(const S*)(sb + r0 + (uint64_t)mirror_y(a) * dirb + dz[ez + 1] + xo[ex + 1]), a);
-      if (xwall) val = SS::dec(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
+      val = get(*(const S*)(sb + r0 + (uint64_t)mirror_y(a) * dirb + dz[ez + 1] + xo[ex + 1]), a);
+      if (xwall) val = get(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
     } else if (bby || bbz) {  // uniform
-      val = SS::dec(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
-      if (b.lid_on && b.wy && top) val += T(weight(a)) * (ex * b.lid6[0] + ey * b.lid6[1] + ez * b.lid6[2]);
+      val = get(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
+      // the correction in the units of val
+      if (b.lid_on && b.wy && top)
+        val += T(weight(a) * (SU ? dev_scale(a) : 1.0f)) * (ex * b.lid6[0] + ey * b.lid6[1] + ez * b.lid6[2]);
     } else {
-      val = SS::dec(*(const S*)(sb + r0 + (uint64_t)a * dirb + (dy[ey + 1] + dz[ez + 1]) + xo[ex + 1]), a);
-      if (xwall) val = SS::dec(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
+      val = get(*(const S*)(sb + r0 + (uint64_t)a * dirb + (dy[ey + 1] + dz[ez + 1]) + xo[ex + 1]), a);
+      if (xwall) val = get(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
     }
     v[ez + 1][ey + 1][ex + 1] = val;
   }
@@ -299,7 +316,8 @@ __device__ __forceinline__ void pull_box(const typename Stor<ST>::S* __restrict_
 // relaxation time tau = tau_0 + 3 nu_t, nu_t = (C D)^2 |S|, is the positive root
 // of tau^2 - tau_0 tau - 9 sqrt(2) (C D)^2 |Pi| / (2 rho) = 0.  D uses the
 // distance to the nearest y wall half a link outside (uniform per wavefront).
-template <typename T>
+// SU: v carries the factor UNIT of the storage units.
+template <bool SU = false, typename T>
 __device__ __forceinline__ void les_rates(const T (&v)[3][3][3], T rho, const Box<T>& b, const Rates<T>& R, int y,
                                           int ny, T (&ws)[6], T (&cs)[6]) {
   const T k200 = v[0][0][2], k020 = v[0][2][0], k002 = v[2][0][0];
@@ -312,17 +330,17 @@ __device__ __forceinline__ void les_rates(const T (&v)[3][3][3], T rho, const Bo
   const T d = b.les_s > T(0) ? T(1) - exp(-yw * b.les_s * b.les_ia) : T(1);
   const T cd = b.les_c * d;
   const T tau0 = recip(R.w[4]);
-  const T tau = T(0.5) * (tau0 + sqrt(tau0 * tau0 + T(18.0 * 1.4142135623730951) * cd * cd * q * recip(rho)));
+  const T tau = T(0.5) * (tau0 + sqrt(tau0 * tau0 + T(18.0 * 1.4142135623730951 / Units<SU>::U) * cd * cd * q * recip(rho)));
   const T w = recip(tau);
   ws[0] = ws[1] = ws[2] = ws[4] = ws[5] = w;
   cs[0] = cs[1] = cs[2] = cs[4] = cs[5] = T(1) - w;
 }
 
-// store the post-collision cube (deviations times 2^inv_shift) of node
-// (x, y, z); same wavefront contract as pull().  The row base walks the 27
-// direction blocks of the segment in scalar registers; the per-lane part is
-// the x offset only.
-template <int ST>
+// store the post-collision cube (deviations times 2^inv_shift, and times
+// UNIT in storage units) of node (x, y, z); same wavefront contract as
+// pull().  The row base walks the 27 direction blocks of the segment in scalar
+// registers; the per-lane part is the x offset only.
+template <int ST, bool SU = false>
 __device__ __forceinline__ void push(typename Stor<ST>::S* __restrict__ dst, const Geom& g, int x, int y, int z,
                                      const typename Stor<ST>::R (&v)[3][3][3], uint32_t step) {
   using S = typename Stor<ST>::S;
@@ -336,7 +354,8 @@ __device__ __forceinline__ void push(typename Stor<ST>::S* __restrict__ dst, con
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     // streaming store: the next step reads it back from HBM, not from cache
-    __builtin_nontemporal_store(Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a), h + (uint32_t)a * 0x9E3779B9u),
+    __builtin_nontemporal_store(Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a) / Units<SU>::U,
+                                              h + (uint32_t)a * 0x9E3779B9u),
                                 (S*)(base + off));
     base += dirb;
   }

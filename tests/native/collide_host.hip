@@ -41,6 +41,36 @@ extern "C" void host_collide_maxwell_f64(const double* f, const double* omega, c
 extern "C" void host_collide_maxwell_f32(const double* f, const double* omega, const double* F, double* out) {
   run<float, true>(f, omega, F, out);
 }
+// The same collision in storage units (the FP16/BF16 kernels' arithmetic):
+// the cube comes in as deviations times dev_scale(alpha) and goes out times
+// UNIT; out holds the deviations times 2^inv_shift (scales removed), so that a
+// test can compare them bitwise with host_collide_dev_f32.
+template <bool SU, bool MAXWELL>
+static void run_dev(const float* dev, const double* omega, const double* F, float* out) {
+  float v[3][3][3];
+  for (int a = 0; a < Q; ++a) v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] = SU ? dev[a] * dev_scale(a) : dev[a];
+  Rates<float> R;
+  for (int j = 0; j < Q; ++j) {
+    R.w[j] = (float)omega[j];
+    R.c[j] = (float)(1.0 - omega[j]);
+    R.h[j] = (float)(1.0 - 0.5 * omega[j]);
+  }
+  const float ws[6] = {R.w[4], R.w[5], R.w[6], R.w[7], R.w[8], R.w[9]};
+  const float cs[6] = {R.c[4], R.c[5], R.c[6], R.c[7], R.c[8], R.c[9]};
+  float rho, ux, uy, uz;
+  collide<float, true, MAXWELL, SU>(v, R, ws, cs, (float)F[0], (float)F[1], (float)F[2], rho, ux, uy, uz);
+  for (int a = 0; a < Q; ++a) out[a] = v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] * (float)(1.0 / Units<SU>::U);
+}
+extern "C" void host_collide_dev_f32(const float* dev, const double* omega, const double* F, int maxwell, float* out) {
+  if (maxwell) run_dev<false, true>(dev, omega, F, out);
+  else run_dev<false, false>(dev, omega, F, out);
+}
+extern "C" void host_collide_units_f32(const float* dev, const double* omega, const double* F, int maxwell,
+                                       float* out) {
+  if (maxwell) run_dev<true, true>(dev, omega, F, out);
+  else run_dev<true, false>(dev, omega, F, out);
+}
+
 // f^eq(rho, u) through the kernels' inverse sweeps (what lbm_init stores)
 extern "C" void host_feq_f64(double rho, const double* u, double* out) {
   double v[3][3][3];

@@ -524,15 +524,17 @@ def test_closure_rejects_maxwellian_attractors():
 ])
 def test_box_walls_and_lid_match_oracle(shape, walls, lid, force):
     """Halfway bounce-back on any set of faces and the moving-lid correction
-    (reading R23) against the oracle: FP64 to 1e-12, FP32 to the per-step
-    bound, on ragged shapes and row blocks."""
+    (reading R23) against the oracle: FP64 to 1e-12, FP32 and the 16-bit
+    storage forms (whose arithmetic runs on the stored numbers, so the lid
+    correction is taken in their units) to the per-step bound, on ragged shapes
+    and row blocks."""
     nx, ny, nz = shape
     g0 = _state(shape, seed=90 + nx, amp=0.05)
     om = O.omega_table(0.02)
     steps = 5
     ref = O.run(g0, om, force, walls=walls, lid=lid, steps=steps)
     kw = dict(walls_y="y" in walls, walls_x="x" in walls, walls_z="z" in walls, lid_velocity=lid, force=force)
-    for storage in ("f64", "f32"):
+    for storage in ("f64", "f32", "f16dev", "bf16dev"):
         with L.Lattice(L.Config(nx, ny, nz, storage=storage, nu=0.02, **kw)) as lat:
             lat.set_f(g0)
             lat.step(steps)
@@ -540,7 +542,7 @@ def test_box_walls_and_lid_match_oracle(shape, walls, lid, force):
         if storage == "f64":
             assert _rel(got, ref) <= 1e-12, storage
         else:
-            assert np.all(np.abs(got - ref) <= _tol("f32", steps, ref))
+            assert np.all(np.abs(got - ref) <= _tol(storage, steps, ref)), storage
 
 
 def test_lid_driven_cavity_on_gpu_matches_oracle_and_keeps_mass():
@@ -582,7 +584,8 @@ def test_closure_rejects_box_walls():
 def test_symmetry_plane_and_les_match_oracle(shape, walls, les):
     """The Sec. 4 half channel (readings R24, R25): a wall below y = 0, a
     specular symmetry plane above y = ny - 1, body force, and the per-node
-    Smagorinsky rates; FP64 to 1e-12 and FP32 to the per-step bound."""
+    Smagorinsky rates; FP64 to 1e-12, FP32 and the 16-bit storage forms to the
+    per-step bound."""
     nx, ny, nz = shape
     g0 = _state(shape, seed=120 + nx, amp=0.05)
     om = O.omega_table(0.005)
@@ -592,7 +595,7 @@ def test_symmetry_plane_and_les_match_oracle(shape, walls, les):
     kw = dict(walls_y=True, walls_x="x" in walls, sym_top="s" in walls, force=force)
     if les is not None:
         kw.update(les_cs=les[0], les_wall_units=les[1], les_aplus=les[2])
-    for storage in ("f64", "f32"):
+    for storage in ("f64", "f32", "f16dev", "bf16dev"):
         with L.Lattice(L.Config(nx, ny, nz, storage=storage, nu=0.005, **kw)) as lat:
             lat.set_f(g0)
             lat.step(steps)
@@ -600,7 +603,7 @@ def test_symmetry_plane_and_les_match_oracle(shape, walls, les):
         if storage == "f64":
             assert _rel(got, ref) <= 1e-12, storage
         else:
-            assert np.all(np.abs(got - ref) <= _tol("f32", steps, ref))
+            assert np.all(np.abs(got - ref) <= _tol(storage, steps, ref)), storage
     if les is not None:  # the model acts on this state
         assert _rel(O.run(g0, om, force, walls=walls, steps=steps), ref) > 1e-6
 

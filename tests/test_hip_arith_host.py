@@ -24,6 +24,9 @@ def host():
     for n in ("host_collide_f64", "host_collide_f32", "host_collide_maxwell_f64", "host_collide_maxwell_f32"):
         getattr(lib, n).argtypes = [_dp, _dp, _dp, _dp]
     lib.host_feq_f64.argtypes = [ctypes.c_double, _dp, _dp]
+    _fp = ctypes.POINTER(ctypes.c_float)
+    for n in ("host_collide_dev_f32", "host_collide_units_f32"):
+        getattr(lib, n).argtypes = [_fp, _dp, _dp, ctypes.c_int, _fp]
     return lib
 
 
@@ -62,3 +65,34 @@ def test_host_equilibrium_matches_oracle(host, rho, u):
     uu = np.ascontiguousarray(u, dtype=np.float64)
     host.host_feq_f64(rho, uu.ctypes.data_as(_dp), out.ctypes.data_as(_dp))
     np.testing.assert_allclose(out, O.feq(rho, u), rtol=0, atol=4e-16)
+
+
+def _call_dev(fn, dev, om, F, maxwell):
+    fp = ctypes.POINTER(ctypes.c_float)
+    out = np.zeros(27, dtype=np.float32)
+    d = np.ascontiguousarray(dev, dtype=np.float32)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (om, F)]
+    fn(d.ctypes.data_as(fp), *(x.ctypes.data_as(_dp) for x in a), int(maxwell), out.ctypes.data_as(fp))
+    return out
+
+
+@pytest.mark.parametrize("maxwell", [False, True])
+@pytest.mark.parametrize("seed", range(16))
+def test_storage_unit_collision_is_bitwise_the_deviation_one(host, seed, maxwell):
+    """The FP16/BF16 kernels run the collision on the stored numbers (each
+    deviation times its power-of-two storage scale, moments times 2^18);
+    every factor is an exact power of two, so the post-collision deviations
+    must be bitwise those of the same FP32 arithmetic on plain deviations,
+    from deviations of 1e-9 w up to w."""
+    rng = np.random.default_rng(700 + seed)
+    u = 0.1 * rng.uniform(-1, 1, 3)
+    f = O.feq(1 + 0.05 * rng.uniform(-1, 1), u) * W.random_factors(27, seed, 0.2)
+    amp = 10.0 ** rng.uniform(-9, 0)  # overall size of the non-equilibrium part
+    dev = ((f - WA) * amp).astype(np.float32)
+    om = O.omega_table(10 ** rng.uniform(-5, -0.5), omega_bulk=rng.uniform(0.5, 1.9),
+                       omega_higher=rng.uniform(0.5, 1.9), mode="paper")
+    F = 1e-4 * rng.uniform(-1, 1, 3) * amp
+    a = _call_dev(host.host_collide_dev_f32, dev, om, F, maxwell)
+    b = _call_dev(host.host_collide_units_f32, dev, om, F, maxwell)
+    assert np.all(np.isfinite(a))
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), np.max(np.abs(a - b))
