@@ -348,6 +348,41 @@ def test_channel_sampled_nodes_f32(shape):
     assert ratio <= 1.0, ratio
 
 
+@pytest.mark.parametrize("storage,mant", [("f16dev", 10), ("bf16dev", 7)])
+def test_channel_sampled_nodes_16bit(storage, mant):
+    """The benchmark channel 256 x 128 x 128 in FP16 / BF16 deviation storage
+    (arithmetic on the stored numbers, stochastic rounding), in the launch
+    configuration the benchmark times: one step at sampled nodes (walls,
+    corners, interior) against the oracle's evaluation from the GPU's own
+    stored state.  Bound per value: one unit in the last place of the new
+    stored deviation (2^-mant relative; stochastic rounding may go either way),
+    the 16-bit subnormal spacing, and the FP32 arithmetic term."""
+    nx, ny, nz = 256, 128, 128
+    nu = 0.01
+    F = (8 * nu * 0.05 / ny ** 2, 0.0, 0.0)
+    rho, u = W.channel_turbulent_start(nx, ny, nz, u_bulk=0.03, amp=0.1, seed=1234, kmax=2)
+    rng = np.random.default_rng(78)
+    sel = np.unique(np.concatenate([
+        rng.integers(0, nx * ny * nz, 3000),
+        np.array([(z * ny + y) * nx + x for x in (0, 1, 63, 64, nx - 1) for y in (0, 1, ny - 1) for z in (0, nz - 1)]),
+    ]))
+    om = O.omega_table(nu)
+    with L.Lattice(L.Config(nx, ny, nz, storage=storage, walls_y=True, nu=nu, force=F)) as lat:
+        lat.init(rho, u)
+        lat.step(5)
+        g_prev = lat.get_f()
+        lat.step(1)
+        g_next = lat.get_f_nodes(sel)
+    ref = O.step_nodes(g_prev, sel, om, F, walls_y=True)
+    wa = W_ALPHA.reshape(27, 1)
+    # storage scale 2^(12 + 2|e|^2); the speed class |e|^2 from w_0 / w_alpha = 4^|e|^2
+    cls = np.rint(np.log(W_ALPHA.max() / W_ALPHA) / np.log(4.0)).reshape(27, 1)
+    scale = 2.0 ** (12 + 2 * cls)
+    tol = 2.0 ** -mant * np.abs(ref - wa) + 2.0 ** -24 / scale + 4e-7 * wa * 2
+    ratio = float((np.abs(g_next - ref) / tol).max())
+    assert ratio <= 1.0, ratio
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
 def test_get_f_nodes_equals_get_f(storage):
     """lbm_get_f_nodes returns exactly what lbm_get_f holds at the listed nodes
