@@ -129,6 +129,28 @@ def test_reduced_precision_within_stated_bound(storage, walls, force):
         assert ratio <= 1.0, (storage, steps, ratio)
 
 
+def test_f32_velocity_tracks_f64_over_2000_steps():
+    """FP32 storage against FP64 over 2,000 steps of a perturbed forced
+    channel.  Bound: the per-step FP32 bound on every population (4e-7 w_alpha)
+    carried into u_x = sum f e_x / rho is 4e-7 sum w_alpha |e_x| = 4e-7 / 3 per
+    step, and rounding errors of successive steps add like a random walk:
+    sqrt(2000) times that.  A systematic drift (errors adding up linearly)
+    would exceed it."""
+    nx, ny, nz = 64, 32, 16
+    F = (8 * 0.01 * 0.05 / ny ** 2, 0.0, 0.0)
+    rho, u = W.channel_turbulent_start(nx, ny, nz, u_bulk=0.03, amp=0.2, seed=9, kmax=2)
+    us = {}
+    for st in ("f64", "f32"):
+        with L.Lattice(L.Config(nx, ny, nz, storage=st, walls_y=True, nu=0.01, force=F)) as lat:
+            lat.init(rho, u)
+            lat.step(2000)
+            us[st] = lat.moments()[1]
+    err = float(np.abs(us["f32"] - us["f64"]).max())
+    bound = np.sqrt(2000) * 4e-7 / 3
+    print(f"max |u32 - u64| = {err:.3e} (bound {bound:.3e}; max |u64| = {np.abs(us['f64']).max():.4f})")
+    assert err <= bound, (err, bound)
+
+
 # ------------------------------------------------------------------ invariants on the GPU
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_mass_conserved_and_momentum_gains_force(storage):
