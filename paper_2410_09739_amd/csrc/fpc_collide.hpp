@@ -35,7 +35,7 @@
 // multiply.  The two outer points of every 3-point line share a scale and the
 // middle one has a quarter of it, so each sweep takes its middle value times 4
 // and its outputs carry the outer points' scale; after the three forward
-// sweeps every moment carries the one factor UNIT = 2^18.  The collision then
+// sweeps every moment carries the one factor UNIT = 2^18 (Units<SU>::U).  The collision then
 // runs on moments times UNIT: constants of the rest state and the force are
 // taken times UNIT and 1/rho (where it multiplies a product of two moments)
 // times 1/UNIT.  Every such factor is an exact power of two, so the results
