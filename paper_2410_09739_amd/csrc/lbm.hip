@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "lbm_internal.hpp"
 
@@ -114,20 +115,22 @@ __global__ __launch_bounds__(256) void k_get_f_nodes(const typename Stor<ST>::S*
 }
 
 // Step 7 fields from the stored post-collision state: rho = 1 + sum delta,
-// rho u = sum delta e - F/2.
+// rho u = sum delta e - F/2.  FP64 output sums in FP64 whatever the storage
+// (as the diagnostics do); FP32 output sums in the storage's arithmetic type.
 template <int ST, typename OUT>
 __global__ __launch_bounds__(256) void k_moments(const typename Stor<ST>::S* __restrict__ src, OUT* __restrict__ rho,
                                                  OUT* __restrict__ u, int64_t n, Geom g, double Fx, double Fy,
                                                  double Fz) {
   using T = typename Stor<ST>::R;
+  using A = typename std::conditional<sizeof(OUT) == sizeof(double), double, T>::type;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int x, y, z;
   node_xyz(g, i, x, y, z);
-  T v[3][3][3];
+  A v[3][3][3];
 #pragma unroll
-  for (int a = 0; a < Q; ++a) v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] = Stor<ST>::dec(src[pop_index(g, a, x, y, z)], a);
-  T rp, jx, jy, jz;
+  for (int a = 0; a < Q; ++a) v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] = (A)Stor<ST>::dec(src[pop_index(g, a, x, y, z)], a);
+  A rp, jx, jy, jz;
   density_momentum(v, rp, jx, jy, jz);
   const double r = 1.0 + (double)rp;
   if (rho) rho[i] = (OUT)r;

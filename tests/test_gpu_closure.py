@@ -161,12 +161,16 @@ def _state(shape, seed, amp=0.05):
     return O.init(rho, u) * W.random_factors((27, nz, ny, nx), seed=seed + 1, amplitude=amp)
 
 
+@pytest.mark.parametrize("shape,storage", [((16, 12, 8), "f64"), ((136, 10, 6), "f32"), ((130, 8, 4), "f16dev")])
 @pytest.mark.parametrize("walls", [False, True])
-def test_coarsen_and_targets_match_oracle(walls):
-    shape = (16, 12, 8)
+def test_coarsen_and_targets_match_oracle(walls, shape, storage):
+    """Box filter, filtered strain and targets against the oracle on the
+    GPU's own stored state (both sides in FP64 from the same populations):
+    one segment, and rows of 3 segments with a ragged last one in FP32 and
+    FP16 storage."""
     F = (2e-5, 0.0, 1e-5)
     g0 = _state(shape, 13)
-    with L.Lattice(L.Config(*shape, storage="f64", walls_y=walls, nu=0.02, force=F)) as fine:
+    with L.Lattice(L.Config(*shape, storage=storage, walls_y=walls, nu=0.02, force=F)) as fine:
         fine.set_f(g0)
         fine.step(2)
         g = fine.get_f()
