@@ -187,11 +187,13 @@ int lbm_step(lbm_ctx* c, int64_t n);
 int lbm_synchronize(lbm_ctx* c);
 
 /* Step 7 fields of the current time level to host arrays rho [N] and u [3][N]
- * (either may be NULL).  Synchronous. */
+ * (either may be NULL), summed in FP64 from the stored populations whatever
+ * the storage form.  Synchronous. */
 int lbm_moments(lbm_ctx* c, double* rho, double* u);
 
 /* Same fields into caller-owned device memory, enqueued on the stream:
- * rho_dev [N], u_dev [3][N]; element type double if f64 != 0, else float. */
+ * rho_dev [N], u_dev [3][N]; element type double if f64 != 0 (summed in FP64),
+ * else float (summed in the storage form's arithmetic type). */
 int lbm_moments_device(lbm_ctx* c, void* rho_dev, void* u_dev, int32_t f64);
 
 /* FP64 reductions over the current state (deterministic order).  Synchronous.
