@@ -178,6 +178,25 @@ def test_taylor_green_kinetic_energy_history_by_storage_form():
     assert dev["f32"] <= 0.01 and dev["f16dev"] <= 0.01, dev
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
+def test_moments_are_summed_in_fp64_for_every_form(storage):
+    """lbm_moments (FP64 output) equals the oracle's Step 7 fields of the same
+    stored populations to FP64 rounding, whatever the storage form: the sums
+    run in FP64, not in the storage's arithmetic type."""
+    shape = (70, 9, 6)
+    F = (2e-5, -1e-5, 0.0)
+    g0 = _state(shape, seed=61)
+    with L.Lattice(L.Config(*shape, storage=storage, walls_y=True, nu=0.02, force=F)) as lat:
+        lat.set_f(g0)
+        lat.step(3)
+        g = lat.get_f()
+        r_gpu, u_gpu = lat.moments()
+    r_ref, u_ref = O.macroscopic(g, force=F)
+    assert r_gpu.shape == r_ref.shape and u_gpu.shape == u_ref.shape
+    assert np.abs(r_gpu - r_ref).max() <= 1e-13
+    assert np.abs(u_gpu - u_ref).max() <= 1e-13 * np.abs(u_ref).max() + 1e-16
+
+
 # ------------------------------------------------------------------ invariants on the GPU
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_mass_conserved_and_momentum_gains_force(storage):
