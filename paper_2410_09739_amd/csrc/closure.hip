@@ -163,47 +163,73 @@ __global__ __launch_bounds__(256) void k_closure_eval(const float* __restrict__ 
 // u~ = avg(rho u) / rho~ (Favre), tau_ij = avg(rho u_i u_j) - rho~ u~_i u~_j,
 // order xx, yy, zz, xy, xz, yz.  Fine rho, u are the Step 7 fields of the stored
 // post-collision state (rho u = sum f~ e - F/2).  FP64 throughout.
+// One block per fine row segment pair in (y, z): wavefront w takes the 64 fine
+// nodes of segment blockIdx.x in row (2 Y + (w & 1), 2 Z + (w >> 1)), one node
+// per lane (coalesced loads of the blocked layout).  Each lane forms rho, j and
+// j_i j_j / rho of its node; lanes 2k and 2k + 1 add their x pair with a lane
+// shuffle, and the four rows of the block add through LDS, giving 32 coarse
+// nodes per block.  nx is even, so a pair lies wholly inside or outside the
+// grid.
+constexpr int CO_NV = 10;  // per fine node: rho, j (3), j_i j_j / rho (6)
 template <int ST>
 __global__ __launch_bounds__(256) void k_coarsen(const typename Stor<ST>::S* __restrict__ src, Geom g, double Fx,
                                                  double Fy, double Fz, double* __restrict__ rc, double* __restrict__ uc,
                                                  double* __restrict__ tc) {
-  const int cx = g.nx / 2, cy = g.ny / 2, cz = g.nz / 2;
-  const int64_t nc = (int64_t)cx * cy * cz;
-  const int64_t ic = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ic >= nc) return;
-  const int X = (int)(ic % cx), Y = (int)((ic / cx) % cy), Z = (int)(ic / ((int64_t)cx * cy));
-  double R = 0, M[3] = {0, 0, 0}, Tm[6] = {0, 0, 0, 0, 0, 0};
-  for (int dz = 0; dz < 2; ++dz)
-    for (int dy = 0; dy < 2; ++dy)
-      for (int dx = 0; dx < 2; ++dx) {
-        double rp = 0, j[3] = {0, 0, 0};
+  __shared__ double part[4][CO_NV][32];
+  const int cx = g.nx / 2, cy = g.ny / 2;
+  const int64_t nc = (int64_t)cx * cy * (g.nz / 2);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int Y = blockIdx.y, Z = blockIdx.z;
+  const int x = blockIdx.x * SEG + lane, y = 2 * Y + (w & 1), z = 2 * Z + (w >> 1);
+  double q[CO_NV];
 #pragma unroll
-        for (int a = 0; a < Q; ++a) {
-          const double d = (double)Stor<ST>::dec(src[pop_index(g, a, 2 * X + dx, 2 * Y + dy, 2 * Z + dz)], a);
-          rp += d;
-          j[0] += EX[a] * d;
-          j[1] += EY[a] * d;
-          j[2] += EZ[a] * d;
-        }
-        const double r = 1.0 + rp;
-        j[0] -= 0.5 * Fx;
-        j[1] -= 0.5 * Fy;
-        j[2] -= 0.5 * Fz;
-        R += r;
-        for (int d = 0; d < 3; ++d) M[d] += j[d];
-        Tm[0] += j[0] * j[0] / r;
-        Tm[1] += j[1] * j[1] / r;
-        Tm[2] += j[2] * j[2] / r;
-        Tm[3] += j[0] * j[1] / r;
-        Tm[4] += j[0] * j[2] / r;
-        Tm[5] += j[1] * j[2] / r;
-      }
-  const double rb = R / 8.0;
-  const double u[3] = {M[0] / R, M[1] / R, M[2] / R};
+  for (int k = 0; k < CO_NV; ++k) q[k] = 0.0;
+  if (x < g.nx) {
+    double rp = 0, j0 = 0, j1 = 0, j2 = 0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const double d = (double)Stor<ST>::dec(src[pop_index(g, a, x, y, z)], a);
+      rp += d;
+      j0 += EX[a] * d;
+      j1 += EY[a] * d;
+      j2 += EZ[a] * d;
+    }
+    const double r = 1.0 + rp;
+    j0 -= 0.5 * Fx;
+    j1 -= 0.5 * Fy;
+    j2 -= 0.5 * Fz;
+    const double ir = 1.0 / r;
+    q[0] = r;
+    q[1] = j0;
+    q[2] = j1;
+    q[3] = j2;
+    q[4] = j0 * j0 * ir;
+    q[5] = j1 * j1 * ir;
+    q[6] = j2 * j2 * ir;
+    q[7] = j0 * j1 * ir;
+    q[8] = j0 * j2 * ir;
+    q[9] = j1 * j2 * ir;
+  }
+#pragma unroll
+  for (int k = 0; k < CO_NV; ++k) q[k] += __shfl_xor(q[k], 1);
+  if (!(lane & 1)) {
+#pragma unroll
+    for (int k = 0; k < CO_NV; ++k) part[w][k][lane >> 1] = q[k];
+  }
+  __syncthreads();
+  if (w != 0 || lane >= 32) return;
+  const int X = blockIdx.x * (SEG / 2) + lane;
+  if (X >= cx) return;
+  double t[CO_NV];
+#pragma unroll
+  for (int k = 0; k < CO_NV; ++k) t[k] = (part[0][k][lane] + part[1][k][lane]) + (part[2][k][lane] + part[3][k][lane]);
+  const int64_t ic = X + (int64_t)cx * (Y + (int64_t)cy * Z);
+  const double R = t[0], rb = R / 8.0;
+  const double u[3] = {t[1] / R, t[2] / R, t[3] / R};
   rc[ic] = rb;
   for (int d = 0; d < 3; ++d) uc[d * nc + ic] = u[d];
   const int pi[6] = {0, 1, 2, 0, 0, 1}, pj[6] = {0, 1, 2, 1, 2, 2};
-  for (int k = 0; k < 6; ++k) tc[k * nc + ic] = Tm[k] / 8.0 - rb * u[pi[k]] * u[pj[k]];
+  for (int k = 0; k < 6; ++k) tc[k * nc + ic] = t[4 + k] / 8.0 - rb * u[pi[k]] * u[pj[k]];
 }
 
 // strain rate S_ij = (d_i u_j + d_j u_i)/2 by centred differences (periodic x,
@@ -697,15 +723,18 @@ extern "C" int lbm_coarsen(lbm_ctx* c, double* rho_dev, double* u_dev, double* t
   if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_coarsen: state not initialised");
   if (c->cfg.nx % 2 || c->cfg.ny % 2 || c->cfg.nz % 2)
     return set_err(c, LBM_EINVAL, "lbm_coarsen: nx, ny, nz must be even");
+  if (c->cfg.ny / 2 > 65535 || c->cfg.nz / 2 > 65535)
+    return set_err(c, LBM_EINVAL, "lbm_coarsen: ny / 2 and nz / 2 must not exceed 65535");
   if (sbar_dev && bc_kind(c) == 2)
     return set_err(c, LBM_EINVAL, "lbm_coarsen: the filtered strain needs a periodic or y-wall lattice");
   HIPCHK(c, hipSetDevice(c->device));
   const Geom g = geom(c);
   const int64_t nc = c->n / 8;
   const double* F = c->cfg.force;
+  const dim3 cgrid((unsigned)g.nxs, (unsigned)(c->cfg.ny / 2), (unsigned)(c->cfg.nz / 2));  // y, z <= 65535: checked above
   DISPATCH_ST(c->cfg.storage,
-              k_coarsen<ST><<<nblocks(nc, 256), 256, 0, c->stream>>>((const typename Stor<ST>::S*)c->buf[c->cur], g,
-                                                                      F[0], F[1], F[2], rho_dev, u_dev, tau_dev));
+              k_coarsen<ST><<<cgrid, 256, 0, c->stream>>>((const typename Stor<ST>::S*)c->buf[c->cur], g, F[0], F[1],
+                                                          F[2], rho_dev, u_dev, tau_dev));
   LAUNCHCHK(c);
   if (sbar_dev) {
     int rc = alloc_scratch(c);
