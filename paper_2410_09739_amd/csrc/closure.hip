@@ -235,11 +235,10 @@ __global__ __launch_bounds__(256) void k_coarsen(const typename Stor<ST>::S* __r
 // strain rate S_ij = (d_i u_j + d_j u_i)/2 by centred differences (periodic x,
 // z; periodic y or an antisymmetric ghost across the half-link walls), order
 // xx, yy, zz, xy, xz, yz
-__device__ __forceinline__ void strain_at(const double* __restrict__ u, const Geom& g, int walls, int64_t i,
-                                          double (&S)[6]) {
+__device__ __forceinline__ void strain_xyz(const double* __restrict__ u, const Geom& g, int walls, int x, int y,
+                                           int z, double (&S)[6]) {
   const int64_t n = (int64_t)g.nx * g.ny * g.nz;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
   const int xp = x == nx - 1 ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
   const int zp = z == nz - 1 ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
   int yp = y == ny - 1 ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
@@ -261,6 +260,14 @@ __device__ __forceinline__ void strain_at(const double* __restrict__ u, const Ge
   S[3] = 0.5 * (gr[0][1] + gr[1][0]);
   S[4] = 0.5 * (gr[0][2] + gr[2][0]);
   S[5] = 0.5 * (gr[1][2] + gr[2][1]);
+}
+
+// the same at the flat node index i = x + nx (y + ny z) (below 2^31)
+__device__ __forceinline__ void strain_at(const double* __restrict__ u, const Geom& g, int walls, int64_t i,
+                                          double (&S)[6]) {
+  const uint32_t ii = (uint32_t)i, nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
+  const uint32_t r = ii / nx;
+  strain_xyz(u, g, walls, (int)(ii - r * nx), (int)(r % ny), (int)(r / ny), S);
 }
 
 constexpr int RB = 1024;  // blocks of the fixed-order reductions
@@ -307,23 +314,25 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 // strain of the fine velocity (rho, u: fine fields, u as [3][N]).
 __global__ __launch_bounds__(256) void k_filtered_strain(const double* __restrict__ rho, const double* __restrict__ u,
                                                          Geom g, int walls, double* __restrict__ sb) {
-  const int cx = g.nx / 2, cy = g.ny / 2, cz = g.nz / 2;
-  const int64_t nc = (int64_t)cx * cy * cz;
-  const int64_t ic = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t cx = g.nx / 2, cy = g.ny / 2, cz = g.nz / 2;
+  const uint32_t nc = cx * cy * cz;  // below 2^31
+  const uint32_t ic = blockIdx.x * blockDim.x + threadIdx.x;
   if (ic >= nc) return;
-  const int X = (int)(ic % cx), Y = (int)((ic / cx) % cy), Z = (int)(ic / ((int64_t)cx * cy));
+  const uint32_t r = ic / cx;
+  const int X = (int)(ic - r * cx), Y = (int)(r % cy), Z = (int)(r / cy);
   double R = 0.0, A[6] = {0, 0, 0, 0, 0, 0};
   for (int dz = 0; dz < 2; ++dz)
     for (int dy = 0; dy < 2; ++dy)
       for (int dx = 0; dx < 2; ++dx) {
-        const int64_t i = ((int64_t)(2 * Z + dz) * g.ny + (2 * Y + dy)) * g.nx + (2 * X + dx);
+        const int x = 2 * X + dx, y = 2 * Y + dy, z = 2 * Z + dz;
+        const int64_t i = ((int64_t)z * g.ny + y) * g.nx + x;
         double S[6];
-        strain_at(u, g, walls, i, S);
+        strain_xyz(u, g, walls, x, y, z, S);
         const double r = rho[i];
         R += r;
         for (int k = 0; k < 6; ++k) A[k] += r * S[k];
       }
-  for (int k = 0; k < 6; ++k) sb[k * nc + ic] = 2.0 * A[k] / R;
+  for (int k = 0; k < 6; ++k) sb[(int64_t)k * nc + ic] = 2.0 * A[k] / R;
 }
 
 // nu*_j = max(0, S_j (nu_j (Sbar_j - S_j) - tau_j / (2 rho)) / (S_j^2 + eps^2))
