@@ -270,3 +270,107 @@ def macroscopic(state: np.ndarray, force=(0.0, 0.0, 0.0), post_collision: bool =
     for d in range(3):
         j[d] += sgn * force[d]
     return rho, j / rho
+
+
+# ---------------------------------------------------------------- diagnostics
+def _ghosted(u: np.ndarray, mask: int, lid) -> np.ndarray:
+    """The velocity field [3, nz, ny, nx] with one ghost layer on every side.
+
+    Periodic axes wrap.  Across a half-link wall at rest the ghost holds -u of
+    the adjacent fluid node (u = 0 halfway between them); across the moving lid
+    above y = ny - 1 it holds 2 U - u (u = U halfway); across the specular
+    symmetry plane above y = ny - 1 the tangential components u_x, u_z mirror
+    (ghost = u) and the normal one u_y changes sign.  Corners of the ghost layer
+    are never read by the centred differences."""
+    _, nz, ny, nx = u.shape
+    g = np.zeros((3, nz + 2, ny + 2, nx + 2))
+    g[:, 1:-1, 1:-1, 1:-1] = u
+    # x faces
+    if mask & 2:
+        g[:, 1:-1, 1:-1, 0] = -u[:, :, :, 0]
+        g[:, 1:-1, 1:-1, -1] = -u[:, :, :, -1]
+    else:
+        g[:, 1:-1, 1:-1, 0] = u[:, :, :, -1]
+        g[:, 1:-1, 1:-1, -1] = u[:, :, :, 0]
+    # z faces
+    if mask & 4:
+        g[:, 0, 1:-1, 1:-1] = -u[:, 0]
+        g[:, -1, 1:-1, 1:-1] = -u[:, -1]
+    else:
+        g[:, 0, 1:-1, 1:-1] = u[:, -1]
+        g[:, -1, 1:-1, 1:-1] = u[:, 0]
+    # y faces
+    if mask & 1:
+        g[:, 1:-1, 0, 1:-1] = -u[:, :, 0, :]
+        top = u[:, :, -1, :]
+        if mask & 8:
+            g[:, 1:-1, -1, 1:-1] = top * np.array([1.0, -1.0, 1.0])[:, None, None]
+        elif lid is not None:
+            g[:, 1:-1, -1, 1:-1] = 2.0 * np.asarray(lid, dtype=np.float64)[:, None, None] - top
+        else:
+            g[:, 1:-1, -1, 1:-1] = -top
+    else:
+        g[:, 1:-1, 0, 1:-1] = u[:, :, -1, :]
+        g[:, 1:-1, -1, 1:-1] = u[:, :, 0, :]
+    return g
+
+
+def vorticity(u: np.ndarray, walls_y: bool = False, walls=None, lid=None) -> np.ndarray:
+    """curl u [3, nz, ny, nx] by second-order centred differences,
+    d_x q(i) = (q(i+1) - q(i-1)) / 2 (lattice units), with the ghost layers of
+    ``_ghosted`` at walls, the lid and the symmetry plane."""
+    g = _ghosted(_f64(u), _walls(walls_y, walls), lid)
+
+    def d(c, axis):  # centred difference of component c along axis (0 x, 1 y, 2 z)
+        if axis == 0:
+            return 0.5 * (g[c, 1:-1, 1:-1, 2:] - g[c, 1:-1, 1:-1, :-2])
+        if axis == 1:
+            return 0.5 * (g[c, 1:-1, 2:, 1:-1] - g[c, 1:-1, :-2, 1:-1])
+        return 0.5 * (g[c, 2:, 1:-1, 1:-1] - g[c, :-2, 1:-1, 1:-1])
+
+    return np.stack([d(2, 1) - d(1, 2), d(0, 2) - d(2, 0), d(1, 0) - d(0, 1)])
+
+
+def diagnostics(state: np.ndarray, force=(0.0, 0.0, 0.0), walls_y: bool = False, walls=None, lid=None) -> dict:
+    """FP64 diagnostics of a post-collision lattice state, from their definitions:
+    mass sum rho; momentum sum rho u (Appendix D Step 7, with the F/2 shift);
+    kinetic energy 1/2 sum rho |u|^2; enstrophy 1/2 sum |curl u|^2 (``vorticity``);
+    max |u|; min rho; nodes with a non-finite population; and the force of the
+    fluid on the walls, sum over the bounce-back links of 2 f~_a e_a (a link
+    leaves a fluid node towards a wall; the symmetry plane takes no force)."""
+    f = _f64(state)
+    mask = _walls(walls_y, walls)
+    rho, u = macroscopic(f, force)
+    e, _, _ = lattice()
+    wall = np.zeros(3)
+    _, nz, ny, nx = f.shape
+    for a in range(Q):
+        ex, ey, ez = (int(c) for c in e[a])
+        sel = np.zeros((nz, ny, nx), dtype=bool)
+        if mask & 1:
+            if ey == -1:
+                sel[:, 0, :] = True
+            if ey == 1 and not mask & 8:
+                sel[:, ny - 1, :] = True
+        if mask & 2:
+            if ex == -1:
+                sel[:, :, 0] = True
+            if ex == 1:
+                sel[:, :, nx - 1] = True
+        if mask & 4:
+            if ez == -1:
+                sel[0] = True
+            if ez == 1:
+                sel[nz - 1] = True
+        wall += 2.0 * f[a][sel].sum() * e[a]
+    w = vorticity(u, walls=mask, lid=lid)
+    return {
+        "mass": float(rho.sum()),
+        "momentum": [float((rho * u[d]).sum()) for d in range(3)],
+        "kinetic_energy": float(0.5 * (rho * (u ** 2).sum(0)).sum()),
+        "enstrophy": float(0.5 * (w ** 2).sum()),
+        "max_speed": float(np.sqrt((u ** 2).sum(0)).max()),
+        "min_rho": float(rho.min()),
+        "n_nonfinite": int((~np.isfinite(f)).any(0).sum()),
+        "wall_force": wall.tolist(),
+    }

@@ -255,3 +255,66 @@ def test_filtered_strain_matches_a_loop_over_boxes():
                                 rsum += rho[z, y, x]
                     ref[:, Z, Y, X] = 2.0 * acc / rsum
         np.testing.assert_allclose(C.filtered_strain(rho, u, walls), ref, rtol=1e-12, atol=1e-16)
+
+
+def test_bf16_rounding_equals_torch_cpu_cast():
+    """round_bf16 against an independent implementation of the same rounding:
+    torch's CPU float32 -> bfloat16 conversion (round to nearest, ties to even).
+    Inputs cover random magnitudes, exact ties (low 16 bits 0x8000) with even and
+    odd kept halves, values next to ties, subnormals, the overflow edge, signed
+    zeros and infinities."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(123)
+    mant = rng.integers(0, 1 << 23, 4000, dtype=np.uint64)
+    expo = rng.integers(1, 255, 4000, dtype=np.uint64)
+    sign = rng.integers(0, 2, 4000, dtype=np.uint64)
+    bits = (sign << 31) | (expo << 23) | mant
+    ties = (bits & ~np.uint64(0xFFFF)) | np.uint64(0x8000)
+    near = np.concatenate([ties - 1, ties + 1])
+    sub = rng.integers(1, 1 << 23, 500, dtype=np.uint64)
+    edge = np.array([0x7F7F7FFF, 0x7F7F8000, 0x7F7FFFFF, 0x80000000, 0x00000000, 0x7F800000, 0xFF800000,
+                     0x00008000, 0x00018000, 0x3F808000, 0x3F818000], dtype=np.uint64)
+    allbits = np.concatenate([bits, ties, near, sub, edge]).astype(np.uint32)
+    x = allbits.view(np.float32)
+    ref = torch.from_numpy(x.copy()).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+    got = C.round_bf16(x)
+    np.testing.assert_array_equal(np.signbit(got), np.signbit(ref))
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_splitmix64_output_function_reproduces_the_published_sequence():
+    """The generator's mixing function is SplitMix64's (Steele, Lea and Flood,
+    2014).  Stepping the state by the golden gamma 0x9E3779B97F4A7C15 from the
+    seed 1234567 gives the sequence published with the reference implementation
+    (Vigna's splitmix64.c test values)."""
+    M = (1 << 64) - 1
+    s, out = 1234567, []
+    for _ in range(5):
+        s = (s + 0x9E3779B97F4A7C15) & M
+        out.append(C._mix64(s))
+    assert out == [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                   4593380528125082431, 16408922859458223821]
+
+
+def test_minibatch_indices_follow_their_definition_and_are_uniform():
+    """sample_indices: slot j of step t is mix64(seed ^ mix64(t gamma + j)) mod n,
+    checked against the published-sequence generator above for the inner word;
+    the indices stay in [0, n), differ between steps and seeds, and a large
+    draw is uniform over n bins (chi-square at the 1e-4 level)."""
+    M = (1 << 64) - 1
+    gamma = 0x9E3779B97F4A7C15
+    for seed, t, n in [(7, 0, 1000), (123456789, 41, 17), (2**63 + 5, 9999, 1 << 20)]:
+        idx = C.sample_indices(seed, t, 64, n)
+        for j in (0, 1, 63):
+            inner = C._mix64((t * gamma + j) & M)
+            assert idx[j] == C._mix64(seed ^ inner) % n
+        assert idx.min() >= 0 and idx.max() < n
+    assert not np.array_equal(C.sample_indices(1, 0, 64, 1 << 30), C.sample_indices(1, 1, 64, 1 << 30))
+    assert not np.array_equal(C.sample_indices(1, 0, 64, 1 << 30), C.sample_indices(2, 0, 64, 1 << 30))
+    n = 50
+    draws = np.concatenate([C.sample_indices(99, t, 500, n) for t in range(40)])
+    counts = np.bincount(draws, minlength=n)
+    expect = draws.size / n
+    chi2 = float(((counts - expect) ** 2 / expect).sum())
+    from scipy.stats import chi2 as chi2dist
+    assert chi2dist.sf(chi2, n - 1) > 1e-4

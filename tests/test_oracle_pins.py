@@ -248,6 +248,120 @@ def test_each_group_relaxes_at_its_own_rate():
                 assert h(kt) == pytest.approx(h(k1), abs=1e-15), (j, i)
 
 
+# Combined moments of orders 4-6 and the rate that relaxes each one
+# (Appendix D Step 3): omega_17..19 the fourth-order combinations 4s1, 4d1,
+# 4d2; omega_20..22 the moments 211, 121, 112; omega_23..25 122, 212, 221;
+# omega_26 the sixth-order moment 222.
+HIGH_GROUPS = {
+    17: lambda k: k[IX["220"]] + k[IX["202"]] + k[IX["022"]],
+    18: lambda k: k[IX["220"]] + k[IX["202"]] - k[IX["022"]],
+    19: lambda k: k[IX["220"]] - k[IX["202"]],
+    20: lambda k: k[IX["211"]], 21: lambda k: k[IX["121"]], 22: lambda k: k[IX["112"]],
+    23: lambda k: k[IX["122"]], 24: lambda k: k[IX["212"]], 25: lambda k: k[IX["221"]],
+}
+
+
+@pytest.mark.parametrize("j", sorted(HIGH_GROUPS) + [26])
+def test_each_higher_order_group_relaxes_at_its_own_rate(j):
+    """Orders 4-6, one rate at a time.  With F = 0 and every other rate 1, the
+    post-collision orders 2 and 3 are at equilibrium (kappa~_200 = rho c_s^2,
+    off-diagonal and third-order moments 0), so the attractors built from them
+    (Sec. 3.5, Eq. Mvcmattractor3D) take closed forms: kappa^Mv_220 = kappa^Mv_202
+    = kappa^Mv_022 = rho c_s^4 (4s1 -> rho/3, 4d1 -> rho/9, 4d2 -> 0), the mixed
+    fourth- and fifth-order attractors vanish, and kappa^Mv_222 =
+    (c_s^2 / 3) (kappa~_220 + kappa~_202 + kappa~_022) with the post-collision
+    fourth order.  The group relaxed with omega_j must move by
+    omega_j (kappa^Mv - kappa) and every other group must keep its unit-rate
+    value; a swap of two rates (e.g. omega_20 with omega_23) fails here."""
+    f = _state(7 + j, amp=0.25)
+    base = np.ones(27)
+    _, _, k1 = O.collide_node(f, base, return_moments=True)
+    om = base.copy()
+    om[j] = 0.35
+    _, kp, kt = O.collide_node(f, om, return_moments=True)
+    rho = kp[0]
+    cs2 = 1.0 / 3.0
+    eq4 = {17: 3 * rho * cs2 * cs2, 18: rho * cs2 * cs2, 19: 0.0}
+    if j == 26:
+        target = cs2 / 3.0 * (kt[IX["220"]] + kt[IX["202"]] + kt[IX["022"]])
+        assert target == pytest.approx(rho / 27.0, rel=1e-14)  # fourth order at equilibrium here
+        got, pre = kt[IX["222"]], kp[IX["222"]]
+    else:
+        target = eq4.get(j, 0.0)
+        got, pre = HIGH_GROUPS[j](kt), HIGH_GROUPS[j](kp)
+    assert got == pytest.approx(pre + 0.35 * (target - pre), rel=1e-12, abs=1e-16), j
+    for i, h in HIGH_GROUPS.items():
+        if i != j:
+            assert h(kt) == pytest.approx(h(k1), abs=1e-15), (j, i)
+    if j not in (17, 18, 19, 26):
+        # the sixth-order moment sees the fourth-order combinations only
+        assert kt[IX["222"]] == pytest.approx(k1[IX["222"]], abs=1e-15), j
+
+
+@pytest.mark.parametrize("j", [17, 18, 19])
+def test_sixth_order_attractor_uses_the_post_collision_fourth_order(j):
+    """A fourth-order rate away from 1 leaves the fourth order off equilibrium
+    after the collision; with omega_26 = 1, kappa~_222 must equal the attractor
+    (c_s^2 / 3)(kappa~_220 + kappa~_202 + kappa~_022) of those post-collision
+    values (orders 2 and 3 at equilibrium), not of the pre-collision ones."""
+    f = _state(31 + j, amp=0.3)
+    om = np.ones(27)
+    om[j] = 1.7
+    _, kp, kt = O.collide_node(f, om, return_moments=True)
+    post = kt[IX["220"]] + kt[IX["202"]] + kt[IX["022"]]
+    pre = kp[IX["220"]] + kp[IX["202"]] + kp[IX["022"]]
+    assert abs(post - pre) > 1e-4 * kp[0]
+    assert kt[IX["222"]] == pytest.approx(post / 9.0, rel=1e-13)
+    assert abs(kt[IX["222"]] - pre / 9.0) > 1e-6
+
+
+def _moment_order(j):
+    """Order of the moments relaxed with omega_j, read off the lattice's moment
+    exponents of one member of the group (Appendix D Step 3)."""
+    member = {4: "110", 5: "101", 6: "011", 7: "200", 8: "200", 9: "200", 10: "120", 11: "120",
+              12: "210", 13: "210", 14: "201", 15: "201", 16: "111", 17: "220", 18: "220", 19: "220",
+              20: "211", 21: "121", 22: "112", 23: "122", 24: "212", 25: "221", 26: "222"}[j]
+    _, _, mnp = O.lattice()
+    return int(mnp[IX[member]].sum())
+
+
+@pytest.mark.parametrize("nu", [1e-6, 1e-3, 0.01, 1.0 / 6.0, 0.5, 10.0])
+def test_order_scaled_rates_are_the_trapezoidal_discretisation_of_order_times_omega_fp(nu):
+    """Eq. (FPcoll3d): the continuous model relaxes a moment of order n = m+n+p at
+    n omega_FP.  Second order: 2 omega_FP, and the shear viscosity fixes the
+    discrete omega_2 through Eq. (transportcoeff3DFPCLBM).  The lattice rates are
+    the Henon (trapezoidal, Crank-Nicolson) integration of a linear relaxation at
+    rate lambda over one step: omega = lambda / (1 + lambda / 2).  So omega_FP
+    follows from omega_2 and every higher group must carry lambda = n omega_FP
+    with n its moments' order; all rates stay in (0, 2)."""
+    om = O.omega_table(nu, mode="order_scaled")
+    w2 = om[4]
+    lam2 = w2 / (1.0 - w2 / 2.0)  # inverse of the trapezoidal map
+    omega_fp = lam2 / 2.0
+    assert nu == pytest.approx((1.0 / 3.0) / (2.0 * omega_fp), rel=1e-12)  # nu = c_s^2 / lambda_2
+    for j in range(10, 27):
+        n = _moment_order(j)
+        lam = n * omega_fp
+        assert om[j] == pytest.approx(lam / (1.0 + lam / 2.0), rel=1e-13), (j, n)
+        assert 0.0 < om[j] < 2.0
+    # bulk and shear rates are not order-scaled
+    assert om[7] == 1.0 and np.all(om[[4, 5, 6, 8, 9]] == w2)
+
+
+def test_order_scaled_rates_approach_the_continuous_ratio_for_slow_relaxation():
+    """For slow relaxation (omega_2 -> 0, large viscosity) the discrete rates tend
+    to the continuous ones, omega_n / omega_2 -> n / 2 (Eq. FPcoll3d), with an
+    O(omega_2) deviation; for fast relaxation they stay below 2."""
+    for nu in [1e3, 1e5, 1e7]:
+        om = O.omega_table(nu, mode="order_scaled")
+        w2 = om[4]
+        for j in range(10, 27):
+            n = _moment_order(j)
+            assert om[j] / w2 == pytest.approx(n / 2.0, rel=2 * w2 * n), (nu, j)
+    om = O.omega_table(1e-9, mode="order_scaled")
+    assert np.all(om < 2.0) and np.all(om[10:] > om[4] - 1e-9)
+
+
 def _cube_maps():
     e, _, _ = O.lattice()
     for perm in itertools.permutations(range(3)):
@@ -622,3 +736,132 @@ def test_streaming_in_place_without_double_buffer_is_caught():
                     f[a, z, y, x] = f[a, (z - e[a, 2]) % nz, (y - e[a, 1]) % ny, (x - e[a, 0]) % nx]
     good = O.stream(g)
     assert np.abs(f - good).max() > 1e-3 * np.abs(good).max()
+
+
+# ------------------------------------------------------------------ diagnostics
+def _grid(nx, ny, nz):
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    return x, y, z
+
+
+@pytest.mark.parametrize("n", [8, 12])
+def test_enstrophy_of_the_taylor_green_field_is_the_closed_form(n):
+    """u = u0 sin kx cos ky cos kz, v = -u0 cos kx sin ky cos kz, w = 0 with
+    k = 2 pi / n (cell-centred, periodic).  Its curl is
+    (-u0 k cos kx sin ky sin kz, -u0 k sin kx cos ky sin kz, 2 u0 k sin kx sin ky cos kz);
+    a centred difference of sin(k x) or cos(k x) equals the derivative times
+    sin(k) / k, and the grid means of the squared products are 1/8, so
+    1/2 sum |curl u|^2 = (3/8) u0^2 sin(k)^2 n^3."""
+    u0, k = 0.05, 2 * np.pi / n
+    x, y, z = _grid(n, n, n)
+    u = np.stack([u0 * np.sin(k * x) * np.cos(k * y) * np.cos(k * z),
+                  -u0 * np.cos(k * x) * np.sin(k * y) * np.cos(k * z), np.zeros_like(x)])
+    w = O.vorticity(u)
+    s = np.sin(k)
+    np.testing.assert_allclose(w[2], 2 * u0 * s * np.sin(k * x) * np.sin(k * y) * np.cos(k * z), atol=1e-15)
+    np.testing.assert_allclose(w[0], -u0 * s * np.cos(k * x) * np.sin(k * y) * np.sin(k * z), atol=1e-15)
+    ens = 0.5 * float((w ** 2).sum())
+    assert ens == pytest.approx(3.0 / 8.0 * u0 ** 2 * s ** 2 * n ** 3, rel=1e-12)
+    # through the lattice state: f^eq of the field, rho = 1
+    d = O.diagnostics(O.init(np.ones((n, n, n)), u))
+    assert d["enstrophy"] == pytest.approx(ens, rel=1e-12)
+    assert d["kinetic_energy"] == pytest.approx(0.5 * float((u ** 2).sum()), rel=1e-13)
+    assert d["max_speed"] == pytest.approx(float(np.sqrt((u ** 2).sum(0)).max()), rel=1e-13)
+    assert d["min_rho"] == pytest.approx(1.0, abs=1e-14)
+    assert d["mass"] == pytest.approx(n ** 3, rel=1e-14)
+
+
+@pytest.mark.parametrize("n", [6, 10])
+def test_vorticity_of_the_abc_beltrami_flow_is_sin_k_times_the_velocity(n):
+    """The Arnold-Beltrami-Childress field u = (A sin kz + C cos ky,
+    B sin kx + A cos kz, C sin ky + B cos kx) has curl u = k u; with centred
+    differences every derivative carries sin(k)/k, so the discrete curl is
+    sin(k) u, element by element, in all three components (a wrong sign or
+    index in any of the six derivatives fails)."""
+    A, B, C = 0.03, -0.02, 0.05
+    k = 2 * np.pi / n
+    x, y, z = _grid(n, n + 0, n)
+    u = np.stack([A * np.sin(k * z) + C * np.cos(k * y), B * np.sin(k * x) + A * np.cos(k * z),
+                  C * np.sin(k * y) + B * np.cos(k * x)])
+    np.testing.assert_allclose(O.vorticity(u), np.sin(k) * u, atol=1e-16)
+
+
+@pytest.mark.parametrize("case", ["walls", "symmetry"])
+def test_enstrophy_of_a_sine_profile_between_walls_and_under_a_symmetry_plane(case):
+    """u_x(y) = sin(kappa (y + 1/2)) vanishes at the half-link wall y = -1/2 and is
+    odd about it; with kappa = pi / H it also vanishes at the upper wall
+    y = H - 1/2, with kappa = pi / (2H) it is even about the symmetry plane
+    there.  The ghost layers (-u at a wall, mirrored tangential velocity at the
+    plane) are then exact extensions, every centred difference is
+    sin(kappa) cos(kappa (y + 1/2)), and the sum over y of cos^2 is H / 2:
+    1/2 sum |curl u|^2 = (1/4) nx nz H sin(kappa)^2."""
+    nx, ny, nz = 4, 10, 3
+    kap = np.pi / ny if case == "walls" else np.pi / (2 * ny)
+    walls = "y" if case == "walls" else "ys"
+    _, y, _ = _grid(nx, ny, nz)
+    u = np.stack([np.sin(kap * y), np.zeros_like(y), np.zeros_like(y)])
+    w = O.vorticity(u, walls=walls)
+    np.testing.assert_allclose(w[2], -np.sin(kap) * np.cos(kap * y), atol=1e-15)
+    assert 0.5 * float((w ** 2).sum()) == pytest.approx(0.25 * nx * nz * ny * np.sin(kap) ** 2, rel=1e-12)
+    # the same profile along z between z walls, and along x between x walls
+    xg, _, zg = _grid(6, 5, 8)
+    kz = np.pi / 8
+    uz = np.stack([np.sin(kz * zg), np.zeros_like(zg), np.zeros_like(zg)])
+    wz = O.vorticity(uz, walls="z")
+    assert 0.5 * float((wz ** 2).sum()) == pytest.approx(0.25 * 6 * 5 * 8 * np.sin(kz) ** 2, rel=1e-12)
+    kx = np.pi / 6
+    ux = np.stack([np.zeros_like(xg), np.sin(kx * xg), np.zeros_like(xg)])
+    wx = O.vorticity(ux, walls="x")
+    assert 0.5 * float((wx ** 2).sum()) == pytest.approx(0.25 * 6 * 5 * 8 * np.sin(kx) ** 2, rel=1e-12)
+
+
+def test_enstrophy_of_plane_couette_flow_under_a_moving_lid():
+    """Plane Couette flow u_x = U (y + 1/2) / H between the resting wall at
+    y = -1/2 and the lid at y = H - 1/2 moving with U: the ghost values -u (wall)
+    and 2U - u (lid) lie on the same line, so every centred difference is U / H
+    and the enstrophy is 1/2 nx nz H (U/H)^2.  A resting-wall ghost under the lid
+    would give the top row a different slope."""
+    nx, ny, nz, U = 5, 9, 4, 0.07
+    _, y, _ = _grid(nx, ny, nz)
+    u = np.stack([U * y / ny, np.zeros_like(y), np.zeros_like(y)])
+    w = O.vorticity(u, walls="y", lid=(U, 0.0, 0.0))
+    np.testing.assert_allclose(w[2], -U / ny, rtol=1e-13)
+    np.testing.assert_allclose(w[:2], 0.0, atol=1e-17)
+    assert 0.5 * float((w ** 2).sum()) == pytest.approx(0.5 * nx * nz * ny * (U / ny) ** 2, rel=1e-12)
+    w_rest = O.vorticity(u, walls="y")
+    assert abs(w_rest[2, :, -1, :] + U / ny).min() > 0.1 * U / ny
+
+
+def test_diagnostic_sums_are_the_step7_fields():
+    """Mass, momentum (with the F/2 shift of a post-collision state), kinetic
+    energy, min rho and the non-finite count against Appendix D Step 7 computed
+    by brute force over nodes and directions."""
+    e, _, _ = O.lattice()
+    rng = np.random.default_rng(3)
+    nx, ny, nz = 5, 4, 3
+    rho = 1 + 0.05 * rng.standard_normal((nz, ny, nx))
+    u = 0.03 * rng.standard_normal((3, nz, ny, nx))
+    f = O.init(rho, u) * (1 + 0.02 * rng.standard_normal((27, nz, ny, nx)))
+    F = np.array([1e-4, -2e-4, 3e-4])
+    d = O.diagnostics(f, F)
+    mass = mom = ke = 0.0
+    mom = np.zeros(3)
+    rmin = np.inf
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                r = sum(f[a, z, y, x] for a in range(27))
+                j = sum(f[a, z, y, x] * e[a] for a in range(27)) - F / 2
+                mass += r
+                mom += j
+                ke += 0.5 * float(j @ j) / r
+                rmin = min(rmin, r)
+    assert d["mass"] == pytest.approx(mass, rel=1e-14)
+    np.testing.assert_allclose(d["momentum"], mom, rtol=1e-12, atol=1e-16)
+    assert d["kinetic_energy"] == pytest.approx(ke, rel=1e-12)
+    assert d["min_rho"] == pytest.approx(rmin, rel=1e-15)
+    assert d["n_nonfinite"] == 0
+    f[3, 1, 2, 0] = np.nan
+    f[5, 1, 2, 0] = np.inf
+    f[0, 0, 0, 4] = -np.inf
+    assert O.diagnostics(f, F)["n_nonfinite"] == 2
