@@ -1,18 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the fused D3Q27 FPC-LBM stream-and-collide step on one MI355X.
 
-Workload (the channel case): 256 x 128 x 128 nodes, walls half a link outside
-y = 0 and y = 127 (halfway bounce-back), periodic in x and z, nu = 0.01,
-constant body force F_x = 8 nu u_max / H^2 with u_max = 0.05 and H = 128,
-starting from rest.  A step is one fused stream + collide launch over all
-nodes.  Inputs are synthetic (no dataset) and already resident in HBM when the
-timed region starts.
+Workload: the 3D Taylor-Green vortex at Re = 1600 on a 512^3 periodic box
+(u0 = 0.05, L = 512 / 2 pi, nu = u0 L / Re = 2.5465e-3; u = u0 sin x cos y cos z,
+v = -u0 cos x sin y cos z, w = 0, rho = 1 + 3 p' with the matching pressure,
+populations at equilibrium).  A step is one fused stream + collide launch over
+all 134,217,728 nodes.  Inputs are synthetic and already resident in HBM when
+the timed region starts.
+
+Every storage form (FP64, FP32, FP16 and BF16 deviations from the lattice
+weights) runs the same sequence from the same start: ``--settle`` untimed steps
+(the kernels reach their steady clock and the flow leaves the initial field),
+``--warmup`` untimed steps, then ``--steps`` steps timed with HIP events on the
+library's stream.  At the end of the window each form's kinetic energy,
+dissipation nu <|curl u|^2> and velocity field are compared with the FP64 run
+on the same GPU: that is the error at which the form's throughput is stated.
 
 Printed (one JSON line): MLUPS of the FP32-storage form as ``value``, the HBM
-roofline of the stream-collide kernel measured with HIP events on the stream
-the kernel runs on, every storage form's MLUPS / roofline fraction / error
-against the analytic start-up profile and against the FP64 run, and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+roofline of its stream-collide kernel (algorithmic bytes per launch over the
+measured launch time), every storage form's MLUPS, roofline fraction and error
+against FP64, the learned-closure kernel on the coarse channel 192x96x96 for
+context, and the FP64 CPU oracle timed on a bounded slab of the same field.
 """
 from __future__ import annotations
 
@@ -28,7 +36,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_channel_256x128x128.md")
+N_TGV = 512
+U0 = 0.05
+RE = 1600.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_taylor_green_512.md")
+
+
+def tgv_params(n: int):
+    Lc = n / (2 * np.pi)
+    return Lc, U0 * Lc / RE
 
 
 def closure_params():
@@ -46,38 +62,29 @@ def closure_params():
     return np.concatenate(parts).astype(np.float32) * 1e-3
 
 
-def analytic_startup(ny: int, nu: float, F: float, t: float, nterms: int = 400) -> np.ndarray:
-    """Start-up of plane Poiseuille flow from rest between walls at y = 0 and H
-    (here the half-link wall positions), u(y, t) for the node centres."""
-    H = float(ny)
-    y = np.arange(ny) + 0.5
-    u = F / (2 * nu) * y * (H - y)
-    for n in range(1, 2 * nterms, 2):
-        u -= 4 * F * H * H / (nu * n ** 3 * np.pi ** 3) * np.sin(n * np.pi * y / H) * np.exp(-n * n * np.pi ** 2 * nu * t / (H * H))
-    return u
-
-
-def run_form(L, torch, storage, shape, nu, F, steps, warmup):
-    nx, ny, nz = shape
+def run_tgv_form(L, torch, storage, n, nu, rd, ud, settle, warmup, steps):
+    """One storage form: init from the device fields, settle + warmup untimed,
+    then ``steps`` launches timed with HIP events on the library's stream.
+    Returns the time per step, the end diagnostics and the FP64 velocity field
+    at the end (a device tensor)."""
     stream = torch.cuda.Stream()
-    cfg = L.Config(nx, ny, nz, storage=storage, walls_y=True, nu=nu, force=(F, 0.0, 0.0),
-                   hip_stream=stream.cuda_stream)
+    cfg = L.Config(n, n, n, storage=storage, nu=nu, hip_stream=stream.cuda_stream)
     with L.Lattice(cfg) as lat:
-        lat.init()  # rest: rho = 1, u = 0
-        lat.step(warmup)
+        L.lbm_init_device(lat.ctx, rd.data_ptr(), ud.data_ptr())
+        lat.step(settle + warmup)
         lat.synchronize()
         start = torch.cuda.Event(enable_timing=True)
         end = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
         start.record(stream)
         lat.step(steps)
         end.record(stream)
         end.synchronize()
-        torch.cuda.synchronize()
-        ms = start.elapsed_time(end)
-        _, u = lat.moments()
+        ms = start.elapsed_time(end) / steps
         diag = lat.diagnostics()
-    return ms, u, diag
+        u = torch.empty(3 * n ** 3, dtype=torch.float64, device="cuda")
+        L.lbm_moments_device(lat.ctx, 0, u.data_ptr(), True)
+        lat.synchronize()
+    return ms, diag, u
 
 
 def run_closure_form(L, torch, storage, shape, nu, F, steps, warmup, params):
@@ -115,25 +122,34 @@ def copy_calibration(torch, nbytes: int = 1 << 31, reps: int = 5):
     print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}), flush=True)
 
 
-def cpu_baseline(shape, nu, F, steps):
+def cpu_baseline(n, nu, planes, steps):
+    """The FP64 oracle on the first ``planes`` z-planes of the same n^3 field
+    (periodic in z over the slab): the work per node is that of the full box."""
     import oracle as O
-    nx, ny, nz = shape
-    g = O.init(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
+    from paper_2410_09739_amd import workloads as W
+    rho, u = W.taylor_green(n)
+    rho, u = np.ascontiguousarray(rho[:planes]), np.ascontiguousarray(u[:, :planes])
+    g = O.init(rho, u)
+    del rho, u
     om = O.omega_table(nu)
     t0 = time.perf_counter()
-    O.run(g, om, (F, 0.0, 0.0), walls_y=True, steps=steps)
+    O.run(g, om, steps=steps)
     dt = time.perf_counter() - t0
-    return nx * ny * nz * steps / dt / 1e6, dt, O.num_threads()
+    return n * n * planes * steps / dt / 1e6, dt, O.num_threads()
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--forms", default="f32,f64,f16dev,bf16dev")
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--settle", type=int, default=200,
+                    help="untimed steps before the warmup (steady clock, developed flow)")
+    ap.add_argument("--n", type=int, default=N_TGV, help="edge of the periodic box (512: the headline case)")
+    ap.add_argument("--forms", default="f64,f32,f16dev,bf16dev")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--cpu-planes", type=int, default=16)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--closure-steps", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (for scaling rocprofv3 byte counters)")
@@ -146,58 +162,70 @@ def main():
     import torch
     from paper_2410_09739_amd import lbm as L
     from paper_2410_09739_amd import profiling as P
+    from paper_2410_09739_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration(torch)
         return
-    shape = (256, 128, 128)
-    nx, ny, nz = shape
-    N = nx * ny * nz
-    nu, umax = 0.01, 0.05
-    F = 8 * nu * umax / ny ** 2
+    n = args.n
+    N = n ** 3
+    Lc, nu = tgv_params(n)
+    rho, u = W.taylor_green(n, u0=U0)
+    rd = torch.from_numpy(rho.ravel()).cuda()
+    ud = torch.from_numpy(u.reshape(-1)).cuda()
+    del rho, u
+    mass0 = float(rd.sum().item())
+    torch.cuda.synchronize()
 
     forms = [s for s in args.forms.split(",") if s]
     if "f32" not in forms:
         forms.insert(0, "f32")
-    results, profiles = {}, {}
+    if "f64" in forms:  # the reference of every error runs first
+        forms.remove("f64")
+        forms.insert(0, "f64")
+    total = args.settle + args.warmup + args.steps
+    results, u64, d64 = {}, None, None
     for st in forms:
-        ms, u, diag = run_form(L, torch, st, shape, nu, F, args.steps, args.warmup)
+        ms, diag, uf = run_tgv_form(L, torch, st, n, nu, rd, ud, args.settle, args.warmup, args.steps)
         sb = L.STORAGE_BYTES[L.STORAGE[st]]
-        ms_step = ms / args.steps
         bytes_launch = N * 54 * sb
-        gbs = bytes_launch / (ms_step * 1e-3) / 1e9
-        prof = u[0].mean(axis=(0, 2))  # x-z average of u_x(y)
-        t = args.warmup + args.steps - 0.5
-        ua = analytic_startup(ny, nu, F, t)
-        profiles[st] = (u, prof)
-        results[st] = {
-            "mlups": N / (ms_step * 1e-3) / 1e6,
-            "ms_per_step": ms_step,
-            "bytes_per_node": 54 * sb,
-            "achieved_GBs": gbs,
-            "frac_hbm": gbs / HBM_PEAK_GBS,
-            "profile_rel_l2_vs_analytic": float(np.sqrt(np.sum((prof - ua) ** 2) / np.sum(ua ** 2))),
-            "mass_drift": diag["mass"] / N - 1.0,
-        }
-        print(f"# {st}: {results[st]['mlups']:.0f} MLUPS, {gbs:.0f} GB/s, "
-              f"profile err {results[st]['profile_rel_l2_vs_analytic']:.2e}", file=sys.stderr, flush=True)
-    if "f64" in profiles:
-        u64 = profiles["f64"][0]
-        for st in results:
-            results[st]["max_abs_u_err_vs_f64_over_umax"] = float(np.abs(profiles[st][0] - u64).max() / umax)
+        gbs = bytes_launch / (ms * 1e-3) / 1e9
+        r = {"mlups": N / (ms * 1e-3) / 1e6, "ms_per_step": ms, "bytes_per_node": 54 * sb,
+             "achieved_GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+             "kinetic_energy_per_node": diag["kinetic_energy"] / N,
+             "dissipation_per_node": 2.0 * nu * diag["enstrophy"] / N,
+             "mass_rel_drift": (diag["mass"] - mass0) / mass0}
+        if st == "f64":
+            u64, d64 = uf, diag
+        elif u64 is not None:
+            r["ke_rel_err_vs_f64"] = abs(diag["kinetic_energy"] - d64["kinetic_energy"]) / d64["kinetic_energy"]
+            r["dissipation_rel_err_vs_f64"] = abs(diag["enstrophy"] - d64["enstrophy"]) / d64["enstrophy"]
+            r["max_abs_u_err_vs_f64_over_u0"] = float((uf - u64).abs().max().item()) / U0
+            r["rms_u_err_vs_f64_over_u0"] = float(((uf - u64) ** 2).mean().sqrt().item()) / U0
+        del uf
+        results[st] = r
+        print(f"# {st}: {r['mlups']:.0f} MLUPS, {gbs:.0f} GB/s ({r['frac_hbm']:.3f} of peak)"
+              + (f", KE err {r['ke_rel_err_vs_f64']:.2e}, max|du|/u0 {r['max_abs_u_err_vs_f64_over_u0']:.2e}"
+                 if "ke_rel_err_vs_f64" in r else ""), file=sys.stderr, flush=True)
+    if "f64" in results:
+        results["f64"].update({"ke_rel_err_vs_f64": 0.0, "dissipation_rel_err_vs_f64": 0.0,
+                               "max_abs_u_err_vs_f64_over_u0": 0.0, "rms_u_err_vs_f64_over_u0": 0.0})
+    del u64, rd, ud
+    torch.cuda.empty_cache()
 
-    # learned-closure forms on the coarse channel 192 x 96 x 96 (the closure
-    # workload: nu and force of the fine channel under acoustic 2x coarsening)
+    # learned-closure forms on the coarse channel 192 x 96 x 96 (context: the
+    # closure workload, nu and force of the fine channel under 2x coarsening)
     closure = {}
     if args.closure_steps > 0:
         cshape = (192, 96, 96)
+        cnu, F = 0.005, 2 * 8 * 0.01 * 0.05 / 128 ** 2
         params = closure_params()
         for st, use in [("f32", False), ("f16dev", False), ("bf16dev", False), ("f32", True), ("f16dev", True),
                         ("bf16dev", True)]:
             key = st + ("+closure" if use else "")
-            closure[key] = run_closure_form(L, torch, st, cshape, nu / 2, 2 * F, args.closure_steps, 20,
+            closure[key] = run_closure_form(L, torch, st, cshape, cnu, F, args.closure_steps, 200,
                                             params if use else None)
             closure[key] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in closure[key].items()}
             print(f"# coarse {key}: {closure[key]['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
@@ -206,7 +234,8 @@ def main():
     roof = {"bound": "hbm", "achieved": round(main_form["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(main_form["frac_hbm"], 4), "traffic": None}
     tr = P.read_traffic_md(TRAFFIC_FILE)
-    if tr and tr.get("kernel_source_sha") == P.kernel_source_hash() and "f32" in tr.get("forms", {}):
+    if (tr and tr.get("kernel_source_sha") == P.kernel_source_hash() and "f32" in tr.get("forms", {})
+            and tr.get("nodes") == N):
         roof["traffic"] = tr["forms"]["f32"]["hbm_bytes_per_launch"]
 
     line = {
@@ -222,20 +251,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "channel 256x128x128, halfway bounce-back walls in y, body force, nu=0.01, "
-                               "u_max=0.05, from rest; FP32 storage of f - w",
-                   "nx": nx, "ny": ny, "nz": nz, "parallelism": "single GPU"},
+        "config": {"workload": f"Taylor-Green vortex {n}^3 periodic, Re=1600, u0=0.05, nu={nu:.5e}; "
+                               f"FP32 storage of f - w; {args.settle} settle + {args.warmup} warmup steps "
+                               f"untimed, {args.steps} timed",
+                   "nx": n, "ny": n, "nz": n, "settle_steps": args.settle,
+                   "error_at_step": total, "error_at_tstar": round(total * U0 / Lc, 4),
+                   "parallelism": "single GPU"},
         "roofline": roof,
-        "forms": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+        "forms": {k: {kk: (float(f"{vv:.6g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in results.items()},
-        "closure_forms_192x96x96": closure,
+        "closure_forms_channel_192x96x96": closure,
     }
     if not args.no_cpu_baseline:
-        cshape = (256, 128, 16)
-        mlups, dt, cores = cpu_baseline(cshape, nu, F, args.cpu_steps)
+        mlups, dt, cores = cpu_baseline(n, nu, args.cpu_planes, args.cpu_steps)
         line["cpu_baseline"] = {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-                                "sample": f"{args.cpu_steps} steps of a 256x128x16 slab of the same channel "
-                                          f"(periodic z), FP64, {dt:.1f} s"}
+                                "sample": f"{args.cpu_steps} steps of the first {args.cpu_planes} z-planes "
+                                          f"({n}x{n}x{args.cpu_planes} nodes, periodic) of the same {n}^3 "
+                                          f"Taylor-Green field, FP64, {dt:.1f} s"}
     print(json.dumps(line), flush=True)
 
 

@@ -145,10 +145,17 @@ typedef struct {
   double mass;            /* sum rho                                              */
   double momentum[3];     /* sum rho u (Step 7 definition)                        */
   double kinetic_energy;  /* 1/2 sum rho |u|^2                                    */
-  double enstrophy;       /* 1/2 sum |curl u|^2, centred differences (periodic;   */
-                          /* antisymmetric ghost layer at the half-link walls)    */
-  double wall_force[3];   /* force of the fluid on the walls: sum over bounce-back */
-                          /* links of 2 f~_alpha e_alpha (zero without walls)     */
+  double enstrophy;       /* 1/2 sum |curl u|^2, curl u by centred differences   */
+                          /* (q(i+1) - q(i-1))/2 of the Step 7 velocity; periodic */
+                          /* axes wrap; ghost value -u across a resting wall,     */
+                          /* 2U - u across the moving lid, mirrored tangential u  */
+                          /* across the symmetry plane                            */
+  double wall_force[3];   /* force of the fluid on the walls: sum over the links  */
+                          /* from a fluid node into a wall (any walled face; the  */
+                          /* symmetry plane takes none) of 2 f~_alpha e_alpha;    */
+                          /* at a moving lid the momentum correction of the       */
+                          /* bounced population is not included; zero without     */
+                          /* walls                                                */
   double max_speed;       /* max |u|                                              */
   double min_rho;         /* min rho                                              */
   int64_t n_nonfinite;    /* nodes with a non-finite population                   */

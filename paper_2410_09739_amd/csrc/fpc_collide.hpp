@@ -382,6 +382,135 @@ __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& 
   inverse_all<T, SU>(v, ux, uy, uz);
 }
 
+// ---------------------------------------------------------------------------
+// The collision with the rates of the paper's runs (Sec. 4: bulk rate omega_7
+// and every rate of orders 3-6 equal to 1) and no body force.  A group relaxed
+// at rate 1 lands on its attractor: order 3 on 0, the orders-4 and -5
+// attractors are built from the post-collision orders 2 and 3, order 6 from
+// orders 2 and 4 (Sec. 3.5), and the 2s1 combination on its equilibrium rho'.
+// So the post-collision cube depends only on rho', u and the five
+// second-order moments that relax at the shear rates (110, 101, 011, 2d1,
+// 2d2): none of the pre-collision moments of order 3 or higher is needed.
+// They are not computed.  The second-order central moments come from the raw
+// ones about the origin, kappa_ab = M_ab - j_a u_b (j = rho u without a
+// force), the raw moments from line sums of the cube.  The result equals the
+// general relax() up to rounding; that one computes kappa + 1 (kappa^Mv - kappa).
+
+// Raw moments of orders 0-2 of the deviation cube (times UNIT in storage
+// units): m0 = rho', j = sum delta e, m2 = (200, 020, 002, 110, 101, 011).
+// One pass per axis over line sums, as density_momentum, keeping the pair
+// sums f(+1) + f(-1) that give the second order.
+template <typename T, bool SU = false>
+__host__ __device__ __forceinline__ void low_moments(const T (&v)[3][3][3], T& m0, T& jx, T& jy, T& jz, T (&m2)[6]) {
+  constexpr int M = Units<SU>::M;
+  // x: order 0, 1, 2 of every (y, z) line
+  T s[3][3], d[3][3], p[3][3];
+#pragma unroll
+  for (int iz = 0; iz < 3; ++iz)
+#pragma unroll
+    for (int iy = 0; iy < 3; ++iy) {
+      p[iz][iy] = v[iz][iy][2] + v[iz][iy][0];
+      s[iz][iy] = p[iz][iy] + T(M) * v[iz][iy][1];
+      d[iz][iy] = v[iz][iy][2] - v[iz][iy][0];
+    }
+  // y: (x order, y order) = (0,0), (0,1), (0,2), (1,0), (1,1), (2,0) per z plane
+  T a00[3], a01[3], a02[3], a10[3], a11[3], a20[3];
+#pragma unroll
+  for (int iz = 0; iz < 3; ++iz) {
+    a02[iz] = s[iz][2] + s[iz][0];
+    a00[iz] = a02[iz] + T(M) * s[iz][1];
+    a01[iz] = s[iz][2] - s[iz][0];
+    a10[iz] = (d[iz][2] + d[iz][0]) + T(M) * d[iz][1];
+    a11[iz] = d[iz][2] - d[iz][0];
+    a20[iz] = (p[iz][2] + p[iz][0]) + T(M) * p[iz][1];
+  }
+  // z
+  const T zz = a00[2] + a00[0];
+  m0 = zz + T(M) * a00[1];
+  jz = a00[2] - a00[0];
+  jy = (a01[2] + a01[0]) + T(M) * a01[1];
+  jx = (a10[2] + a10[0]) + T(M) * a10[1];
+  m2[0] = (a20[2] + a20[0]) + T(M) * a20[1];  // 200
+  m2[1] = (a02[2] + a02[0]) + T(M) * a02[1];  // 020
+  m2[2] = zz;                                  // 002
+  m2[3] = (a11[2] + a11[0]) + T(M) * a11[1];  // 110
+  m2[4] = a10[2] - a10[0];                     // 101
+  m2[5] = a01[2] - a01[0];                     // 011
+}
+
+// Step 7 fields and the primed second-order central moments without a force:
+// k2 = (kappa'_200, kappa'_020, kappa'_002, kappa_110, kappa_101, kappa_011),
+// kappa'_aa = kappa_aa - c_s^2 (the rest state's part; it is M'_aa - j_a u_a
+// for the deviation moments M').  Storage units as pre_collision.
+template <typename T, bool SU = false>
+__host__ __device__ __forceinline__ void second_order_central(const T (&v)[3][3][3], T& rhop, T& rho, T& ux, T& uy,
+                                                              T& uz, T (&k2)[6]) {
+  constexpr double U = Units<SU>::U;
+  T jx, jy, jz, m2[6];
+  low_moments<T, SU>(v, rhop, jx, jy, jz, m2);
+  rho = T(1) + rhop * T(1.0 / U);
+  const T iru = recip(rho) * T(1.0 / U);
+  ux = jx * iru;
+  uy = jy * iru;
+  uz = jz * iru;
+  k2[0] = m2[0] - jx * ux;
+  k2[1] = m2[1] - jy * uy;
+  k2[2] = m2[2] - jz * uz;
+  k2[3] = m2[3] - jx * uy;
+  k2[4] = m2[4] - jx * uz;
+  k2[5] = m2[5] - jy * uz;
+}
+
+// Step 3 with bulk and higher rates 1 and no force, from the moments of
+// second_order_central, then the inverse sweeps: the cube is overwritten
+// with the post-collision deviations (times 2^inv_shift, and UNIT in storage
+// units), as collide() leaves it.  ws, cs: the shear-group rates
+// omega_4..omega_9 at this node and 1 - ws (ws[3], the bulk rate, is 1).
+template <typename T, bool SU = false>
+__host__ __device__ __forceinline__ void relax_unit_higher(T (&v)[3][3][3], const T (&cs)[6], T rhop, T rho, T ux,
+                                                           T uy, T uz, const T (&k2)[6]) {
+  constexpr double U = Units<SU>::U;
+  const T third = T(1.0 / 3.0);
+  const T thirdU = T(U / 3.0), ninthU = T(U / 9.0);
+  const T ir = recip(rho);
+  const T iru = ir * T(1.0 / U);
+  // order 2: 2s1 on its attractor rho' (rate 1), the shear groups at their rates
+  const T t110 = cs[0] * k2[3];
+  const T t101 = cs[1] * k2[4];
+  const T t011 = cs[2] * k2[5];
+  const T t2d1 = cs[4] * (k2[0] - k2[1]);
+  const T t2d2 = cs[5] * (k2[0] - k2[2]);
+  const T t200 = third * (rhop + t2d1 + t2d2);
+  const T t020 = third * (rhop - T(2) * t2d1 + t2d2);
+  const T t002 = third * (rhop + t2d1 - T(2) * t2d2);
+  // order 3 -> 0; order 4 -> attractors from post-collision order 2
+  const T t220 = ((t200 + t020) * thirdU + t200 * t020 + T(2) * t110 * t110 - ninthU * rhop) * iru;
+  const T t202 = ((t200 + t002) * thirdU + t200 * t002 + T(2) * t101 * t101 - ninthU * rhop) * iru;
+  const T t022 = ((t020 + t002) * thirdU + t020 * t002 + T(2) * t011 * t011 - ninthU * rhop) * iru;
+  const T A2 = thirdU + t200, B2 = thirdU + t020, C2 = thirdU + t002;
+  const T t211 = (A2 * t011 + T(2) * t110 * t101) * iru;
+  const T t121 = (B2 * t101 + T(2) * t110 * t011) * iru;
+  const T t112 = (C2 * t110 + T(2) * t011 * t101) * iru;
+  // order 5 -> its attractor, which vanishes with order 3 at 0 (every term
+  // holds a third-order moment); order 6 -> attractor from orders 2 and 4
+  const T t222 = ((t200 + t020 + t002) * ninthU + (t022 + t202 + t220) * thirdU + t200 * t022 + t020 * t202 +
+                  t002 * t220 + T(4) * (t110 * t112 + t101 * t121 + t011 * t211)) *
+                     (third * iru) -
+                 rhop * (T(1.0 / 27.0) * ir);
+  v[0][0][0] = rhop;
+  v[0][0][1] = T(0); v[0][1][0] = T(0); v[1][0][0] = T(0);
+  v[0][1][1] = t110; v[1][0][1] = t101; v[1][1][0] = t011;
+  v[0][0][2] = t200; v[0][2][0] = t020; v[2][0][0] = t002;
+  v[0][2][1] = T(0); v[2][0][1] = T(0); v[0][1][2] = T(0);
+  v[2][1][0] = T(0); v[1][0][2] = T(0); v[1][2][0] = T(0);
+  v[1][1][1] = T(0);
+  v[0][2][2] = t220; v[2][0][2] = t202; v[2][2][0] = t022;
+  v[1][1][2] = t211; v[1][2][1] = t121; v[2][1][1] = t112;
+  v[2][2][1] = T(0); v[2][1][2] = T(0); v[1][2][2] = T(0);
+  v[2][2][2] = t222;
+  inverse_all<T, SU>(v, ux, uy, uz);
+}
+
 // Whole collision of one node (Appendix D Steps 7, 1-5): deviation cube in,
 // post-collision deviations (times 2^inv_shift) out; in storage units (SU) the
 // cube comes in as stored numbers and goes out times UNIT.
@@ -392,6 +521,16 @@ __host__ __device__ __forceinline__ void collide(T (&v)[3][3][3], const Rates<T>
   T rhop;
   pre_collision<T, FORCE, SU>(v, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
   relax<T, FORCE, MAXWELL, SU>(v, R, ws, cs, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
+}
+
+// Whole collision with bulk and higher rates 1 and no force (see
+// relax_unit_higher); same contract as collide().
+template <typename T, bool SU = false>
+__host__ __device__ __forceinline__ void collide_unit_higher(T (&v)[3][3][3], const T (&cs)[6], T& rho, T& ux, T& uy,
+                                                             T& uz) {
+  T rhop, k2[6];
+  second_order_central<T, SU>(v, rhop, rho, ux, uy, uz, k2);
+  relax_unit_higher<T, SU>(v, cs, rhop, rho, ux, uy, uz, k2);
 }
 
 }  // namespace fpc

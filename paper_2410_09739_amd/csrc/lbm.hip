@@ -21,35 +21,7 @@
 
 #include "lbm_internal.hpp"
 
-// ===========================================================================
-// fused stream + collide (plain method)
-// Block (64, 4): each wavefront is one x segment of one row (y, z uniform).
-// BC: 0 periodic, 1 walls across y (the channel), 2 walls on any faces and a
-// moving lid (StepArgs::box).
-template <int ST, int BC, bool FORCE, bool MAXWELL>
-__global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>::S* __restrict__ src,
-                                                        typename Stor<ST>::S* __restrict__ dst,
-                                                        StepArgs<typename Stor<ST>::R> A) {
-  using T = typename Stor<ST>::R;
-  // FP16/BF16: arithmetic on the stored numbers (storage units), which drops
-  // the multiply of every loaded value by its scale.  Not in the periodic
-  // FP16 kernel: its single gather path lets the compiler fold the scale into
-  // the conversions (v_fma_mix_f32) already, and storage units measured a few
-  // instructions more there.
-  constexpr bool SU = Stor<ST>::units && !(BC == 0 && (ST == LBM_F16DEV || ST == LBM_F16DEV_RNE));
-  int x, y, z;
-  if (!wave_segment(A.g, x, y, z) || x >= A.g.nx) return;
-  T v[3][3][3];
-  if (BC == 2) pull_box<ST, SU>(src, A.g, A.box, x, y, z, v);
-  else pull<ST, BC == 1, SU>(src, A.g, x, y, z, v);
-  T ws[6] = {A.r.w[4], A.r.w[5], A.r.w[6], A.r.w[7], A.r.w[8], A.r.w[9]};
-  T cs[6] = {A.r.c[4], A.r.c[5], A.r.c[6], A.r.c[7], A.r.c[8], A.r.c[9]};
-  T rhop, rho, ux, uy, uz;
-  pre_collision<T, FORCE, SU>(v, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
-  if (BC == 2 && A.box.les_on) les_rates<SU>(v, rho, A.box, A.r, y, A.g.ny, ws, cs);  // uniform branch
-  relax<T, FORCE, MAXWELL, SU>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
-  push<ST, SU>(dst, A.g, x, y, z, v, A.step);
-}
+#include "stream_collide.hpp"
 
 // ===========================================================================
 // initialisation: f~(0) = f^eq(rho, u); kappa' = rho' E, mapped back by the
@@ -234,10 +206,14 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_nodes(const typename Stor
     acc[P_NONFIN] += finite ? 0.0 : 1.0;
     acc[P_MAXU] = fmax(acc[P_MAXU], sqrt(s2));
     acc[P_MINRHO] = fmin(acc[P_MINRHO], r);
-    if (walls & 1) {
+    if (walls & 7) {
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
-        if ((EY[a] == -1 && y == 0) || (EY[a] == 1 && y == g.ny - 1 && !(walls & 8))) {
+        // links from this node into a wall (the symmetry plane takes no force)
+        const bool ly = (walls & 1) && ((EY[a] == -1 && y == 0) || (EY[a] == 1 && y == g.ny - 1 && !(walls & 8)));
+        const bool lx = (walls & 2) && ((EX[a] == -1 && x == 0) || (EX[a] == 1 && x == g.nx - 1));
+        const bool lz = (walls & 4) && ((EZ[a] == -1 && z == 0) || (EZ[a] == 1 && z == g.nz - 1));
+        if (ly || lx || lz) {
           const double fa = weight(a) + d[a];
           acc[P_WX] += 2.0 * fa * EX[a];
           acc[P_WY] += 2.0 * fa * EY[a];
@@ -249,43 +225,53 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_nodes(const typename Stor
   block_reduce<NP>(acc, kind, part + (int64_t)blockIdx.x * NP);
 }
 
-// 1/2 |curl u|^2 with centred differences; periodic, or an antisymmetric
-// ghost layer across the half-link walls (u = 0 at the wall).  walls: wall
-// mask (1 = y, 2 = x, 4 = z).
+// 1/2 |curl u|^2 with centred differences, d q(i) = (q(i+1) - q(i-1)) / 2.
+// Periodic axes wrap; across a half-link wall at rest the ghost value is -u of
+// the adjacent node (u = 0 halfway), across the moving lid above y = ny - 1 it
+// is 2 U - u (u = U halfway), and across the symmetry plane there the
+// tangential components (the only ones differentiated in y) mirror.
+// walls: wall mask (1 = y, 2 = x, 4 = z, 8 = symmetry plane on top).
 __global__ __launch_bounds__(DIAG_THREADS) void k_diag_enstrophy(const double* __restrict__ u, double* __restrict__ part,
-                                                                 Geom g, int walls) {
+                                                                 Geom g, int walls, double lidx, double lidy,
+                                                                 double lidz) {
   const int64_t n = (int64_t)g.nx * g.ny * g.nz;
   double acc[1] = {0.0};
   const int kind[1] = {0};
   const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const double lid[3] = {lidx, lidy, lidz};
   for (int64_t i = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x; i < n; i += (int64_t)DIAG_BLOCKS * DIAG_THREADS) {
     const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
-    int xp = x == nx - 1 ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
-    int zp = z == nz - 1 ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
-    int yp = y == ny - 1 ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
-    double sxp = 1.0, sxm = 1.0, syp = 1.0, sym = 1.0, szp = 1.0, szm = 1.0;
-    if (walls & 1) {
-      // wall: antisymmetric ghost; symmetry plane on top (walls & 8): the
-      // tangential components u_x, u_z (the only ones differentiated in y) mirror
-      if (y == ny - 1) { yp = y; syp = (walls & 8) ? 1.0 : -1.0; }
-      if (y == 0) { ym = y; sym = -1.0; }
-    }
-    if (walls & 2) {
-      if (x == nx - 1) { xp = x; sxp = -1.0; }
-      if (x == 0) { xm = x; sxm = -1.0; }
-    }
-    if (walls & 4) {
-      if (z == nz - 1) { zp = z; szp = -1.0; }
-      if (z == 0) { zm = z; szm = -1.0; }
-    }
     auto at = [&](int c, int xx, int yy, int zz) { return u[(int64_t)c * n + ((int64_t)zz * ny + yy) * nx + xx]; };
-    const double dwy_dx = 0.5 * (sxp * at(2, xp, y, z) - sxm * at(2, xm, y, z));  // d uz / dx
-    const double dvy_dz = 0.5 * (szp * at(1, x, y, zp) - szm * at(1, x, y, zm));  // d uy / dz
-    const double duz_dy = 0.5 * (syp * at(2, x, yp, z) - sym * at(2, x, ym, z));
-    const double dux_dy = 0.5 * (syp * at(0, x, yp, z) - sym * at(0, x, ym, z));
-    const double dux_dz = 0.5 * (szp * at(0, x, y, zp) - szm * at(0, x, y, zm));
-    const double duy_dx = 0.5 * (sxp * at(1, xp, y, z) - sxm * at(1, xm, y, z));
-    const double wx = duz_dy - dvy_dz, wy = dux_dz - dwy_dx, wz = duy_dx - dux_dy;
+    // value of component c one node along axis (0 x, 1 y, 2 z) in direction s (+-1)
+    auto nb = [&](int c, int axis, int s) -> double {
+      int xx = x, yy = y, zz = z;
+      if (axis == 0) {
+        xx = x + s;
+        if (xx < 0 || xx >= nx) {
+          if (walls & 2) return -at(c, x, y, z);
+          xx = xx < 0 ? nx - 1 : 0;
+        }
+      } else if (axis == 1) {
+        yy = y + s;
+        if (yy < 0 || yy >= ny) {
+          if (walls & 1) {
+            if (yy < 0) return -at(c, x, y, z);
+            if (walls & 8) return at(c, x, y, z);  // tangential components mirror
+            return 2.0 * lid[c] - at(c, x, y, z);
+          }
+          yy = yy < 0 ? ny - 1 : 0;
+        }
+      } else {
+        zz = z + s;
+        if (zz < 0 || zz >= nz) {
+          if (walls & 4) return -at(c, x, y, z);
+          zz = zz < 0 ? nz - 1 : 0;
+        }
+      }
+      return at(c, xx, yy, zz);
+    };
+    auto d = [&](int c, int axis) { return 0.5 * (nb(c, axis, 1) - nb(c, axis, -1)); };
+    const double wx = d(2, 1) - d(1, 2), wy = d(0, 2) - d(2, 0), wz = d(1, 0) - d(0, 1);
     acc[0] += 0.5 * (wx * wx + wy * wy + wz * wz);
   }
   block_reduce<1>(acc, kind, part + (int64_t)blockIdx.x);
@@ -548,6 +534,16 @@ extern "C" int lbm_init(lbm_ctx* c, const double* rho, const double* u) {
   return LBM_OK;
 }
 
+// The rates of the paper's runs: bulk (omega_7) and every rate of orders 3-6
+// exactly 1.  With no force the step kernel then takes the collision that
+// needs only the second-order moments (relax_unit_higher).
+static bool unit_higher_rates(const lbm_ctx* c) {
+  if (c->omega[7] != 1.0) return false;
+  for (int j = 10; j < LBM_Q; ++j)
+    if (c->omega[j] != 1.0) return false;
+  return true;
+}
+
 template <int ST>
 static int launch_steps(lbm_ctx* c, int64_t nsteps) {
   using T = typename Stor<ST>::R;
@@ -572,7 +568,12 @@ static int launch_steps(lbm_ctx* c, int64_t nsteps) {
       {{k_stream_collide<ST, 0, false, true>, k_stream_collide<ST, 0, true, true>},
        {k_stream_collide<ST, 1, false, true>, k_stream_collide<ST, 1, true, true>},
        {k_stream_collide<ST, 2, false, true>, k_stream_collide<ST, 2, true, true>}}};
-  const KFn kern = table[c->cfg.attractor == LBM_ATTRACTOR_MAXWELL][bc_kind(c)][force];
+  static const KFn unit_higher[3] = {k_stream_collide<ST, 0, false, false, true>,
+                                     k_stream_collide<ST, 1, false, false, true>,
+                                     k_stream_collide<ST, 2, false, false, true>};
+  const bool maxwell = c->cfg.attractor == LBM_ATTRACTOR_MAXWELL;
+  const KFn kern = (!force && !maxwell && unit_higher_rates(c)) ? unit_higher[bc_kind(c)]
+                                                                 : table[maxwell][bc_kind(c)][force];
   for (int64_t s = 0; s < nsteps; ++s) {
     const S* src = (const S*)c->buf[c->cur];
     S* dst = (S*)c->buf[c->cur ^ 1];
@@ -738,7 +739,9 @@ extern "C" int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
               k_diag_nodes<ST><<<DIAG_BLOCKS, DIAG_THREADS, 0, c->stream>>>(
                   (const typename Stor<ST>::S*)c->buf[c->cur], c->scratch, part, g, wall_mask(c), F[0], F[1], F[2]));
   LAUNCHCHK(c);
-  k_diag_enstrophy<<<DIAG_BLOCKS, DIAG_THREADS, 0, c->stream>>>(c->scratch, part_ens, g, wall_mask(c));
+  const double* lid = c->cfg.lid_velocity;
+  k_diag_enstrophy<<<DIAG_BLOCKS, DIAG_THREADS, 0, c->stream>>>(c->scratch, part_ens, g, wall_mask(c), lid[0], lid[1],
+                                                                lid[2]);
   LAUNCHCHK(c);
   k_diag_final<<<1, DIAG_THREADS, 0, c->stream>>>(part, part_ens, dout);
   LAUNCHCHK(c);

@@ -311,17 +311,19 @@ __device__ __forceinline__ void pull_box(const typename Stor<ST>::S* __restrict_
 
 // Smagorinsky LES with van Driest damping (the Sec. 4 channel): the shear
 // rates omega_4,5,6,8,9 of this node from its deviatoric pre-collision stress
-// Pi (v holds kappa' after pre_collision; the rest state has no deviatoric
-// part).  |S| = sqrt(2 S:S) with S = -Pi / (2 rho c_s^2 tau), so the
+// Pi (the primed second-order central moments; the rest state has no
+// deviatoric part).  |S| = sqrt(2 S:S) with S = -Pi / (2 rho c_s^2 tau), so the
 // relaxation time tau = tau_0 + 3 nu_t, nu_t = (C D)^2 |S|, is the positive root
 // of tau^2 - tau_0 tau - 9 sqrt(2) (C D)^2 |Pi| / (2 rho) = 0.  D uses the
 // distance to the nearest y wall half a link outside (uniform per wavefront).
 // SU: v carries the factor UNIT of the storage units.
+// k2: the node's second-order central moments (kappa'_200, kappa'_020,
+// kappa'_002, kappa_110, kappa_101, kappa_011).
 template <bool SU = false, typename T>
-__device__ __forceinline__ void les_rates(const T (&v)[3][3][3], T rho, const Box<T>& b, const Rates<T>& R, int y,
+__device__ __forceinline__ void les_rates(const T (&k2)[6], T rho, const Box<T>& b, const Rates<T>& R, int y,
                                           int ny, T (&ws)[6], T (&cs)[6]) {
-  const T k200 = v[0][0][2], k020 = v[0][2][0], k002 = v[2][0][0];
-  const T k110 = v[0][1][1], k101 = v[1][0][1], k011 = v[1][1][0];
+  const T k200 = k2[0], k020 = k2[1], k002 = k2[2];
+  const T k110 = k2[3], k101 = k2[4], k011 = k2[5];
   const T tr = (k200 + k020 + k002) * T(1.0 / 3.0);
   const T dxx = k200 - tr, dyy = k020 - tr, dzz = k002 - tr;
   const T q = sqrt(dxx * dxx + dyy * dyy + dzz * dzz + T(2) * (k110 * k110 + k101 * k101 + k011 * k011));

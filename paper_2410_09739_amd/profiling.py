@@ -28,7 +28,7 @@ import re
 from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["paper_2410_09739_amd/csrc/lbm.hip", "paper_2410_09739_amd/csrc/fpc_collide.hpp",
+KERNEL_SOURCES = ["paper_2410_09739_amd/csrc/stream_collide.hpp", "paper_2410_09739_amd/csrc/fpc_collide.hpp",
                   "paper_2410_09739_amd/csrc/d3q27.hpp", "paper_2410_09739_amd/csrc/lbm_internal.hpp"]
 # storage form id (template argument of k_stream_collide) -> (name, bytes per population)
 FORMS = {0: ("f64", 8), 1: ("f32", 4), 2: ("f16dev", 2), 3: ("bf16dev", 2), 4: ("f16dev_rne", 2),

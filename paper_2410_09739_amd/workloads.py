@@ -29,14 +29,15 @@ def taylor_green(n: int, u0: float = 0.05, rho0: float = 1.0, cell_centred: bool
     ny = n if ny is None else ny
     nz = n if nz is None else nz
     off = 0.5 if cell_centred else 0.0
-    x = 2 * np.pi * (np.arange(n) + off) / n
-    y = 2 * np.pi * (np.arange(ny) + off) / ny
-    z = 2 * np.pi * (np.arange(nz) + off) / nz
-    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    # separable factors, broadcast over the grid (the same products, in the same
+    # order, as on a full coordinate mesh)
+    x = (2 * np.pi * (np.arange(n) + off) / n)[None, None, :]
+    y = (2 * np.pi * (np.arange(ny) + off) / ny)[None, :, None]
+    z = (2 * np.pi * (np.arange(nz) + off) / nz)[:, None, None]
     u = np.zeros((3, nz, ny, n))
-    u[0] = u0 * np.sin(X) * np.cos(Y) * np.cos(Z)
-    u[1] = -u0 * np.cos(X) * np.sin(Y) * np.cos(Z)
-    p = rho0 * u0 * u0 / 16.0 * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0)
+    u[0] = u0 * np.sin(x) * np.cos(y) * np.cos(z)
+    u[1] = -u0 * np.cos(x) * np.sin(y) * np.cos(z)
+    p = rho0 * u0 * u0 / 16.0 * (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0)
     rho = rho0 + 3.0 * p
     return rho, u
 

@@ -71,6 +71,42 @@ extern "C" void host_collide_units_f32(const float* dev, const double* omega, co
   else run_dev<true, false>(dev, omega, F, out);
 }
 
+// The collision the step kernels take for the paper's rates (bulk and orders
+// 3-6 at 1) without a force: second-order moments only (relax_unit_higher).
+template <typename T>
+static void run_unit(const double* f, const double* omega, double* out) {
+  T v[3][3][3];
+  for (int a = 0; a < Q; ++a) v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] = (T)(f[a] - weight(a));
+  const T cs[6] = {(T)(1.0 - omega[4]), (T)(1.0 - omega[5]), (T)(1.0 - omega[6]),
+                   (T)(1.0 - omega[7]), (T)(1.0 - omega[8]), (T)(1.0 - omega[9])};
+  T rho, ux, uy, uz;
+  collide_unit_higher<T>(v, cs, rho, ux, uy, uz);
+  for (int a = 0; a < Q; ++a) out[a] = weight(a) + (double)(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] * (T)inv_factor(a));
+}
+extern "C" void host_collide_unit_f64(const double* f, const double* omega, double* out) {
+  run_unit<double>(f, omega, out);
+}
+extern "C" void host_collide_unit_f32(const double* f, const double* omega, double* out) {
+  run_unit<float>(f, omega, out);
+}
+// the same in storage units and on plain deviations (FP32), for a bitwise comparison
+template <bool SU>
+static void run_unit_dev(const float* dev, const double* omega, float* out) {
+  float v[3][3][3];
+  for (int a = 0; a < Q; ++a) v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] = SU ? dev[a] * dev_scale(a) : dev[a];
+  const float cs[6] = {(float)(1.0 - omega[4]), (float)(1.0 - omega[5]), (float)(1.0 - omega[6]),
+                       (float)(1.0 - omega[7]), (float)(1.0 - omega[8]), (float)(1.0 - omega[9])};
+  float rho, ux, uy, uz;
+  collide_unit_higher<float, SU>(v, cs, rho, ux, uy, uz);
+  for (int a = 0; a < Q; ++a) out[a] = v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] * (float)(1.0 / Units<SU>::U);
+}
+extern "C" void host_collide_unit_dev_f32(const float* dev, const double* omega, float* out) {
+  run_unit_dev<false>(dev, omega, out);
+}
+extern "C" void host_collide_unit_units_f32(const float* dev, const double* omega, float* out) {
+  run_unit_dev<true>(dev, omega, out);
+}
+
 // f^eq(rho, u) through the kernels' inverse sweeps (what lbm_init stores)
 extern "C" void host_feq_f64(double rho, const double* u, double* out) {
   double v[3][3][3];

@@ -86,6 +86,49 @@ def test_f64_matches_oracle_other_rate_sets(mode):
     assert err <= 1e-12, err
 
 
+# The step kernel takes a collision that computes only the second-order
+# moments when the bulk rate and every rate of orders 3-6 are 1 and there is no
+# force (the paper's rate set; relax_unit_higher), and the general one
+# otherwise.  Both against the oracle on every boundary kind: periodic, y walls,
+# walls on all faces with a moving lid, the half channel with LES.
+UNIT_CASES = {
+    "periodic": dict(shape=(70, 9, 6), walls=0, lid=None, les=None, cfg={}),
+    "y walls": dict(shape=(13, 10, 9), walls="y", lid=None, les=None, cfg=dict(walls_y=True)),
+    "box and lid": dict(shape=(65, 7, 6), walls="xyz", lid=(0.04, 0.0, 0.01), les=None,
+                        cfg=dict(walls_y=True, walls_x=True, walls_z=True, lid_velocity=(0.04, 0.0, 0.01))),
+    "half channel les": dict(shape=(64, 12, 4), walls="ys", lid=None, les=(0.3, 4.0, 26.0),
+                             cfg=dict(walls_y=True, sym_top=True, les_cs=0.3, les_wall_units=4.0, les_aplus=26.0)),
+}
+
+
+@pytest.mark.parametrize("rates", ["paper", "bulk 0.8", "higher 1.3"])
+@pytest.mark.parametrize("case", sorted(UNIT_CASES))
+def test_unit_rate_and_general_collisions_match_oracle(case, rates):
+    """Without a force: the paper's rates take the unit-rate collision, a bulk
+    rate of 0.8 or higher-order rates of 1.3 the general one.  FP64 to 1e-12,
+    FP32 and the 16-bit forms to the per-step bound, after 1 and 6 steps."""
+    c = UNIT_CASES[case]
+    nx, ny, nz = c["shape"]
+    nu = 0.01
+    ob = 0.8 if rates == "bulk 0.8" else 1.0
+    oh = 1.3 if rates == "higher 1.3" else 1.0
+    om = O.omega_table(nu, omega_bulk=ob, omega_higher=oh)
+    g0 = _state(c["shape"], seed=200 + nx, amp=0.08)
+    for steps in (1, 6):
+        ref = O.run(g0, om, walls=c["walls"], lid=c["lid"], les=c["les"], steps=steps)
+        for storage in ("f64", "f32", "f16dev", "bf16dev"):
+            with L.Lattice(L.Config(nx, ny, nz, storage=storage, nu=nu, omega_bulk=ob, omega_higher=oh,
+                                    **c["cfg"])) as lat:
+                lat.set_f(g0)
+                lat.step(steps)
+                got = lat.get_f()
+            if storage == "f64":
+                assert _rel(got, ref) <= 1e-12, (storage, steps, _rel(got, ref))
+            else:
+                ratio = float((np.abs(got - ref) / _tol(storage, steps, ref)).max())
+                assert ratio <= 1.0, (storage, steps, ratio)
+
+
 def test_taylor_green_32_cube_f64_200_steps():
     """The 32^3 periodic Taylor-Green case (u0 = 0.05, Re = 100 with L = N/2pi)
     for 200 steps from f^eq: populations and Step 7 fields match the oracle."""
@@ -266,6 +309,51 @@ def test_wall_force_diagnostic_matches_momentum_exchange():
         if e[a, 1] == 1:
             wall += 2 * g[a, :, ny - 1, :].sum() * e[a]
     np.testing.assert_allclose(d["wall_force"], wall, rtol=1e-12, atol=1e-15)
+
+
+DIAG_CASES = {
+    "periodic": dict(cfg={}, walls=0, lid=None),
+    "y walls": dict(cfg=dict(walls_y=True), walls="y", lid=None),
+    "half channel": dict(cfg=dict(walls_y=True, sym_top=True), walls="ys", lid=None),
+    "box and lid": dict(cfg=dict(walls_y=True, walls_x=True, walls_z=True, lid_velocity=(0.03, 0.0, -0.01)),
+                        walls="xyz", lid=(0.03, 0.0, -0.01)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(DIAG_CASES))
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+def test_diagnostics_match_the_oracle_definitions(case, storage):
+    """Every lbm_diagnostics field (mass, momentum, kinetic energy, enstrophy with
+    its ghost layers at walls, lid and symmetry plane, max |u|, min rho, wall
+    force on every walled face, non-finite count) against the oracle's
+    diagnostics of the same stored populations (read back exactly), and for FP64
+    storage also against the oracle's own run from the same start."""
+    spec = DIAG_CASES[case]
+    shape = (70, 9, 6)  # two x segments, the second ragged
+    nx, ny, nz = shape
+    F = (2e-5, 0.0, -1e-5) if case != "box and lid" else (0.0, 0.0, 0.0)
+    g0 = _state(shape, seed=61, amp=0.03)
+    cfg = L.Config(*shape, storage=storage, nu=0.03, force=F, **spec["cfg"])
+    with L.Lattice(cfg) as lat:
+        lat.set_f(g0)
+        lat.step(3)
+        g = lat.get_f()
+        d = lat.diagnostics()
+    ref = O.diagnostics(g, F, walls=spec["walls"], lid=spec["lid"])
+    for k in ("mass", "kinetic_energy", "enstrophy", "max_speed", "min_rho"):
+        assert d[k] == pytest.approx(ref[k], rel=1e-11), k
+    np.testing.assert_allclose(d["momentum"], ref["momentum"], rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(d["wall_force"], ref["wall_force"], rtol=1e-11, atol=1e-13)
+    assert d["n_nonfinite"] == 0
+    assert ref["enstrophy"] > 0 and ref["min_rho"] < 1.0
+    if spec["walls"]:
+        assert np.abs(ref["wall_force"]).max() > 0
+    if storage == "f64":
+        om = O.omega_table(0.03)
+        run = O.run(g0, om, F, walls=spec["walls"], lid=spec["lid"], steps=3)
+        ref64 = O.diagnostics(run, F, walls=spec["walls"], lid=spec["lid"])
+        for k in ("kinetic_energy", "enstrophy", "max_speed", "min_rho"):
+            assert d[k] == pytest.approx(ref64[k], rel=1e-10), k
 
 
 # ------------------------------------------------------------------ checkpoint / state handling

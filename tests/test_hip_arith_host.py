@@ -27,6 +27,10 @@ def host():
     _fp = ctypes.POINTER(ctypes.c_float)
     for n in ("host_collide_dev_f32", "host_collide_units_f32"):
         getattr(lib, n).argtypes = [_fp, _dp, _dp, ctypes.c_int, _fp]
+    for n in ("host_collide_unit_f64", "host_collide_unit_f32"):
+        getattr(lib, n).argtypes = [_dp, _dp, _dp]
+    for n in ("host_collide_unit_dev_f32", "host_collide_unit_units_f32"):
+        getattr(lib, n).argtypes = [_fp, _dp, _fp]
     return lib
 
 
@@ -96,3 +100,50 @@ def test_storage_unit_collision_is_bitwise_the_deviation_one(host, seed, maxwell
     b = _call_dev(host.host_collide_units_f32, dev, om, F, maxwell)
     assert np.all(np.isfinite(a))
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), np.max(np.abs(a - b))
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_host_unit_rate_collision_matches_oracle(host, seed):
+    """The step kernels' collision for the paper's rates (bulk omega_7 and every
+    rate of orders 3-6 equal to 1) without a force computes only the
+    second-order moments before relaxing; it must equal the oracle's full
+    Appendix D collision (explicit matrices, every moment relaxed) to the same
+    bounds as the general path, for shear viscosities from 1e-5 to 0.3 and
+    states far from equilibrium."""
+    rng = np.random.default_rng(900 + seed)
+    u = 0.15 * rng.uniform(-1, 1, 3)
+    f = O.feq(1 + 0.08 * rng.uniform(-1, 1), u) * W.random_factors(27, seed + 50, 0.3)
+    om = O.omega_table(10 ** rng.uniform(-5, -0.5))
+    assert om[7] == 1.0 and np.all(om[10:] == 1.0)
+    ref = O.collide_node(f, om)
+    out = np.zeros(27)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (f, om)]
+    host.host_collide_unit_f64(*(x.ctypes.data_as(_dp) for x in a), out.ctypes.data_as(_dp))
+    err = np.max(np.abs(out - ref) / np.maximum(np.abs(ref), WA))
+    assert err <= 1e-13, err
+    out32 = np.zeros(27)
+    host.host_collide_unit_f32(*(x.ctypes.data_as(_dp) for x in a), out32.ctypes.data_as(_dp))
+    assert np.all(np.abs(out32 - ref) <= 4e-7 * WA), np.max(np.abs(out32 - ref) / WA)
+    # and the general path (every moment relaxed at rate 1) agrees with it
+    gen = _call(host.host_collide_f64, f, om, np.zeros(3))
+    assert np.max(np.abs(gen - out) / np.maximum(np.abs(ref), WA)) <= 1e-13
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_unit_rate_collision_in_storage_units_is_bitwise_the_deviation_one(host, seed):
+    """As for the general collision: the storage-unit form of the unit-rate
+    collision (the 16-bit kernels' arithmetic) is bitwise the FP32 arithmetic on
+    plain deviations, for deviations from 1e-9 w to w."""
+    fp = ctypes.POINTER(ctypes.c_float)
+    rng = np.random.default_rng(950 + seed)
+    u = 0.1 * rng.uniform(-1, 1, 3)
+    f = O.feq(1 + 0.05 * rng.uniform(-1, 1), u) * W.random_factors(27, seed + 70, 0.2)
+    dev = ((f - WA) * 10.0 ** rng.uniform(-9, 0)).astype(np.float32)
+    om = np.ascontiguousarray(O.omega_table(10 ** rng.uniform(-5, -0.5)))
+    outs = []
+    for fn in (host.host_collide_unit_dev_f32, host.host_collide_unit_units_f32):
+        o = np.zeros(27, dtype=np.float32)
+        fn(dev.ctypes.data_as(fp), om.ctypes.data_as(_dp), o.ctypes.data_as(fp))
+        outs.append(o)
+    assert np.all(np.isfinite(outs[0]))
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
