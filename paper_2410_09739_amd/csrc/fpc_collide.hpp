@@ -54,8 +54,13 @@
 
 namespace fpc {
 
-// 1/x: FP32 on the GPU takes the hardware reciprocal (v_rcp_f32, 1 ulp)
-// instead of the ten-instruction IEEE division; FP64 and host builds divide.
+// 1/x: FP64 and host builds divide.  FP32 on the GPU takes the hardware
+// reciprocal (v_rcp_f32) and one Newton step, r' = r + r (1 - x r) with the
+// residual from a fused multiply-add, instead of the ten-instruction IEEE
+// division.  The hardware value is within 1 ulp but not always the nearest
+// (measured: about one value in nine one ulp off for x near 1, most of them
+// above, so it is biased); after the step it is the correctly rounded 1/x
+// (measured on 4M values in each of [0.5, 2] and [0.999, 1.001]).
 template <typename T>
 __host__ __device__ __forceinline__ T recip(T x) {
   return T(1) / x;
@@ -63,7 +68,8 @@ __host__ __device__ __forceinline__ T recip(T x) {
 template <>
 __host__ __device__ __forceinline__ float recip<float>(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  return __builtin_amdgcn_rcpf(x);
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
 #else
   return 1.0f / x;
 #endif
@@ -85,6 +91,28 @@ struct Units {
   static constexpr double line(int k) { return SU ? double(1u << (DEV_LOG2_0 + 2 * (k + 1))) : 1.0; }
   static constexpr double U = line(2);
 };
+
+// 1 / rho for rho = 1 + x, x = rho' (the density deviation; rhop carries UNIT
+// in storage units), without rounding 1 + x first.  The momentum the
+// collision rebuilds is (1 + x) u with u = j / rho; taken as j / fl(1 + x), it
+// is off by the rounding of 1 + x (up to 6e-8 in FP32), and these offsets do
+// not average out: on the Taylor-Green vortex they added about 4e-9 of the
+// kinetic energy per step.  One Newton step on the exact 1 + x,
+// r' = r + r e with e = (1 - r) - x r (1 - r is exact for r in [1/2, 2]),
+// from the hardware reciprocal of fl(1 + x) gives 1 / (1 + x) to within about
+// half an ulp.
+template <typename T, bool SU = false>
+__host__ __device__ __forceinline__ T recip_rho(T rhop) {
+  const T x = rhop * T(1.0 / Units<SU>::U);
+#if defined(__HIP_DEVICE_COMPILE__)
+  const T r = sizeof(T) == sizeof(float) ? T(__builtin_amdgcn_rcpf(float(T(1) + x))) : T(1) / (T(1) + x);
+#else
+  const T r = T(1) / (T(1) + x);
+#endif
+  const T e = fma(-x, r, T(1) - r);
+  return fma(r, e, r);
+}
+
 
 // ---------------------------------------------------------------------------
 // 3-point sweeps.  Forward: values (dm, d0, dp) at e = -1, 0, +1, deviations
@@ -157,6 +185,29 @@ __host__ __device__ __forceinline__ void forward_yz(T (&v)[3][3][3], T uy, T uz)
     }
 }
 
+// Rest-state constants of the inverse-sweep lines that rebuild the momentum:
+// the y lines of x-order 0 (rest weight W1[iz], times 2 for an outer z line,
+// which the z sweep doubled) and every x line (W1[iy] W1[iz], times the
+// doublings of both earlier sweeps).  In exact arithmetic the rest weights of
+// the lines of one sweep sum to 1, so the momentum is rebuilt as rho u.  The
+// nearest FP32 values do not: the y lines give 1 + 2^-25 and the x lines
+// 1 + 2^-27, so every collision would scale u_y and u_x by that factor, a
+// steady gain of kinetic energy of about 4e-8 of it per step on the
+// Taylor-Green vortex.  For FP32 one constant of each sweep is taken one unit
+// in the last place below the nearest value (the outer y lines, 1/3 -> 11184810
+// 2^-25; the corner x lines, 1/9 -> 14913080 2^-27), which makes each sum
+// exactly 1.  FP64 keeps the nearest values (its excess is 2^-54 per step).
+template <typename T>
+constexpr double rest_y(int iz) {
+  return iz == 1 ? W1[1] : (sizeof(T) == sizeof(float) ? 11184810.0 / 33554432.0 : 2.0 * W1[0]);
+}
+template <typename T>
+constexpr double rest_x(int iy, int iz) {
+  const int outer = (iy != 1) + (iz != 1);
+  if (outer == 2 && sizeof(T) == sizeof(float)) return 14913080.0 / 134217728.0;
+  return W1[iy] * W1[iz] * double(1 << outer);
+}
+
 // Inverse sweeps (z, then y, then x).  Each sweep doubles the values it writes
 // at e = +-1, so the line constants W of a later sweep are scaled by the
 // doublings its inputs already carry; on return the cube holds
@@ -178,7 +229,7 @@ __host__ __device__ __forceinline__ void inverse_all(T (&v)[3][3][3], T ux, T uy
 #pragma unroll
   for (int iz = 0; iz < 3; ++iz) {
     const double sz = iz == 1 ? 1.0 : 2.0;
-    inv3<T, 0>(v[iz][0][0], v[iz][1][0], v[iz][2][0], uy, uy2, ty, T(C1[0] * W1[iz] * sz * U));
+    inv3<T, 0>(v[iz][0][0], v[iz][1][0], v[iz][2][0], uy, uy2, ty, T(rest_y<T>(iz) * U));
     inv3<T, 1>(v[iz][0][1], v[iz][1][1], v[iz][2][1], uy, uy2, ty, T(0));
     inv3<T, 0>(v[iz][0][2], v[iz][1][2], v[iz][2][2], uy, uy2, ty, T(C1[2] * W1[iz] * sz * U));
   }
@@ -186,8 +237,7 @@ __host__ __device__ __forceinline__ void inverse_all(T (&v)[3][3][3], T ux, T uy
   for (int iz = 0; iz < 3; ++iz)
 #pragma unroll
     for (int iy = 0; iy < 3; ++iy) {
-      const double syz = (iz == 1 ? 1.0 : 2.0) * (iy == 1 ? 1.0 : 2.0);
-      inv3<T, 0>(v[iz][iy][0], v[iz][iy][1], v[iz][iy][2], ux, ux2, tx, T(W1[iy] * W1[iz] * syz * U));
+      inv3<T, 0>(v[iz][iy][0], v[iz][iy][1], v[iz][iy][2], ux, ux2, tx, T(rest_x<T>(iy, iz) * U));
     }
 }
 
@@ -229,7 +279,7 @@ __host__ __device__ __forceinline__ void pre_collision(T (&v)[3][3][3], T Fx, T 
   T jx, jy, jz;
   density_momentum<T, SU>(v, rhop, jx, jy, jz);
   rho = T(1) + rhop * T(1.0 / U);
-  const T iru = recip(rho) * T(1.0 / U);
+  const T iru = recip_rho<T, SU>(rhop) * T(1.0 / U);
   if (FORCE) {
     jx += T(0.5 * U) * Fx;
     jy += T(0.5 * U) * Fy;
@@ -255,7 +305,7 @@ __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& 
   constexpr double U = Units<SU>::U;
   const T third = T(1.0 / 3.0), ninth = T(1.0 / 9.0);
   const T thirdU = T(U / 3.0), ninthU = T(U / 9.0);
-  const T ir = recip(rho);
+  const T ir = recip_rho<T, SU>(rhop);
   const T iru = ir * T(1.0 / U);
 
   // pre-collision primed central moments (v[c][b][a] = kappa'_abc)
@@ -449,7 +499,7 @@ __host__ __device__ __forceinline__ void second_order_central(const T (&v)[3][3]
   T jx, jy, jz, m2[6];
   low_moments<T, SU>(v, rhop, jx, jy, jz, m2);
   rho = T(1) + rhop * T(1.0 / U);
-  const T iru = recip(rho) * T(1.0 / U);
+  const T iru = recip_rho<T, SU>(rhop) * T(1.0 / U);
   ux = jx * iru;
   uy = jy * iru;
   uz = jz * iru;
@@ -472,7 +522,7 @@ __host__ __device__ __forceinline__ void relax_unit_higher(T (&v)[3][3][3], cons
   constexpr double U = Units<SU>::U;
   const T third = T(1.0 / 3.0);
   const T thirdU = T(U / 3.0), ninthU = T(U / 9.0);
-  const T ir = recip(rho);
+  const T ir = recip_rho<T, SU>(rhop);
   const T iru = ir * T(1.0 / U);
   // order 2: 2s1 on its attractor rho' (rate 1), the shear groups at their rates
   const T t110 = cs[0] * k2[3];

@@ -301,45 +301,6 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_final(const double* __res
 // error text of calls without a context (create), one per host thread
 static thread_local char g_create_err[512] = "";
 
-size_t elem_size(int st);
-
-// Launch shape of the step kernels: 1D blocks of up to 4 wavefronts, each
-// one 64-node x segment of one row (wave_segment); for nx = 256 a block is one
-// row.
-// Every block full either way: one block row per (y, z) when the row splits
-// into whole blocks (nxs <= 4 or a multiple of 4), else the flat grid.
-static bool flat_grid(int nx, int ny, int nz) {
-  const int nxs = (nx + SEG - 1) / SEG;
-  return !(nxs <= SEGS_PER_BLOCK || nxs % SEGS_PER_BLOCK == 0) || ny > 65535 || nz > 65535;
-}
-
-void step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid) {
-  const int nxs = (nx + SEG - 1) / SEG;
-  if (flat_grid(nx, ny, nz)) {
-    const int64_t nseg = (int64_t)nxs * ny * nz;  // below 2^31 (lbm_create)
-    block = dim3(SEG * SEGS_PER_BLOCK, 1, 1);
-    grid = dim3((unsigned)((nseg + SEGS_PER_BLOCK - 1) / SEGS_PER_BLOCK), 1, 1);
-  } else {
-    const int w = nxs < SEGS_PER_BLOCK ? nxs : SEGS_PER_BLOCK;
-    block = dim3(SEG * w, 1, 1);
-    grid = dim3((nxs + w - 1) / w, ny, nz);
-  }
-}
-
-// storage layout of a configuration (see lbm_internal.hpp)
-static Geom make_geom(const lbm_config* cfg) {
-  Geom g{};
-  g.nx = cfg->nx;
-  g.ny = cfg->ny;
-  g.nz = cfg->nz;
-  g.nxs = (cfg->nx + SEG - 1) / SEG;
-  g.nxp = g.nxs * SEG;
-  g.rowlen = (int64_t)LBM_Q * g.nxp;
-  g.by_nxs = make_div31((uint32_t)g.nxs);
-  g.by_ny = make_div31((uint32_t)g.ny);
-  g.flat = flat_grid(g.nx, g.ny, g.nz) ? 1 : 0;
-  return g;
-}
 
 int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
   char* dst = c ? c->err : g_create_err;
@@ -392,18 +353,6 @@ extern "C" int lbm_omega_table(const lbm_config* cfg, double out[LBM_Q]) {
     if (!(w[j] > 0.0 && w[j] < 2.0)) return LBM_EINVAL;
   for (int j = 0; j < LBM_Q; ++j) out[j] = w[j];
   return LBM_OK;
-}
-
-size_t elem_size(int st) {
-  switch (st) {
-    case LBM_F64: return 8;
-    case LBM_F32: return 4;
-    case LBM_F16DEV:
-    case LBM_BF16DEV:
-    case LBM_F16DEV_RNE:
-    case LBM_BF16DEV_RNE: return 2;
-    default: return 0;
-  }
 }
 
 extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {

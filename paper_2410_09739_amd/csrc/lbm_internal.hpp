@@ -1,367 +1,13 @@
-// lbm_internal.hpp -- pieces shared by the translation units of liblbm.so
-// (storage forms, the context, error handling, launch shapes).  Not part of
-// the public interface (include/lbm.h).
+// lbm_internal.hpp -- host-side pieces shared by the translation units of
+// liblbm.so (the context, error handling, dispatch helpers).  Not part of the
+// public interface (include/lbm.h).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
-#include "../../include/lbm.h"
-#include "d3q27.hpp"
-#include "fpc_collide.hpp"
-
-using namespace fpc;
-
-// ===========================================================================
-// storage forms
-template <int ST>
-struct Stor;
-
-template <>
-struct Stor<LBM_F64> {
-  using S = double;
-  using R = double;
-  static constexpr bool units = false;  // stores plain deviations
-  static __device__ __forceinline__ R dec(S s, int) { return s; }
-  static __device__ __forceinline__ R raw(S s) { return s; }
-  // f: exact power of two still carried by r (see inverse_all)
-  static constexpr bool stochastic = false;
-  static __device__ __forceinline__ S enc(R r, int, double f = 1.0, uint32_t = 0) { return r * f; }
-  static __device__ __forceinline__ S enc_nearest(R r, int a, double f = 1.0) { return enc(r, a, f); }
-};
-
-template <>
-struct Stor<LBM_F32> {
-  using S = float;
-  using R = float;
-  static constexpr bool units = false;
-  static __device__ __forceinline__ R dec(S s, int) { return s; }
-  static __device__ __forceinline__ R raw(S s) { return s; }
-  static constexpr bool stochastic = false;
-  static __device__ __forceinline__ S enc(R r, int, double f = 1.0, uint32_t = 0) { return r * (float)f; }
-  static __device__ __forceinline__ S enc_nearest(R r, int a, double f = 1.0) { return enc(r, a, f); }
-};
-
-// FP16 / BF16 deviation storage.  SR = true: stochastic rounding with the
-// gfx950 conversions v_cvt_sr_{f16,bf16}_f32, which compare the dropped bits
-// with the high bits of a random word (E[round(x)] = x), so that increments
-// smaller than half an ulp (a small body force, slow viscous change) are kept
-// on average instead of being rounded away.  SR = false: round to nearest even.
-typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-
-template <bool SR>
-struct StorF16 {
-  using S = _Float16;
-  using R = float;
-  static constexpr bool stochastic = SR;
-  // the kernels' arithmetic runs in storage units (fpc_collide.hpp): raw()
-  // is the stored number, dec() the deviation
-  static constexpr bool units = true;
-  static __device__ __forceinline__ R raw(S s) { return (float)s; }
-  static __device__ __forceinline__ R dec(S s, int a) { return (float)s * (1.0f / dev_scale(a)); }
-  static __device__ __forceinline__ S enc(R r, int a, double f = 1.0, uint32_t rnd = 0) {
-    const float x = r * (float)(dev_scale(a) * f);
-    if (SR) {
-      // the conversion writes the low half and keeps the high one, which is
-      // never stored: seed it with x's own bits (x is dead afterwards), so
-      // no register has to be cleared first
-      f16x2_t h = __builtin_bit_cast(f16x2_t, x);
-      h = __builtin_amdgcn_cvt_sr_f16_f32(h, x, rnd, false);
-      return h[0];
-    }
-    return (_Float16)x;  // round to nearest even (default mode)
-  }
-  static __device__ __forceinline__ S enc_nearest(R r, int a, double f = 1.0) {
-    return (_Float16)(r * (float)(dev_scale(a) * f));
-  }
-};
-
-template <bool SR>
-struct StorBF16 {
-  using S = uint16_t;
-  using R = float;
-  static constexpr bool stochastic = SR;
-  static constexpr bool units = true;
-  static __device__ __forceinline__ R raw(S s) { return __uint_as_float((uint32_t)s << 16); }
-  static __device__ __forceinline__ R dec(S s, int a) {
-    return __uint_as_float((uint32_t)s << 16) * (1.0f / dev_scale(a));
-  }
-  static __device__ __forceinline__ S enc(R r, int a, double f = 1.0, uint32_t rnd = 0) {
-    const float x = r * (float)(dev_scale(a) * f);
-    if (SR) {
-      bf16x2_t h = __builtin_bit_cast(bf16x2_t, x);  // high half never stored (see StorF16)
-      h = __builtin_amdgcn_cvt_sr_bf16_f32(h, x, rnd, false);
-      return __builtin_bit_cast(uint16_t, h[0]);
-    }
-    return __builtin_bit_cast(uint16_t, (__bf16)x);  // v_cvt_pk_bf16_f32: nearest even
-  }
-  static __device__ __forceinline__ S enc_nearest(R r, int a, double f = 1.0) {
-    return __builtin_bit_cast(uint16_t, (__bf16)(r * (float)(dev_scale(a) * f)));
-  }
-};
-
-template <> struct Stor<LBM_F16DEV> : StorF16<true> {};
-template <> struct Stor<LBM_BF16DEV> : StorBF16<true> {};
-template <> struct Stor<LBM_F16DEV_RNE> : StorF16<false> {};
-template <> struct Stor<LBM_BF16DEV_RNE> : StorBF16<false> {};
-
-// random word of the stored values of one node in one step: a published
-// 32-bit integer hash (lowbias32) of the node's byte offset and the step,
-// plus a golden-ratio Weyl increment per direction (its high bits, the ones
-// the conversions use, are well spread)
-__device__ __forceinline__ uint32_t node_hash(uint32_t node, uint32_t step) {
-  uint32_t h = node ^ (step * 0x9E3779B1u + 0x7F4A7C15u);
-  h ^= h >> 16;
-  h *= 0x7FEB352Du;
-  h ^= h >> 15;
-  h *= 0x846CA68Bu;
-  h ^= h >> 16;
-  return h;
-}
-
-// Layout of a state buffer in HBM (every storage form): x is cut into
-// segments of SEG = 64 nodes (one wavefront); for every (y, z) row the
-// nxp = ceil(nx / 64) * 64 padded nodes form nxp / 64 segments, and a segment
-// holds its 27 directions one after the other, 64 consecutive x values each:
-//   index(a, x, y, z) = (z ny + y) 27 nxp + 27 * 64 floor(x / 64) + 64 a + (x mod 64).
-// A wavefront that updates one segment reads and writes a few contiguous
-// 27 x 64-value blocks (its own row and the y/z neighbour rows) instead of 54
-// separate direction arrays.  Measured on the 256x128x128 channel against 27
-// direction arrays: FP32 +11 %, FP64 +5 %, BF16 +7 %, FP16 +2 %.
-constexpr int SEG = 64;
-
-// Division of numerators below 2^31 by an invariant d >= 1 as a multiply and
-// a shift (Granlund and Montgomery, 1994): with l = ceil(log2 d) and
-// m = ceil(2^(31+l) / d) < 2^32, floor(n / d) = (n m) >> (31 + l).
-struct Div31 {
-  uint32_t m;
-  uint32_t shift;  // 31 + l
-  __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const {
-    return (uint32_t)(((uint64_t)n * m) >> shift);
-  }
-};
-inline Div31 make_div31(uint32_t d) {
-  uint32_t l = 0;
-  while (((uint64_t)1 << l) < d) ++l;
-  const uint64_t p = (uint64_t)1 << (31 + l);
-  return Div31{(uint32_t)((p + d - 1) / d), 31 + l};
-}
-
-struct Geom {
-  int nx, ny, nz;
-  int nxs;         // x segments per row, ceil(nx / SEG)
-  int nxp;         // nx rounded up to a multiple of SEG
-  int64_t rowlen;  // values per (y, z) row: 27 nxp
-  Div31 by_nxs, by_ny;  // wavefront -> (segment, row) of the step kernels (flat grid)
-  int flat;             // 1: flat grid over all row segments; 0: one block row per (y, z)
-};
-
-// position of x inside a row, in values
-__host__ __device__ __forceinline__ uint32_t x_part(int x) {
-  const uint32_t u = (uint32_t)x;
-  return (u / SEG) * (Q * SEG) + u % SEG;
-}
-
-__host__ __device__ __forceinline__ int64_t pop_index(const Geom& g, int a, int x, int y, int z) {
-  return ((int64_t)z * g.ny + y) * g.rowlen + a * SEG + x_part(x);
-}
-
-// (x, y, z) of the linear node index i = x + nx (y + ny z)
-__host__ __device__ __forceinline__ void node_xyz(const Geom& g, int64_t i, int& x, int& y, int& z) {
-  const int ii = (int)i;  // N < 2^31
-  x = ii % g.nx;
-  const int r = ii / g.nx;
-  y = r % g.ny;
-  z = r / g.ny;
-}
-
-// walls on any face and a moving lid (the general boundary kernel)
-template <typename T>
-struct Box {
-  int wx, wy, wz;  // halfway bounce-back walls across x / y / z
-  int lid_on;      // the wall above y = ny - 1 moves with lid[]
-  T lid6[3];       // 6 U = 2 U / c_s^2 (momentum correction per unit weight)
-  int sym;         // the face above y = ny - 1 is a specular symmetry plane
-  int les_on;      // Smagorinsky LES with van Driest damping
-  T les_c;         // Smagorinsky constant C
-  T les_s;         // u_tau / nu (0: no damping)
-  T les_ia;        // 1 / A+
-};
-
-template <typename T>
-struct StepArgs {
-  Geom g;
-  Rates<T> r;
-  T F[3];
-  uint32_t step;  // completed steps before this one (random words of SR storage)
-  Box<T> box;
-};
-
-// ===========================================================================
-// streaming (Appendix D Step 6), pull form, shared by every kernel that reads a
-// time level: f_alpha(x) = f~_alpha(x - e_alpha), periodic wrap, and halfway
-// bounce-back across the y walls (the node's own opposite population).
-//
-// The caller's wavefront covers one x segment of one row: y and z are uniform
-// across it, so every row and direction base is a scalar 64-bit address and
-// the only per-lane address terms are the three x offsets inside a row
-// (32-bit; checked at creation).  Lanes with x >= nx must not call.
-// SU: leave the stored numbers in v (storage units, fpc_collide.hpp) instead
-// of the deviations.
-template <int ST, bool WALLS, bool SU = false>
-__device__ __forceinline__ void pull(const typename Stor<ST>::S* __restrict__ src, const Geom& g, int x, int y, int z,
-                                     typename Stor<ST>::R (&v)[3][3][3]) {
-  using T = typename Stor<ST>::R;
-  using S = typename Stor<ST>::S;
-  using SS = Stor<ST>;
-  constexpr uint32_t SZ = sizeof(S);
-  const int nx = g.nx, ny = g.ny, nz = g.nz;
-  // rows away from the walls (all but two per plane) take the wall-free gather,
-  // whose loads keep the scalar-base form; the branch is wavefront-uniform
-  if (WALLS && y > 0 && y < ny - 1) return pull<ST, false, SU>(src, g, x, y, z, v);
-  const char* __restrict__ sb = (const char*)src;
-  const int64_t rowb = g.rowlen * SZ;
-  const int64_t planeb = rowb * ny;
-  constexpr uint64_t dirb = SEG * SZ;  // one direction block of a segment
-  // per-lane byte offsets inside a row of the source x for e_x = -1, 0, +1
-  const uint32_t xo[3] = {x_part(x == nx - 1 ? 0 : x + 1) * SZ, x_part(x) * SZ, x_part(x == 0 ? nx - 1 : x - 1) * SZ};
-  // uniform byte offsets: this row, and the steps to the source rows for
-  // e_y, e_z = -1, 0, +1 (periodic wrap), additions only
-  const int64_t r0 = ((int64_t)z * ny + y) * rowb;
-  const int64_t dy[3] = {y == ny - 1 ? rowb - planeb : rowb, 0, y == 0 ? planeb - rowb : -rowb};
-  const int64_t span = planeb * nz;
-  const int64_t dz[3] = {z == nz - 1 ? planeb - span : planeb, 0, z == 0 ? span - planeb : -planeb};
-  const char* dptr = sb + r0;  // this row of direction a
-#pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const int ex = EX[a], ey = EY[a], ez = EZ[a];
-    // halfway bounce-back: if x - e_alpha is a wall node, take the node's own
-    // opposite population (same weight, so the deviation carries over)
-    const bool bb = WALLS && ((ey == 1 && y == 0) || (ey == -1 && y == ny - 1));
-    const int o = opposite(a);
-    // bb is uniform: the base is chosen in scalar registers
-    const char* base = bb ? sb + r0 + (uint64_t)o * dirb : dptr + (dy[ey + 1] + dz[ez + 1]);
-    const uint32_t off = bb ? xo[1] : xo[ex + 1];
-    dptr += dirb;
-    // w_opp = w_alpha and the storage scales are equal
-    const S sv = *(const S*)(base + off);
-    v[ez + 1][ey + 1][ex + 1] = SU ? SS::raw(sv) : SS::dec(sv, a);
-  }
-}
-
-// Gather with walls on any set of faces and an optional moving lid above
-// y = ny - 1 (the cavity of Sec. 4).  A link whose source lies outside a
-// walled face takes the node's own opposite population (halfway
-// bounce-back); a link through the lid adds the moving-wall correction
-// 2 w_a rho_w (e_a . U) / c_s^2 with rho_w = 1.  y and z walls are
-// wavefront-uniform; x walls touch only the first and last lane of a row, so
-// those lanes reload their own opposite population.  Wavefronts away from
-// every wall take the wall-free gather.
-template <int ST, bool SU = false>
-__device__ __forceinline__ void pull_box(const typename Stor<ST>::S* __restrict__ src, const Geom& g,
-                                         const Box<typename Stor<ST>::R>& b, int x, int y, int z,
-                                         typename Stor<ST>::R (&v)[3][3][3]) {
-  using T = typename Stor<ST>::R;
-  using S = typename Stor<ST>::S;
-  using SS = Stor<ST>;
-  auto get = [](S sv, int a) -> T { return SU ? SS::raw(sv) : SS::dec(sv, a); };
-  constexpr uint32_t SZ = sizeof(S);
-  const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int x0 = __builtin_amdgcn_readfirstlane(x - (x % SEG));  // first x of the segment
-  const bool yin = !b.wy || (y > 0 && y < ny - 1);
-  const bool zin = !b.wz || (z > 0 && z < nz - 1);
-  const bool xin = !b.wx || (x0 > 0 && x0 + SEG < nx);
-  if (yin && zin && xin) return pull<ST, false, SU>(src, g, x, y, z, v);
-  const char* __restrict__ sb = (const char*)src;
-  const int64_t rowb = g.rowlen * SZ;
-  const int64_t planeb = rowb * ny;
-  constexpr uint64_t dirb = SEG * SZ;
-  const uint32_t xo[3] = {x_part(x == nx - 1 ? 0 : x + 1) * SZ, x_part(x) * SZ, x_part(x == 0 ? nx - 1 : x - 1) * SZ};
-  const int64_t r0 = ((int64_t)z * ny + y) * rowb;
-  const int64_t dy[3] = {y == ny - 1 ? rowb - planeb : rowb, 0, y == 0 ? planeb - rowb : -rowb};
-  const int64_t span = planeb * nz;
-  const int64_t dz[3] = {z == nz - 1 ? planeb - span : planeb, 0, z == 0 ? span - planeb : -planeb};
-#pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const int ex = EX[a], ey = EY[a], ez = EZ[a];
-    const int o = opposite(a);
-    const bool top = ey == -1 && y == ny - 1;
-    const bool bby = b.wy && ((ey == 1 && y == 0) || (top && !b.sym));
-    const bool bbz = b.wz && ((ez == 1 && z == 0) || (ez == -1 && z == nz - 1));
-    const bool xwall = b.wx && ex != 0 && ((ex == 1 && x == 0) || (ex == -1 && x == nx - 1));  // per lane
-    T val;
-    if (b.sym && top && !bbz) {  // uniform: specular reflection at the symmetry plane
-      // the population that left (x - e_x, ny - 1, z - e_z) with (e_x, +1, e_z)
-      val = get(*(const S*)(sb + r0 + (uint64_t)mirror_y(a) * dirb + dz[ez + 1] + xo[ex + 1]), a);
-      if (xwall) val = get(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
-    } else if (bby || bbz) {  // uniform
-      val = get(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
-      // the correction in the units of val
-      if (b.lid_on && b.wy && top)
-        val += T(weight(a) * (SU ? dev_scale(a) : 1.0f)) * (ex * b.lid6[0] + ey * b.lid6[1] + ez * b.lid6[2]);
-    } else {
-      val = get(*(const S*)(sb + r0 + (uint64_t)a * dirb + (dy[ey + 1] + dz[ez + 1]) + xo[ex + 1]), a);
-      if (xwall) val = get(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
-    }
-    v[ez + 1][ey + 1][ex + 1] = val;
-  }
-}
-
-// Smagorinsky LES with van Driest damping (the Sec. 4 channel): the shear
-// rates omega_4,5,6,8,9 of this node from its deviatoric pre-collision stress
-// Pi (the primed second-order central moments; the rest state has no
-// deviatoric part).  |S| = sqrt(2 S:S) with S = -Pi / (2 rho c_s^2 tau), so the
-// relaxation time tau = tau_0 + 3 nu_t, nu_t = (C D)^2 |S|, is the positive root
-// of tau^2 - tau_0 tau - 9 sqrt(2) (C D)^2 |Pi| / (2 rho) = 0.  D uses the
-// distance to the nearest y wall half a link outside (uniform per wavefront).
-// SU: v carries the factor UNIT of the storage units.
-// k2: the node's second-order central moments (kappa'_200, kappa'_020,
-// kappa'_002, kappa_110, kappa_101, kappa_011).
-template <bool SU = false, typename T>
-__device__ __forceinline__ void les_rates(const T (&k2)[6], T rho, const Box<T>& b, const Rates<T>& R, int y,
-                                          int ny, T (&ws)[6], T (&cs)[6]) {
-  const T k200 = k2[0], k020 = k2[1], k002 = k2[2];
-  const T k110 = k2[3], k101 = k2[4], k011 = k2[5];
-  const T tr = (k200 + k020 + k002) * T(1.0 / 3.0);
-  const T dxx = k200 - tr, dyy = k020 - tr, dzz = k002 - tr;
-  const T q = sqrt(dxx * dxx + dyy * dyy + dzz * dzz + T(2) * (k110 * k110 + k101 * k101 + k011 * k011));
-  T yw = T(y) + T(0.5);
-  if (!b.sym && T(ny) - T(0.5) - T(y) < yw) yw = T(ny) - T(0.5) - T(y);
-  const T d = b.les_s > T(0) ? T(1) - exp(-yw * b.les_s * b.les_ia) : T(1);
-  const T cd = b.les_c * d;
-  const T tau0 = recip(R.w[4]);
-  const T tau = T(0.5) * (tau0 + sqrt(tau0 * tau0 + T(18.0 * 1.4142135623730951 / Units<SU>::U) * cd * cd * q * recip(rho)));
-  const T w = recip(tau);
-  ws[0] = ws[1] = ws[2] = ws[4] = ws[5] = w;
-  cs[0] = cs[1] = cs[2] = cs[4] = cs[5] = T(1) - w;
-}
-
-// store the post-collision cube (deviations times 2^inv_shift, and times
-// UNIT in storage units) of node (x, y, z); same wavefront contract as
-// pull().  The row base walks the 27 direction blocks of the segment in scalar
-// registers; the per-lane part is the x offset only.
-template <int ST, bool SU = false>
-__device__ __forceinline__ void push(typename Stor<ST>::S* __restrict__ dst, const Geom& g, int x, int y, int z,
-                                     const typename Stor<ST>::R (&v)[3][3][3], uint32_t step) {
-  using S = typename Stor<ST>::S;
-  constexpr uint32_t SZ = sizeof(S);
-  constexpr uint64_t dirb = SEG * SZ;
-  // random word input: the node's linear index
-  const uint32_t node = ((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.nx + (uint32_t)x;
-  const uint32_t h = Stor<ST>::stochastic ? node_hash(node, step) : 0u;
-  const uint32_t off = x_part(x) * SZ;
-  char* base = (char*)dst + ((uint64_t)z * g.ny + y) * ((uint64_t)g.rowlen * SZ);
-#pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    // streaming store: the next step reads it back from HBM, not from cache
-    __builtin_nontemporal_store(Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a) / Units<SU>::U,
-                                              h + (uint32_t)a * 0x9E3779B9u),
-                                (S*)(base + off));
-    base += dirb;
-  }
-}
+#include "lattice.hpp"
 
 // ===========================================================================
 // context
@@ -390,7 +36,6 @@ struct lbm_ctx {
 };
 
 int set_err(lbm_ctx* c, int code, const char* fmt, ...);
-void step_launch_shape(int nx, int ny, int nz, dim3& block, dim3& grid);
 inline Geom geom(const lbm_ctx* c) { return c->g; }
 inline bool has_lid(const lbm_ctx* c) {
   return c->cfg.lid_velocity[0] != 0.0 || c->cfg.lid_velocity[1] != 0.0 || c->cfg.lid_velocity[2] != 0.0;
@@ -419,34 +64,6 @@ inline Box<T> box_args(const lbm_ctx* c) {
 inline int wall_mask(const lbm_ctx* c) {
   return (c->cfg.walls_y ? 1 : 0) | (c->cfg.walls_x ? 2 : 0) | (c->cfg.walls_z ? 4 : 0) | (c->cfg.sym_top ? 8 : 0);
 }
-// wavefront -> (x segment, row) for the step kernels; each wavefront keeps
-// one segment of one row (y, z uniform, as pull() needs), and every block is
-// full.  Rows that split into whole blocks (nxs <= 4 or a multiple of 4) use
-// one block row per (y, z): grid (nxs / W, ny, nz), W = min(4, nxs) segments
-// per block.  Other rows (g.flat) use a 1D grid over the nxs ny nz row
-// segments in row-major order, four per block, blocks spanning rows: the
-// hardware hands consecutive blocks to the eight XCDs in turn, and a per-row
-// grid with a partial last block (nxs = 5..7) would give every partial block
-// to the same four XCDs.  false: a wavefront past the end of the flat grid.
-constexpr int SEGS_PER_BLOCK = 4;
-__device__ __forceinline__ bool wave_segment(const Geom& g, int& x, int& y, int& z) {
-  if (!g.flat) {  // grid (ceil(nxs / W), ny, nz), blocks of W = min(4, nxs) segments
-    x = blockIdx.x * blockDim.x + threadIdx.x;
-    y = blockIdx.y;
-    z = blockIdx.z;
-    return true;
-  }
-  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t s = blockIdx.x * (uint32_t)SEGS_PER_BLOCK + w;  // below 2^31
-  const uint32_t row = g.by_nxs.div(s);
-  if (row >= (uint32_t)g.ny * (uint32_t)g.nz) return false;
-  const uint32_t zz = g.by_ny.div(row);
-  y = (int)(row - zz * (uint32_t)g.ny);
-  z = (int)zz;
-  x = (int)(s - row * (uint32_t)g.nxs) * SEG + (int)(threadIdx.x & 63);
-  return true;
-}
-size_t elem_size(int st);
 int alloc_scratch(lbm_ctx* c);
 // closure.hip: enqueue n steps of the stream-collide kernel with the fused closure
 int launch_closure_steps(lbm_ctx* c, int64_t nsteps);

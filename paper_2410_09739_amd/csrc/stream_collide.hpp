@@ -4,7 +4,7 @@
 // kernel depends on is exactly this file and the ones it includes.
 #pragma once
 
-#include "lbm_internal.hpp"
+#include "lattice.hpp"
 
 // Block of up to 4 wavefronts; each wavefront is one 64-node x segment of one
 // row (y, z uniform; wave_segment).  BC: 0 periodic, 1 walls across y (the

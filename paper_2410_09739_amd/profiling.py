@@ -29,7 +29,7 @@ from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_2410_09739_amd/csrc/stream_collide.hpp", "paper_2410_09739_amd/csrc/fpc_collide.hpp",
-                  "paper_2410_09739_amd/csrc/d3q27.hpp", "paper_2410_09739_amd/csrc/lbm_internal.hpp"]
+                  "paper_2410_09739_amd/csrc/d3q27.hpp", "paper_2410_09739_amd/csrc/lattice.hpp"]
 # storage form id (template argument of k_stream_collide) -> (name, bytes per population)
 FORMS = {0: ("f64", 8), 1: ("f32", 4), 2: ("f16dev", 2), 3: ("bf16dev", 2), 4: ("f16dev_rne", 2),
          5: ("bf16dev_rne", 2)}
@@ -106,15 +106,15 @@ def traffic(args) -> dict:
         forms[form] = {"kernel": name, "launches": len(fetch[name]), "fetch_kib": round(fk, 3),
                        "write_kib": round(wk, 3), "hbm_bytes_per_launch": round(hbm),
                        "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": round(hbm / alg, 5)}
-    return {"kernel_source_sha": kernel_source_hash(), "shape": [args.nx, args.ny, args.nz], "nodes": nodes,
+    return {"kernel_source_sha": kernel_source_hash(), "workload": args.workload,
+            "shape": [args.nx, args.ny, args.nz], "nodes": nodes,
             "copy_factor_fetch_bytes_per_kib": round(cf, 3), "copy_factor_write_bytes_per_kib": round(cw, 3),
             "forms": forms}
 
 
 def write_traffic_md(res: dict, out: str, cmds: list[str]) -> None:
     with open(out, "w") as fo:
-        fo.write("# HBM traffic of the fused stream-collide kernel, channel "
-                 + "x".join(str(n) for n in res["shape"]) + " (walls, body force)\n\n")
+        fo.write(f"# HBM traffic of the fused stream-collide kernel, {res['workload']}\n\n")
         fo.write("FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from separate rocprofv3 --pmc runs, "
                  "each scaled by the bytes per KiB that the same counter shows for a plain device "
                  f"copy of known size (fetch {res['copy_factor_fetch_bytes_per_kib']} B/KiB, "
@@ -185,6 +185,7 @@ def main() -> None:
     t.add_argument("--nx", type=int, default=256)
     t.add_argument("--ny", type=int, default=128)
     t.add_argument("--nz", type=int, default=128)
+    t.add_argument("--workload", default="channel 256x128x128 (walls, body force)")
     t.add_argument("--cmd", action="append", default=[])
     a = ap.parse_args()
     if a.cmd_name == "kernel-stats":

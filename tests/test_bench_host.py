@@ -11,8 +11,8 @@ sys.path.insert(0, ROOT)
 
 from paper_2410_09739_amd import profiling as P  # noqa: E402
 
-TRAFFIC = os.path.join(ROOT, "profiles", "traffic_stream_collide_channel_256x128x128.md")
-TRACE = os.path.join(ROOT, "profiles", "stream_collide_channel_256x128x128_kernel_trace.md")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_stream_collide_taylor_green_512.md")
+TRACE = os.path.join(ROOT, "profiles", "stream_collide_taylor_green_512_kernel_trace.md")
 
 
 @pytest.mark.parametrize("n", [2, 8])
@@ -33,14 +33,16 @@ def test_traffic_summary_matches_the_kernel_sources():
     assert t["kernel_source_sha"] == P.kernel_source_hash()
     for form, algo in (("f32", 216), ("f64", 432), ("f16dev", 108), ("bf16dev", 108)):
         f = t["forms"][form]
-        assert f["algorithmic_bytes_per_launch"] == algo * 256 * 128 * 128
+        assert f["algorithmic_bytes_per_launch"] == algo * 512 ** 3
         assert 0.99 < f["traffic_over_algorithmic"] < 1.05
 
 
 def test_kernel_trace_summary_covers_the_timed_kernel():
     text = open(TRACE).read()
     assert "rocprofv3 --kernel-trace --stats" in text
-    assert "k_stream_collide<1, 1, true, false>" in text  # FP32, y walls, force: the benchmark's kernel
+    # FP32, periodic, no force, unit higher-order rates: the benchmark's kernel
+    assert "k_stream_collide<1, 0, false, false, true>" in text
+    assert "512x512x512" in text
 
 
 def test_source_hash_ignores_comments_but_not_code():

@@ -31,6 +31,11 @@ def host():
         getattr(lib, n).argtypes = [_dp, _dp, _dp]
     for n in ("host_collide_unit_dev_f32", "host_collide_unit_units_f32"):
         getattr(lib, n).argtypes = [_fp, _dp, _fp]
+    lib.host_launch_cover.argtypes = [ctypes.c_int] * 4 + [ctypes.POINTER(ctypes.c_int),
+                                                           ctypes.POINTER(ctypes.c_longlong)]
+    lib.host_launch_cover.restype = ctypes.c_longlong
+    for n in ("host_lattice_ke_f64", "host_lattice_ke_f32"):
+        getattr(lib, n).argtypes = [ctypes.c_int] * 3 + [_dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
     return lib
 
 
@@ -147,3 +152,48 @@ def test_unit_rate_collision_in_storage_units_is_bitwise_the_deviation_one(host,
         outs.append(o)
     assert np.all(np.isfinite(outs[0]))
     assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
+
+
+@pytest.mark.parametrize("general", [0, 1])
+def test_fp32_arithmetic_keeps_the_kinetic_energy_of_fp64(host, general):
+    """A 16^3 periodic Taylor-Green vortex (u0 = 0.05, omega_2 = 1.97) stepped
+    400 times with the kernels' arithmetic in FP32 and in FP64 (storage in the
+    same precision).  The FP32 kinetic energy must stay within 2e-6 of the
+    FP64 one (measured 3.4e-7 at most, with no trend).  Two systematic FP32
+    biases broke this: the rest-state line constants of the inverse sweeps,
+    whose nearest FP32 values do not sum to 1 (the rebuilt momentum was scaled
+    by 1 + 2^-25 in y and 1 + 2^-27 in x every step), and 1/rho taken from the
+    rounded 1 + rho'; with both the error was 1.4e-5 here and grew linearly."""
+    n, u0 = 16, 0.05
+    rho, u = W.taylor_green(n, u0=u0)
+    f = np.ascontiguousarray(O.init(rho, u).reshape(27, -1))
+    om = np.ascontiguousarray(O.omega_table(2.5465e-3))
+    steps = 400
+    ke = {}
+    for tag in ("f64", "f32"):
+        out = np.zeros(steps + 1)
+        getattr(host, f"host_lattice_ke_{tag}")(n, n, n, f.ctypes.data_as(_dp), om.ctypes.data_as(_dp), steps,
+                                               general, out.ctypes.data_as(_dp))
+        ke[tag] = out
+    assert ke["f64"][-1] < 0.9 * ke["f64"][0]  # the flow decays
+    rel = np.abs(ke["f32"] - ke["f64"]) / ke["f64"]
+    assert rel.max() < 2e-6, rel.max()
+
+
+@pytest.mark.parametrize("shape", [(512, 8, 4), (256, 9, 5), (320, 7, 3), (448, 5, 6), (65, 11, 3), (1, 17, 5),
+                                   (768, 3, 2), (130, 1, 1), (64, 8, 8), (200, 13, 7), (1024, 6, 1)])
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_step_launch_covers_every_node_once(host, shape, storage):
+    """The step kernels' grid in the XCD-aware block order (FP64, FP32) and in
+    the plain order (FP16): every node is updated by exactly one lane, and
+    every wavefront holds one 64-node segment of one row (y and z uniform,
+    lane = x mod 64), for per-row grids (one to four blocks per row), flat
+    grids (rows of 5-7 segments), ragged rows and block counts with and
+    without a remainder modulo 8."""
+    nx, ny, nz = shape
+    count = np.zeros(nx * ny * nz, dtype=np.int32)
+    bad = ctypes.c_longlong(0)
+    nb = host.host_launch_cover(nx, ny, nz, storage, count.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                ctypes.byref(bad))
+    assert nb > 0 and bad.value == 0
+    assert np.all(count == 1), (count.min(), count.max())
