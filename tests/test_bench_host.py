@@ -27,14 +27,18 @@ def test_bench_refuses_more_than_one_gpu(n):
 def test_traffic_summary_matches_the_kernel_sources():
     """The HBM byte counts the benchmark reports as roofline.traffic were taken
     with the stream-collide sources as they are now (else the benchmark reports
-    null): a kernel change must come with a new measurement."""
+    null): a kernel change must come with a new measurement.  FP32 and FP64 run
+    in the XCD-aware block order and fetch within 2 % of the algorithmic bytes;
+    the 16-bit forms run in the plain order, where the two halves of a 512-node
+    row sit on different XCDs and the cache lines at their seams are fetched
+    by both (8 % more reads; the plain order still runs faster for them)."""
     t = P.read_traffic_md(TRAFFIC)
     assert t is not None
     assert t["kernel_source_sha"] == P.kernel_source_hash()
-    for form, algo in (("f32", 216), ("f64", 432), ("f16dev", 108), ("bf16dev", 108)):
+    for form, algo, bound in (("f32", 216, 1.02), ("f64", 432, 1.02), ("f16dev", 108, 1.10), ("bf16dev", 108, 1.10)):
         f = t["forms"][form]
         assert f["algorithmic_bytes_per_launch"] == algo * 512 ** 3
-        assert 0.99 < f["traffic_over_algorithmic"] < 1.05
+        assert 0.99 < f["traffic_over_algorithmic"] < bound, form
 
 
 def test_kernel_trace_summary_covers_the_timed_kernel():
