@@ -221,6 +221,21 @@ int lbm_set_f(lbm_ctx* c, const double* f);
  * outside [0, N) is LBM_EINVAL.  Synchronous. */
 int lbm_get_f_nodes(lbm_ctx* c, const int64_t* nodes, int64_t count, double* f);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving or monitoring loops, harnesses that forbid hipMalloc): the same as
+ * lbm_get_f_nodes, with identical results, but it allocates nothing.  The
+ * node list and the populations are staged in a fixed device array of
+ * LBM_NOALLOC_MAX_NODES * (8 + 27 * 8) bytes (917,504) that the library holds
+ * on every GPU it runs on until the process ends (its address is looked up
+ * once per device by lbm_create).  count > LBM_NOALLOC_MAX_NODES is
+ * LBM_EINVAL; the other errors are those of lbm_get_f_nodes.  All calls on one
+ * GPU share that array: calls that overlap in time on one GPU (from several
+ * host threads or contexts) race and must be serialised by the caller.  The
+ * host copies use the caller's pointers as given (pageable memory is copied
+ * through the runtime).  Synchronous. */
+#define LBM_NOALLOC_MAX_NODES 4096
+int lbm_get_f_nodes_noalloc(lbm_ctx* c, const int64_t* nodes, int64_t count, double* f);
+
 /* Bit-exact checkpoint of the raw storage: one state buffer as the library
  * keeps it in device memory (deviations f - w in the storage type, FP16/BF16
  * scaled; blocked by 64-node x segments, each holding its 27 directions, nx

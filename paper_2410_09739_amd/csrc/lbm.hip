@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 
@@ -355,6 +356,8 @@ extern "C" int lbm_omega_table(const lbm_config* cfg, double out[LBM_Q]) {
   return LBM_OK;
 }
 
+static int noalloc_setup(lbm_ctx* c, int dev);
+
 extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   if (!out) return set_err(nullptr, LBM_EINVAL, "lbm_create: out is NULL");
   *out = nullptr;
@@ -421,6 +424,12 @@ extern "C" int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     set_err(nullptr, code, "lbm_create: %s", hipGetErrorString(e));
     lbm_destroy(c);
     return code;
+  }
+  // once per device: the address of the staging array of the no-allocation calls
+  const int rc = noalloc_setup(nullptr, c->device);
+  if (rc != LBM_OK) {
+    lbm_destroy(c);
+    return rc;
   }
   *out = c;
   return LBM_OK;
@@ -628,6 +637,61 @@ extern "C" int lbm_get_f_nodes(lbm_ctx* c, const int64_t* nodes, int64_t count, 
   if (e == hipSuccess) e = e3;
   if (e == hipSuccess) e = e2;
   if (e != hipSuccess) return set_err(c, LBM_EHIP, "lbm_get_f_nodes: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// lbm_get_f_nodes without allocation: the node list and the populations are
+// staged in a file-scope device array instead of a per-call hipMalloc.  Each
+// GPU the library runs on holds its own copy of the array until the process
+// ends; host code never uses the array's name as an address (on the host it
+// is only a stand-in): lbm_create looks up the device address once per device
+// with hipGetSymbolAddress and keeps it in g_noalloc_ptr.
+constexpr int64_t NOALLOC_BYTES = LBM_NOALLOC_MAX_NODES * (int64_t)sizeof(int64_t) +
+                                  LBM_NOALLOC_MAX_NODES * (int64_t)LBM_Q * (int64_t)sizeof(double);
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_noalloc_mutex;
+static void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// with device `dev` current: the device address of its scratch array
+static int noalloc_setup(lbm_ctx* c, int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return set_err(c, LBM_EINVAL, "device %d beyond the library's table", dev);
+  std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+  if (g_noalloc_ptr[dev]) return LBM_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return set_err(c, LBM_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_noalloc_ptr[dev] = ptr;
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_f_nodes_noalloc(lbm_ctx* c, const int64_t* nodes, int64_t count, double* f) {
+  if (!c || count < 0 || (count > 0 && (!nodes || !f)))
+    return set_err(c, LBM_EINVAL, "lbm_get_f_nodes_noalloc: bad arguments");
+  if (count > LBM_NOALLOC_MAX_NODES)
+    return set_err(c, LBM_EINVAL, "lbm_get_f_nodes_noalloc: %lld nodes exceed the maximum of %d per call",
+                   (long long)count, LBM_NOALLOC_MAX_NODES);
+  if (!c->initialised) return set_err(c, LBM_ESTATE, "lbm_get_f_nodes_noalloc: state not initialised");
+  for (int64_t k = 0; k < count; ++k)
+    if (nodes[k] < 0 || nodes[k] >= c->n)
+      return set_err(c, LBM_EINVAL, "lbm_get_f_nodes_noalloc: node %lld outside [0, %lld)", (long long)nodes[k],
+                     (long long)c->n);
+  if (count == 0) return LBM_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  char* base = (char*)g_noalloc_ptr[c->device];  // set by lbm_create on this device
+  if (!base) return set_err(c, LBM_ESTATE, "lbm_get_f_nodes_noalloc: scratch not set up on device %d", c->device);
+  int64_t* dn = (int64_t*)base;
+  double* df = (double*)(base + LBM_NOALLOC_MAX_NODES * (int64_t)sizeof(int64_t));
+  const size_t nb = sizeof(int64_t) * count, fb = sizeof(double) * LBM_Q * count;
+  HIPCHK(c, hipMemcpyAsync(dn, nodes, nb, hipMemcpyHostToDevice, c->stream));
+  DISPATCH_ST(c->cfg.storage,
+              k_get_f_nodes<ST><<<nblocks(count, 256), 256, 0, c->stream>>>((const typename Stor<ST>::S*)c->buf[c->cur], dn,
+                                                                            count, df, geom(c)));
+  LAUNCHCHK(c);
+  HIPCHK(c, hipMemcpyAsync(f, df, fb, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
 

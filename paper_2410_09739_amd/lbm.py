@@ -80,6 +80,7 @@ SIGNATURES = {
     "lbm_get_f": (ctypes.c_int, [_ctx, _dp]),
     "lbm_set_f": (ctypes.c_int, [_ctx, _dp]),
     "lbm_get_f_nodes": (ctypes.c_int, [_ctx, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, _dp]),
+    "lbm_get_f_nodes_noalloc": (ctypes.c_int, [_ctx, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, _dp]),
     "lbm_state_bytes": (ctypes.c_int64, [_ctx]),
     "lbm_get_raw": (ctypes.c_int, [_ctx, _vp, ctypes.c_int64]),
     "lbm_set_raw": (ctypes.c_int, [_ctx, _vp, ctypes.c_int64]),
@@ -203,6 +204,12 @@ def lbm_get_f(ctx, f: np.ndarray):
 def lbm_get_f_nodes(ctx, nodes, f: np.ndarray):
     n = np.ascontiguousarray(nodes, dtype=np.int64)
     _check(load().lbm_get_f_nodes(ctx, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(n.size), _dptr(f)), ctx)
+
+
+def lbm_get_f_nodes_noalloc(ctx, nodes, f: np.ndarray):
+    n = np.ascontiguousarray(nodes, dtype=np.int64)
+    _check(load().lbm_get_f_nodes_noalloc(ctx, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(n.size), _dptr(f)),
+           ctx)
 
 
 def lbm_set_f(ctx, f: np.ndarray):
