@@ -437,3 +437,82 @@ def test_closure_pipeline_end_to_end():
     du = np.abs(results[True][1] - results[False][1]).max()
     assert du > 0.0  # the closure acts
     assert du < 0.5 * np.abs(results[False][1]).max()
+
+
+def test_trained_closure_removes_subfilter_flux_error_on_a_held_out_snapshot():
+    """What the trained network gains over the method without it, a priori:
+    on a filtered snapshot that training never saw, the eddy viscosities the
+    network predicts (BF16 matrix-core inference, clamped to [0, 1/3] as the
+    fused step applies them) must remove at least half of the flux error that
+    its targets remove.  The error of a coarse node, per off-diagonal group
+    j (xy, xz, yz), is the filtered fine flux minus the coarse model flux,
+    a_j - nu_t,j S_j with a_j = nu_j (Sbar_j - S_j) - tau_j / (2 rho~) (the
+    sub-filter stress tau, the Favre-filtered fine strain Sbar and the coarse
+    strain S of the filtered velocity, here from the oracle's stencil); summed
+    squares over the snapshot.  Without the network nu_t = 0.  (The a-posteriori
+    gain on the mean profile of coarse channel runs is measured separately and
+    is not reliable at these sizes.)"""
+    fine_shape = (128, 64, 64)
+    h, ut = 32.0, 0.0025
+    nu_f, F_f = ut * h / 180.0, ut * ut / h
+    nc = np.prod(fine_shape) // 8
+    cshape = tuple(s // 2 for s in fine_shape)
+    ccfg = L.Config(*cshape, storage="f32", walls_y=True, nu=nu_f / 2, force=(2 * F_f, 0, 0))
+    rho0, u0 = W.channel_turbulent_start(*fine_shape, u_bulk=15.7 * ut, amp=0.3, seed=3)
+    snaps = []
+    with L.Lattice(L.Config(*fine_shape, storage="f32", walls_y=True, nu=nu_f, force=(F_f, 0, 0))) as fine, \
+            L.Lattice(ccfg) as feat:
+        fine.init(rho0, u0)
+        fine.step(3000)
+        for k in range(5):
+            fine.step(1000)
+            rd, ud = torch.zeros(nc, dtype=torch.float64, device="cuda"), torch.zeros(3 * nc, dtype=torch.float64,
+                                                                                     device="cuda")
+            td, sd = torch.zeros(6 * nc, dtype=torch.float64, device="cuda"), torch.zeros(6 * nc, dtype=torch.float64,
+                                                                                         device="cuda")
+            xd = torch.zeros((nc, 27), dtype=torch.float32, device="cuda")
+            yd = torch.zeros((nc, 6), dtype=torch.float32, device="cuda")
+            torch.cuda.synchronize()
+            L.lbm_coarsen(fine.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), sd.data_ptr())
+            fine.synchronize()
+            L.lbm_init_device(feat.ctx, rd.data_ptr(), ud.data_ptr())
+            L.lbm_closure_features(feat.ctx, xd.data_ptr())
+            L.lbm_closure_targets(feat.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr(), sd.data_ptr(), 0.1,
+                                  yd.data_ptr())
+            feat.synchronize()
+            snaps.append((rd, ud, td, sd, xd, yd))
+    X = torch.cat([s[4] for s in snaps[:-1]])
+    Y = torch.cat([s[5] for s in snaps[:-1]])
+    torch.cuda.synchronize()
+    m = L.MLP(seed=2)
+    m.fit_normalisation(X.data_ptr(), Y.data_ptr(), X.shape[0])
+    m.train(X.data_ptr(), Y.data_ptr(), X.shape[0], 4096, 4000, 1e-3, 9)
+    params = m.export()
+    m.close()
+    rd, ud, td, sd, xd, yd = snaps[-1]
+    nud = torch.zeros((nc, 6), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    L.lbm_closure_eval(params, xd.data_ptr(), nud.data_ptr(), nc)
+    torch.cuda.synchronize()
+    nz, ny, nx = cshape[2], cshape[1], cshape[0]
+    rho = rd.cpu().numpy().reshape(nz, ny, nx)
+    u = ud.cpu().numpy().reshape(3, nz, ny, nx)
+    tau = C.group(td.cpu().numpy().reshape(6, nz, ny, nx))[:3]
+    sbar = C.group(sd.cpu().numpy().reshape(6, nz, ny, nx))[:3]
+    S = C.group(C.strain(u, True))[:3]
+    nu_c = nu_f / 2
+    a = nu_c * (sbar - S) - tau / (2.0 * rho[None])
+
+    def err(nu_t):  # nu_t [3, nz, ny, nx]
+        return float(np.sum((a - nu_t * S) ** 2))
+
+    def field(v):  # [nc, 6] -> the three off-diagonal groups as [3, nz, ny, nx]
+        return np.moveaxis(v[:, :3].reshape(nz, ny, nx, 3), -1, 0).astype(np.float64)
+
+    e0 = err(np.zeros_like(S))
+    e_target = err(field(yd.cpu().numpy()))
+    e_net = err(np.clip(field(nud.cpu().numpy()), 0.0, 1.0 / 3.0))
+    print(f"held-out flux error: none {e0:.4e}, targets {e_target:.4e} ({1 - e_target / e0:.3%} less), "
+          f"network {e_net:.4e} ({1 - e_net / e0:.3%} less)")
+    assert e_target < e0
+    assert e0 - e_net >= 0.5 * (e0 - e_target), (e0, e_target, e_net)
