@@ -197,9 +197,11 @@ def test_f32_velocity_tracks_f64_over_2000_steps():
 def test_taylor_green_kinetic_energy_history_by_storage_form():
     """Kinetic-energy history of the Taylor-Green vortex (128^3, u0 0.05,
     Re 400: the viscosity of the 512^3 Re 1600 case) through t* = 10 in every
-    storage form against the FP64 run, sampled every t*/2: FP32 and FP16
-    deviation storage within 1 % (the precision study's target); BF16 printed
-    (reported, not bound)."""
+    storage form against the FP64 run, sampled every t*/2.  The precision
+    study's target is 1 %; measured 9e-8 (FP32), 1.6e-5 (FP16) and 4.8e-5
+    (BF16 deviation storage), and bound here at about ten times that: 1e-6,
+    2e-4 and 5e-4.  (A systematic FP32 drift of 4e-8 of the energy per step,
+    since removed, gave 1.7e-4 in every form.)"""
     n, u0, re = 128, 0.05, 400.0
     L0 = n / (2 * np.pi)
     nu = u0 * L0 / re
@@ -218,7 +220,7 @@ def test_taylor_green_kinetic_energy_history_by_storage_form():
     dev = {st: float(np.max(np.abs(hist[st] / hist["f64"] - 1))) for st in ("f32", "f16dev", "bf16dev")}
     print("max relative kinetic-energy difference to FP64 through t* = 10:", dev,
           "E(10)/E(0) =", float(hist["f64"][-1] / hist["f64"][0]))
-    assert dev["f32"] <= 0.01 and dev["f16dev"] <= 0.01, dev
+    assert dev["f32"] <= 1e-6 and dev["f16dev"] <= 2e-4 and dev["bf16dev"] <= 5e-4, dev
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
