@@ -126,7 +126,7 @@ __device__ __forceinline__ uint32_t node_hash(uint32_t node, uint32_t step) {
 // segments of SEG = 64 nodes (one wavefront); for every (y, z) row the
 // nxp = ceil(nx / 64) * 64 padded nodes form nxp / 64 segments, and a segment
 // holds its 27 directions one after the other, 64 consecutive x values each:
-//   index(a, x, y, z) = (z ny + y) 27 nxp + 27 * 64 floor(x / 64) + 64 a + (x mod 64).
+//   index(a, x, y, z) = (z ny + y) 27 nxp + 27 * 64 floor(x / 64) + 64 slot(a) + (x mod 64).
 // A wavefront that updates one segment reads and writes a few contiguous
 // 27 x 64-value blocks (its own row and the y/z neighbour rows) instead of 54
 // separate direction arrays.  Measured on the 256x128x128 channel against 27
@@ -161,6 +161,12 @@ struct Geom {
   uint32_t blk_per_xcd; // XCD-aware block order: blocks / 8, or 0 for the plain order
 };
 
+// Position of direction a's block inside a segment: the directions are kept
+// in the order of their velocity cube, slot = 9 (e_z + 1) + 3 (e_y + 1) + (e_x + 1),
+// so the three directions a wavefront pulls from one source row (equal e_y,
+// e_z) lie next to each other.
+__host__ __device__ constexpr int slot(int a) { return 9 * (EZ[a] + 1) + 3 * (EY[a] + 1) + (EX[a] + 1); }
+
 // position of x inside a row, in values
 __host__ __device__ __forceinline__ uint32_t x_part(int x) {
   const uint32_t u = (uint32_t)x;
@@ -168,7 +174,7 @@ __host__ __device__ __forceinline__ uint32_t x_part(int x) {
 }
 
 __host__ __device__ __forceinline__ int64_t pop_index(const Geom& g, int a, int x, int y, int z) {
-  return ((int64_t)z * g.ny + y) * g.rowlen + a * SEG + x_part(x);
+  return ((int64_t)z * g.ny + y) * g.rowlen + slot(a) * SEG + x_part(x);
 }
 
 // (x, y, z) of the linear node index i = x + nx (y + ny z)
@@ -236,16 +242,18 @@ __device__ __forceinline__ void pull(const typename Stor<ST>::S* __restrict__ sr
   const int64_t dy[3] = {y == ny - 1 ? rowb - planeb : rowb, 0, y == 0 ? planeb - rowb : -rowb};
   const int64_t span = planeb * nz;
   const int64_t dz[3] = {z == nz - 1 ? planeb - span : planeb, 0, z == 0 ? span - planeb : -planeb};
-  const char* dptr = sb + r0;  // this row of direction a
+  const char* dptr = sb + r0;  // this row of the direction in slot s
+  // slot order: the three loads from one source row are issued together
 #pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const int ex = EX[a], ey = EY[a], ez = EZ[a];
+  for (int s = 0; s < Q; ++s) {
+    const int ex = s % 3 - 1, ey = (s / 3) % 3 - 1, ez = s / 9 - 1;
+    const int a = alpha_of(ex, ey, ez);
     // halfway bounce-back: if x - e_alpha is a wall node, take the node's own
     // opposite population (same weight, so the deviation carries over)
     const bool bb = WALLS && ((ey == 1 && y == 0) || (ey == -1 && y == ny - 1));
     const int o = opposite(a);
     // bb is uniform: the base is chosen in scalar registers
-    const char* base = bb ? sb + r0 + (uint64_t)o * dirb : dptr + (dy[ey + 1] + dz[ez + 1]);
+    const char* base = bb ? sb + r0 + (uint64_t)slot(o) * dirb : dptr + (dy[ey + 1] + dz[ez + 1]);
     const uint32_t off = bb ? xo[1] : xo[ex + 1];
     dptr += dirb;
     // w_opp = w_alpha and the storage scales are equal
@@ -297,16 +305,16 @@ __device__ __forceinline__ void pull_box(const typename Stor<ST>::S* __restrict_
     T val;
     if (b.sym && top && !bbz) {  // uniform: specular reflection at the symmetry plane
       // the population that left (x - e_x, ny - 1, z - e_z) with (e_x, +1, e_z)
-      val = get(*(const S*)(sb + r0 + (uint64_t)mirror_y(a) * dirb + dz[ez + 1] + xo[ex + 1]), a);
-      if (xwall) val = get(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
+      val = get(*(const S*)(sb + r0 + (uint64_t)slot(mirror_y(a)) * dirb + dz[ez + 1] + xo[ex + 1]), a);
+      if (xwall) val = get(*(const S*)(sb + r0 + (uint64_t)slot(o) * dirb + xo[1]), a);
     } else if (bby || bbz) {  // uniform
-      val = get(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
+      val = get(*(const S*)(sb + r0 + (uint64_t)slot(o) * dirb + xo[1]), a);
       // the correction in the units of val
       if (b.lid_on && b.wy && top)
         val += T(weight(a) * (SU ? dev_scale(a) : 1.0f)) * (ex * b.lid6[0] + ey * b.lid6[1] + ez * b.lid6[2]);
     } else {
-      val = get(*(const S*)(sb + r0 + (uint64_t)a * dirb + (dy[ey + 1] + dz[ez + 1]) + xo[ex + 1]), a);
-      if (xwall) val = get(*(const S*)(sb + r0 + (uint64_t)o * dirb + xo[1]), a);
+      val = get(*(const S*)(sb + r0 + (uint64_t)slot(a) * dirb + (dy[ey + 1] + dz[ez + 1]) + xo[ex + 1]), a);
+      if (xwall) val = get(*(const S*)(sb + r0 + (uint64_t)slot(o) * dirb + xo[1]), a);
     }
     v[ez + 1][ey + 1][ex + 1] = val;
   }
@@ -357,9 +365,10 @@ __device__ __forceinline__ void push(typename Stor<ST>::S* __restrict__ dst, con
   const uint32_t off = x_part(x) * SZ;
   char* base = (char*)dst + ((uint64_t)z * g.ny + y) * ((uint64_t)g.rowlen * SZ);
 #pragma unroll
-  for (int a = 0; a < Q; ++a) {
+  for (int s = 0; s < Q; ++s) {  // slot order: one contiguous run of direction blocks
+    const int a = alpha_of(s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1);
     // streaming store: the next step reads it back from HBM, not from cache
-    __builtin_nontemporal_store(Stor<ST>::enc(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1], a, inv_factor(a) / Units<SU>::U,
+    __builtin_nontemporal_store(Stor<ST>::enc(v[s / 9][(s / 3) % 3][s % 3], a, inv_factor(a) / Units<SU>::U,
                                               h + (uint32_t)a * 0x9E3779B9u),
                                 (S*)(base + off));
     base += dirb;
@@ -388,11 +397,12 @@ __device__ __forceinline__ void push(typename Stor<ST>::S* __restrict__ dst, con
 // 0 %).  Time per step on the 512^3 vortex, chunks against the plain order
 // (same box, interleaved runs; the spread between runs is about 2 %): FP64
 // +4 %, FP32 +2 %, FP16/BF16 -1 % (their second fetch is served by the
-// last-level cache); at 384^3 FP64 +3 %, FP32 -2 %, FP16 -3 %.  Dealing whole
-// rows to the XCDs in turns (runs of one row), and blocks of a whole row of up
-// to 8 segments, also removed the second fetch but were no faster than the
-// plain order.  So the 4- and 8-byte forms take chunks, the 16-bit forms the
-// plain order.
+// last-level cache); at 384^3 FP64 +3 %, FP32 -2 %, FP16 -3 %; at 256^3 (one
+// block per row, no seam between blocks) FP32 -4 %.  Dealing whole rows to
+// the XCDs in turns (runs of one row), and blocks of a whole row of up to 8
+// segments, also removed the second fetch but were no faster than the plain
+// order.  So the 4- and 8-byte forms take chunks where a row is split across
+// blocks (more than four segments), the 16-bit forms keep the plain order.
 constexpr int SEGS_PER_BLOCK = 4;
 constexpr uint32_t XCDS = 8;
 __host__ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t per) {
@@ -470,14 +480,19 @@ inline Geom make_geom(const lbm_config* cfg) {
   g.nz = cfg->nz;
   g.nxs = (cfg->nx + SEG - 1) / SEG;
   g.nxp = g.nxs * SEG;
-  g.rowlen = (int64_t)LBM_Q * g.nxp;
+  // Rows whose byte length is a multiple of 1 KiB get 64 values of padding
+  // (measured, same box: the 512^3 vortex +2.5 % (FP16/BF16) and +0.7 % (FP32),
+  // FP64 unchanged; where the padding was tried on other rows, 256^3 and 384^3
+  // in FP16, it cost 0.5-1.7 %, and those rows are not padded).
+  const int64_t row = (int64_t)LBM_Q * g.nxp;
+  g.rowlen = row + ((row * (int64_t)elem_size(cfg->storage)) % 1024 == 0 ? SEG : 0);
   g.by_nxs = make_div31((uint32_t)g.nxs);
   g.by_ny = make_div31((uint32_t)g.ny);
   g.flat = flat_grid(g.nx, g.ny, g.nz) ? 1 : 0;
   dim3 block, grid;
   step_launch_shape(g.nx, g.ny, g.nz, block, grid);
   g.by_bpr = make_div31(grid.x);
-  const bool chunks = elem_size(cfg->storage) >= 4;
+  const bool chunks = elem_size(cfg->storage) >= 4 && g.nxs > SEGS_PER_BLOCK;  // rows split across blocks
   g.blk_per_xcd = chunks ? (uint32_t)(((uint64_t)grid.x * grid.y * grid.z) / XCDS) : 0u;
   return g;
 }
