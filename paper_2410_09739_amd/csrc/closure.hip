@@ -88,7 +88,8 @@ struct ClosureArgs {
 // loaded into LDS once per block).  Register budget for 3 waves per SIMD
 // (MFMA accumulators in VGPRs, no spills): measured 10-15 % faster than the
 // unconstrained allocation at 2 waves per SIMD.
-template <int ST, bool WALLS, bool FORCE>
+// UH: every rate of orders 3-6 is 1 (the paper's runs; relax<..., UH = true>).
+template <int ST, bool WALLS, bool FORCE, bool UH>
 __global__ __launch_bounds__(256, 3) void k_stream_collide_closure(const typename Stor<ST>::S* __restrict__ src,
                                                                 typename Stor<ST>::S* __restrict__ dst,
                                                                 StepArgs<typename Stor<ST>::R> A, ClosureArgs C,
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(256, 3) void k_stream_collide_closure(const typenam
     mlp_wave(feat, nu, lw, xs);
     T ws[6], cs[6];
     closure_rates(nu, C.inv_w, ws, cs);
-    relax<T, FORCE>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
+    relax<T, FORCE, false, false, UH>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
     push<ST>(dst, A.g, x, y, z, v, A.step);
   }
 }
@@ -562,11 +563,13 @@ __global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ pa
 // ===========================================================================
 // host side
 template <int ST, bool WALLS, bool FORCE>
-static void launch_closure_kernel(lbm_ctx* c, int grid, const StepArgs<typename Stor<ST>::R>& A, const ClosureArgs& C) {
+static void launch_closure_kernel(lbm_ctx* c, int grid, const StepArgs<typename Stor<ST>::R>& A, const ClosureArgs& C,
+                                  bool uh) {
   using S = typename Stor<ST>::S;
   const S* src = (const S*)c->buf[c->cur];
   S* dst = (S*)c->buf[c->cur ^ 1];
-  k_stream_collide_closure<ST, WALLS, FORCE><<<grid, 256, 0, c->stream>>>(src, dst, A, C, c->closure);
+  if (uh) k_stream_collide_closure<ST, WALLS, FORCE, true><<<grid, 256, 0, c->stream>>>(src, dst, A, C, c->closure);
+  else k_stream_collide_closure<ST, WALLS, FORCE, false><<<grid, 256, 0, c->stream>>>(src, dst, A, C, c->closure);
 }
 
 template <typename T>
@@ -593,7 +596,7 @@ static int closure_steps(lbm_ctx* c, int64_t nsteps) {
   // every wavefront runs the same number of segments (sized on first use)
   if (!c->closure_grid) {
     int resident = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, (const void*)k_stream_collide_closure<ST, true, true>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, (const void*)k_stream_collide_closure<ST, true, true, false>,
                                                      256, 0) != hipSuccess || resident < 1) {
       resident = 1;
       (void)hipGetLastError();  // a failed query only shrinks the grid; no error to report later
@@ -608,15 +611,16 @@ static int closure_steps(lbm_ctx* c, int64_t nsteps) {
   const int grid = c->closure_grid;
   const bool walls = c->cfg.walls_y != 0;
   const bool force = c->cfg.force[0] != 0.0 || c->cfg.force[1] != 0.0 || c->cfg.force[2] != 0.0;
+  const bool uh = unit_rates_3_to_6(c);
   StepArgs<T> As = A;
   for (int64_t s = 0; s < nsteps; ++s) {
     As.step = (uint32_t)c->steps;
     if (walls) {
-      if (force) launch_closure_kernel<ST, true, true>(c, grid, As, C);
-      else launch_closure_kernel<ST, true, false>(c, grid, As, C);
+      if (force) launch_closure_kernel<ST, true, true>(c, grid, As, C, uh);
+      else launch_closure_kernel<ST, true, false>(c, grid, As, C, uh);
     } else {
-      if (force) launch_closure_kernel<ST, false, true>(c, grid, As, C);
-      else launch_closure_kernel<ST, false, false>(c, grid, As, C);
+      if (force) launch_closure_kernel<ST, false, true>(c, grid, As, C, uh);
+      else launch_closure_kernel<ST, false, false>(c, grid, As, C, uh);
     }
     LAUNCHCHK(c);
     c->cur ^= 1;

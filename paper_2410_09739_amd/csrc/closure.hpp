@@ -60,6 +60,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // are -F/2 at every node: no information, only FP32 rounding noise),
 // x_abc = (kappa'_abc - rho' E_abc) / rho * 3^((a+b+c)/2), in the paper's
 // moment order.
+// The factor 3^(order/2) / rho is formed once per order, so each feature takes
+// one multiply.
 template <typename T>
 __device__ __forceinline__ void features(const T (&v)[3][3][3], T rhop, T rho, float (&x)[NIN]) {
   constexpr int MM[NIN][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1},
@@ -67,6 +69,9 @@ __device__ __forceinline__ void features(const T (&v)[3][3][3], T rhop, T rho, f
                               {2, 0, 1}, {0, 2, 1}, {1, 1, 1}, {2, 2, 0}, {2, 0, 2}, {0, 2, 2}, {2, 1, 1},
                               {1, 2, 1}, {1, 1, 2}, {1, 2, 2}, {2, 1, 2}, {2, 2, 1}, {2, 2, 2}};
   const T ir = recip(rho);
+  T irn[7];
+#pragma unroll
+  for (int o = 2; o < 7; ++o) irn[o] = ir * T(order_norm(o));
   x[0] = (float)rhop;
   x[1] = x[2] = x[3] = 0.0f;
 #pragma unroll
@@ -75,7 +80,7 @@ __device__ __forceinline__ void features(const T (&v)[3][3][3], T rhop, T rho, f
     const double E = C1[a] * C1[b] * C1[c];
     const T kap = v[c][b][a];
     const T d = (E == 0.0) ? kap : kap - rhop * T(E);
-    x[k] = (float)(d * ir) * order_norm(a + b + c);
+    x[k] = (float)(d * irn[a + b + c]);
   }
 }
 

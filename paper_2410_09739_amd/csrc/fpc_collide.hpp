@@ -298,10 +298,20 @@ __host__ __device__ __forceinline__ void pre_collision(T (&v)[3][3][3], T Fx, T 
 // In storage units (SU) v and rhop carry UNIT, rho and u are plain: the rest
 // state's constants are taken times UNIT (thirdU, ninthU) and a product of two
 // moments is scaled by iru = 1 / (rho UNIT).
-template <typename T, bool FORCE, bool MAXWELL = false, bool SU = false>
+// UH (unit higher): every rate of orders 3-6 (omega_10..omega_26) is 1, as in
+// all runs of the paper (Sec. 4); R.w/c/h[10..26] are then not read.  A group
+// relaxed at rate 1 lands on its attractor plus half its source,
+// kappa~ = kappa + 1 (kappa^Mv - kappa) + (1 - 1/2) sigma, whatever its
+// pre-collision value, and since all members of a decomposition family share
+// the rate, each member does so on its own (t_abc = kappa^Mv_abc + sigma_abc/2).
+// The pre-collision moments of orders 3-5 still enter through the sources.
+// The second order (bulk rate included) stays general.  Equal to UH = false
+// with those rates up to rounding.
+template <typename T, bool FORCE, bool MAXWELL = false, bool SU = false, bool UH = false>
 __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& R, const T (&ws)[6],
                                                const T (&cs)[6], T Fx, T Fy, T Fz, T rhop, T rho, T ux,
                                                T uy, T uz) {
+  static_assert(!(UH && MAXWELL), "the unit-rate form takes the Markovian attractors");
   constexpr double U = Units<SU>::U;
   const T third = T(1.0 / 3.0), ninth = T(1.0 / 9.0);
   const T thirdU = T(U / 3.0), ninthU = T(U / 9.0);
@@ -326,7 +336,10 @@ __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& 
   T s220 = 0, s202 = 0, s022 = 0, s211 = 0, s121 = 0, s112 = 0;
   T s122 = 0, s212 = 0, s221 = 0, s222 = 0;
   if (FORCE) {
-    const T gx = Fx * ir, gy = Fy * ir, gz = Fz * ir;
+    // UH: orders 3-6 take half their source, so the sources of those orders are
+    // formed at once with g / 2 (an exact power-of-two factor); s100..s001 stay whole.
+    const T irs = UH ? T(0.5) * ir : ir;
+    const T gx = Fx * irs, gy = Fy * irs, gz = Fz * irs;
     const T K200 = thirdU + k200, K020 = thirdU + k020, K002 = thirdU + k002;
     const T K220 = ninthU + k220, K202 = ninthU + k202, K022 = ninthU + k022;
     s100 = T(U) * Fx;
@@ -368,54 +381,82 @@ __host__ __device__ __forceinline__ void relax(T (&v)[3][3][3], const Rates<T>& 
   const T t020 = third * (t2s1 - T(2) * t2d1 + t2d2);
   const T t002 = third * (t2s1 + t2d1 - T(2) * t2d2);
 
-  // ---- order 3: attractors 0.
-  const T t3s1 = R.c[10] * (k120 + k102) + R.h[10] * (s120 + s102);
-  const T t3m1 = R.c[11] * (k120 - k102) + R.h[11] * (s120 - s102);
-  const T t3s2 = R.c[12] * (k210 + k012) + R.h[12] * (s210 + s012);
-  const T t3m2 = R.c[13] * (k210 - k012) + R.h[13] * (s210 - s012);
-  const T t3s3 = R.c[14] * (k201 + k021) + R.h[14] * (s201 + s021);
-  const T t3m3 = R.c[15] * (k201 - k021) + R.h[15] * (s201 - s021);
-  const T t111 = R.c[16] * k111 + R.h[16] * s111;
-  const T t120 = T(0.5) * (t3s1 + t3m1), t102 = T(0.5) * (t3s1 - t3m1);
-  const T t210 = T(0.5) * (t3s2 + t3m2), t012 = T(0.5) * (t3s2 - t3m2);
-  const T t201 = T(0.5) * (t3s3 + t3m3), t021 = T(0.5) * (t3s3 - t3m3);
+  T t120, t102, t210, t012, t201, t021, t111, t220, t202, t022, t211, t121, t112, t122, t212, t221, t222;
+  if constexpr (UH) {
+    // ---- orders 3-6 at rate 1: attractor + sigma / 2 (the s here are already halved)
+    (void)R;
+    t120 = s120; t102 = s102; t210 = s210; t012 = s012; t201 = s201; t021 = s021; t111 = s111;
+    // order 4 from post-collision order 2
+    const T A2 = thirdU + t200, B2 = thirdU + t020, C2 = thirdU + t002;
+    t220 = ((t200 + t020) * thirdU + t200 * t020 + T(2) * t110 * t110 - ninthU * rhop) * iru + s220;
+    t202 = ((t200 + t002) * thirdU + t200 * t002 + T(2) * t101 * t101 - ninthU * rhop) * iru + s202;
+    t022 = ((t020 + t002) * thirdU + t020 * t002 + T(2) * t011 * t011 - ninthU * rhop) * iru + s022;
+    t211 = (A2 * t011 + T(2) * t110 * t101) * iru + s211;
+    t121 = (B2 * t101 + T(2) * t110 * t011) * iru + s121;
+    t112 = (C2 * t110 + T(2) * t011 * t101) * iru + s112;
+    // order 5 from post-collision orders 2 and 3
+    const T f5 = T(0.4) * iru;  // 2 / (5 rho)
+    t122 = f5 * (B2 * t102 + C2 * t120 + T(4) * t011 * t111 + T(2) * (t101 * t021 + t110 * t012)) + s122;
+    t212 = f5 * (A2 * t012 + C2 * t210 + T(4) * t101 * t111 + T(2) * (t110 * t102 + t011 * t201)) + s212;
+    t221 = f5 * (A2 * t021 + B2 * t201 + T(4) * t110 * t111 + T(2) * (t011 * t210 + t101 * t120)) + s221;
+    // order 6 from post-collision orders 2 and 4
+    t222 = ((t200 + t020 + t002) * ninthU + (t022 + t202 + t220) * thirdU + t200 * t022 + t020 * t202 +
+            t002 * t220 + T(4) * (t110 * t112 + t101 * t121 + t011 * t211)) *
+               (third * iru) -
+           rhop * (T(1.0 / 27.0) * ir) + s222;
+    (void)k120; (void)k102; (void)k210; (void)k012; (void)k201; (void)k021; (void)k111;
+    (void)k220; (void)k202; (void)k022; (void)k211; (void)k121; (void)k112;
+    (void)k122; (void)k212; (void)k221; (void)k222;
+  } else {
+    // ---- order 3: attractors 0.
+    const T t3s1 = R.c[10] * (k120 + k102) + R.h[10] * (s120 + s102);
+    const T t3m1 = R.c[11] * (k120 - k102) + R.h[11] * (s120 - s102);
+    const T t3s2 = R.c[12] * (k210 + k012) + R.h[12] * (s210 + s012);
+    const T t3m2 = R.c[13] * (k210 - k012) + R.h[13] * (s210 - s012);
+    const T t3s3 = R.c[14] * (k201 + k021) + R.h[14] * (s201 + s021);
+    const T t3m3 = R.c[15] * (k201 - k021) + R.h[15] * (s201 - s021);
+    t111 = R.c[16] * k111 + R.h[16] * s111;
+    t120 = T(0.5) * (t3s1 + t3m1); t102 = T(0.5) * (t3s1 - t3m1);
+    t210 = T(0.5) * (t3s2 + t3m2); t012 = T(0.5) * (t3s2 - t3m2);
+    t201 = T(0.5) * (t3s3 + t3m3); t021 = T(0.5) * (t3s3 - t3m3);
 
-  // ---- order 4: attractors from post-collision order 2 (primed form of
-  // (K200 K020 + 2 K110^2)/rho - 1/9 etc.).
-  // (Maxwellian model: rho' c_s^4 and 0, the primed discrete Maxwellian.)
-  const T m220 = MAXWELL ? ninth * rhop : ((t200 + t020) * thirdU + t200 * t020 + T(2) * t110 * t110 - ninthU * rhop) * iru;
-  const T m202 = MAXWELL ? ninth * rhop : ((t200 + t002) * thirdU + t200 * t002 + T(2) * t101 * t101 - ninthU * rhop) * iru;
-  const T m022 = MAXWELL ? ninth * rhop : ((t020 + t002) * thirdU + t020 * t002 + T(2) * t011 * t011 - ninthU * rhop) * iru;
-  const T A2 = thirdU + t200, B2 = thirdU + t020, C2 = thirdU + t002;  // full post-collision order 2
-  const T m211 = MAXWELL ? T(0) : (A2 * t011 + T(2) * t110 * t101) * iru;
-  const T m121 = MAXWELL ? T(0) : (B2 * t101 + T(2) * t110 * t011) * iru;
-  const T m112 = MAXWELL ? T(0) : (C2 * t110 + T(2) * t011 * t101) * iru;
-  const T c4s1 = k220 + k202 + k022, c4d1 = k220 + k202 - k022, c4d2 = k220 - k202;
-  const T t4s1 = c4s1 + R.w[17] * ((m220 + m202 + m022) - c4s1) + R.h[17] * (s220 + s202 + s022);
-  const T t4d1 = c4d1 + R.w[18] * ((m220 + m202 - m022) - c4d1) + R.h[18] * (s220 + s202 - s022);
-  const T t4d2 = c4d2 + R.w[19] * ((m220 - m202) - c4d2) + R.h[19] * (s220 - s202);
-  const T t211 = k211 + R.w[20] * (m211 - k211) + R.h[20] * s211;
-  const T t121 = k121 + R.w[21] * (m121 - k121) + R.h[21] * s121;
-  const T t112 = k112 + R.w[22] * (m112 - k112) + R.h[22] * s112;
-  const T t220 = T(0.25) * (t4s1 + t4d1 + T(2) * t4d2);
-  const T t202 = T(0.25) * (t4s1 + t4d1 - T(2) * t4d2);
-  const T t022 = T(0.5) * (t4s1 - t4d1);
+    // ---- order 4: attractors from post-collision order 2 (primed form of
+    // (K200 K020 + 2 K110^2)/rho - 1/9 etc.).
+    // (Maxwellian model: rho' c_s^4 and 0, the primed discrete Maxwellian.)
+    const T m220 = MAXWELL ? ninth * rhop : ((t200 + t020) * thirdU + t200 * t020 + T(2) * t110 * t110 - ninthU * rhop) * iru;
+    const T m202 = MAXWELL ? ninth * rhop : ((t200 + t002) * thirdU + t200 * t002 + T(2) * t101 * t101 - ninthU * rhop) * iru;
+    const T m022 = MAXWELL ? ninth * rhop : ((t020 + t002) * thirdU + t020 * t002 + T(2) * t011 * t011 - ninthU * rhop) * iru;
+    const T A2 = thirdU + t200, B2 = thirdU + t020, C2 = thirdU + t002;  // full post-collision order 2
+    const T m211 = MAXWELL ? T(0) : (A2 * t011 + T(2) * t110 * t101) * iru;
+    const T m121 = MAXWELL ? T(0) : (B2 * t101 + T(2) * t110 * t011) * iru;
+    const T m112 = MAXWELL ? T(0) : (C2 * t110 + T(2) * t011 * t101) * iru;
+    const T c4s1 = k220 + k202 + k022, c4d1 = k220 + k202 - k022, c4d2 = k220 - k202;
+    const T t4s1 = c4s1 + R.w[17] * ((m220 + m202 + m022) - c4s1) + R.h[17] * (s220 + s202 + s022);
+    const T t4d1 = c4d1 + R.w[18] * ((m220 + m202 - m022) - c4d1) + R.h[18] * (s220 + s202 - s022);
+    const T t4d2 = c4d2 + R.w[19] * ((m220 - m202) - c4d2) + R.h[19] * (s220 - s202);
+    t211 = k211 + R.w[20] * (m211 - k211) + R.h[20] * s211;
+    t121 = k121 + R.w[21] * (m121 - k121) + R.h[21] * s121;
+    t112 = k112 + R.w[22] * (m112 - k112) + R.h[22] * s112;
+    t220 = T(0.25) * (t4s1 + t4d1 + T(2) * t4d2);
+    t202 = T(0.25) * (t4s1 + t4d1 - T(2) * t4d2);
+    t022 = T(0.5) * (t4s1 - t4d1);
 
-  // ---- order 5: attractors from post-collision orders 2 and 3.
-  const T f5 = T(0.4) * iru;  // 2 / (5 rho)
-  const T m122 = MAXWELL ? T(0) : f5 * (B2 * t102 + C2 * t120 + T(4) * t011 * t111 + T(2) * (t101 * t021 + t110 * t012));
-  const T m212 = MAXWELL ? T(0) : f5 * (A2 * t012 + C2 * t210 + T(4) * t101 * t111 + T(2) * (t110 * t102 + t011 * t201));
-  const T m221 = MAXWELL ? T(0) : f5 * (A2 * t021 + B2 * t201 + T(4) * t110 * t111 + T(2) * (t011 * t210 + t101 * t120));
-  const T t122 = k122 + R.w[23] * (m122 - k122) + R.h[23] * s122;
-  const T t212 = k212 + R.w[24] * (m212 - k212) + R.h[24] * s212;
-  const T t221 = k221 + R.w[25] * (m221 - k221) + R.h[25] * s221;
+    // ---- order 5: attractors from post-collision orders 2 and 3.
+    const T f5 = T(0.4) * iru;  // 2 / (5 rho)
+    const T m122 = MAXWELL ? T(0) : f5 * (B2 * t102 + C2 * t120 + T(4) * t011 * t111 + T(2) * (t101 * t021 + t110 * t012));
+    const T m212 = MAXWELL ? T(0) : f5 * (A2 * t012 + C2 * t210 + T(4) * t101 * t111 + T(2) * (t110 * t102 + t011 * t201));
+    const T m221 = MAXWELL ? T(0) : f5 * (A2 * t021 + B2 * t201 + T(4) * t110 * t111 + T(2) * (t011 * t210 + t101 * t120));
+    t122 = k122 + R.w[23] * (m122 - k122) + R.h[23] * s122;
+    t212 = k212 + R.w[24] * (m212 - k212) + R.h[24] * s212;
+    t221 = k221 + R.w[25] * (m221 - k221) + R.h[25] * s221;
 
-  // ---- order 6: attractor from post-collision orders 2 and 4 (primed form).
-  const T m222 = MAXWELL ? rhop * T(1.0 / 27.0) : ((t200 + t020 + t002) * ninthU + (t022 + t202 + t220) * thirdU + t200 * t022 + t020 * t202 +
-                  t002 * t220 + T(4) * (t110 * t112 + t101 * t121 + t011 * t211)) *
-                     (third * iru) -
-                 rhop * (T(1.0 / 27.0) * ir);
-  const T t222 = k222 + R.w[26] * (m222 - k222) + R.h[26] * s222;
+    // ---- order 6: attractor from post-collision orders 2 and 4 (primed form).
+    const T m222 = MAXWELL ? rhop * T(1.0 / 27.0) : ((t200 + t020 + t002) * ninthU + (t022 + t202 + t220) * thirdU + t200 * t022 + t020 * t202 +
+                    t002 * t220 + T(4) * (t110 * t112 + t101 * t121 + t011 * t211)) *
+                       (third * iru) -
+                   rhop * (T(1.0 / 27.0) * ir);
+    t222 = k222 + R.w[26] * (m222 - k222) + R.h[26] * s222;
+  }
 
   v[0][0][0] = rhop;
   v[0][0][1] = t100; v[0][1][0] = t010; v[1][0][0] = t001;
@@ -563,14 +604,15 @@ __host__ __device__ __forceinline__ void relax_unit_higher(T (&v)[3][3][3], cons
 
 // Whole collision of one node (Appendix D Steps 7, 1-5): deviation cube in,
 // post-collision deviations (times 2^inv_shift) out; in storage units (SU) the
-// cube comes in as stored numbers and goes out times UNIT.
-template <typename T, bool FORCE, bool MAXWELL = false, bool SU = false>
+// cube comes in as stored numbers and goes out times UNIT.  UH: rates of
+// orders 3-6 equal to 1 (see relax).
+template <typename T, bool FORCE, bool MAXWELL = false, bool SU = false, bool UH = false>
 __host__ __device__ __forceinline__ void collide(T (&v)[3][3][3], const Rates<T>& R, const T (&ws)[6],
                                                  const T (&cs)[6], T Fx, T Fy, T Fz, T& rho, T& ux, T& uy,
                                                  T& uz) {
   T rhop;
   pre_collision<T, FORCE, SU>(v, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
-  relax<T, FORCE, MAXWELL, SU>(v, R, ws, cs, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
+  relax<T, FORCE, MAXWELL, SU, UH>(v, R, ws, cs, Fx, Fy, Fz, rhop, rho, ux, uy, uz);
 }
 
 // Whole collision with bulk and higher rates 1 and no force (see

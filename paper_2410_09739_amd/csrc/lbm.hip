@@ -492,15 +492,18 @@ extern "C" int lbm_init(lbm_ctx* c, const double* rho, const double* u) {
   return LBM_OK;
 }
 
-// The rates of the paper's runs: bulk (omega_7) and every rate of orders 3-6
-// exactly 1.  With no force the step kernel then takes the collision that
-// needs only the second-order moments (relax_unit_higher).
-static bool unit_higher_rates(const lbm_ctx* c) {
-  if (c->omega[7] != 1.0) return false;
+// The rates of the paper's runs: every rate of orders 3-6 exactly 1
+// (unit_rates_3_to_6), and the bulk rate omega_7 as well (unit_higher_rates).
+// With no force and the bulk rate 1 the step kernel takes the collision that
+// needs only the second-order moments (relax_unit_higher); with a force (or
+// another bulk rate) the one that drops the pre-collision values of orders 3-6
+// from their own relaxation (relax<..., UH = true>).
+bool unit_rates_3_to_6(const lbm_ctx* c) {
   for (int j = 10; j < LBM_Q; ++j)
     if (c->omega[j] != 1.0) return false;
   return true;
 }
+static bool unit_higher_rates(const lbm_ctx* c) { return c->omega[7] == 1.0 && unit_rates_3_to_6(c); }
 
 template <int ST>
 static int launch_steps(lbm_ctx* c, int64_t nsteps) {
@@ -526,12 +529,16 @@ static int launch_steps(lbm_ctx* c, int64_t nsteps) {
       {{k_stream_collide<ST, 0, false, true>, k_stream_collide<ST, 0, true, true>},
        {k_stream_collide<ST, 1, false, true>, k_stream_collide<ST, 1, true, true>},
        {k_stream_collide<ST, 2, false, true>, k_stream_collide<ST, 2, true, true>}}};
-  static const KFn unit_higher[3] = {k_stream_collide<ST, 0, false, false, true>,
-                                     k_stream_collide<ST, 1, false, false, true>,
-                                     k_stream_collide<ST, 2, false, false, true>};
+  static const KFn second_only[3] = {k_stream_collide<ST, 0, false, false, COLL_SECOND_ONLY>,
+                                     k_stream_collide<ST, 1, false, false, COLL_SECOND_ONLY>,
+                                     k_stream_collide<ST, 2, false, false, COLL_SECOND_ONLY>};
+  static const KFn unit_forced[3] = {k_stream_collide<ST, 0, true, false, COLL_UNIT_HIGHER>,
+                                     k_stream_collide<ST, 1, true, false, COLL_UNIT_HIGHER>,
+                                     k_stream_collide<ST, 2, true, false, COLL_UNIT_HIGHER>};
   const bool maxwell = c->cfg.attractor == LBM_ATTRACTOR_MAXWELL;
-  const KFn kern = (!force && !maxwell && unit_higher_rates(c)) ? unit_higher[bc_kind(c)]
-                                                                 : table[maxwell][bc_kind(c)][force];
+  KFn kern = table[maxwell][bc_kind(c)][force];
+  if (!maxwell && !force && unit_higher_rates(c)) kern = second_only[bc_kind(c)];
+  if (!maxwell && force && unit_rates_3_to_6(c)) kern = unit_forced[bc_kind(c)];
   for (int64_t s = 0; s < nsteps; ++s) {
     const S* src = (const S*)c->buf[c->cur];
     S* dst = (S*)c->buf[c->cur ^ 1];

@@ -67,6 +67,8 @@ inline int wall_mask(const lbm_ctx* c) {
 int alloc_scratch(lbm_ctx* c);
 // closure.hip: enqueue n steps of the stream-collide kernel with the fused closure
 int launch_closure_steps(lbm_ctx* c, int64_t nsteps);
+// lbm.hip: every rate of orders 3-6 is exactly 1 (the paper's runs)
+bool unit_rates_3_to_6(const lbm_ctx* c);
 
 #define HIPCHK(ctx, call)                                                                  \
   do {                                                                                     \

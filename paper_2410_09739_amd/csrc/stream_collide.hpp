@@ -10,14 +10,23 @@
 // row (y, z uniform; wave_segment).  BC: 0 periodic, 1 walls across y (the
 // channel), 2 walls on any faces, a moving lid, the symmetry plane and LES
 // (StepArgs::box).  FORCE: a body force is applied.  MAXWELL: the comparison
-// model's attractors.  UNIT_HIGHER: the rates of the paper's runs (bulk and
-// orders 3-6 equal to 1) with no force and the Markovian attractors; the
-// collision then needs only the second-order moments (relax_unit_higher).
-template <int ST, int BC, bool FORCE, bool MAXWELL, bool UNIT_HIGHER = false>
+// model's attractors.  COLL picks the form of the collision:
+//   COLL_GENERAL: any rates;
+//   COLL_SECOND_ONLY: the rates of the paper's runs (bulk and orders 3-6 equal
+//     to 1) with no force and the Markovian attractors; the collision then
+//     needs only the second-order moments (relax_unit_higher);
+//   COLL_UNIT_HIGHER: orders 3-6 at rate 1 with the Markovian attractors, any
+//     second-order rates, with or without a force (relax<..., UH = true>):
+//     the paper's rates under a body force.
+enum : int { COLL_GENERAL = 0, COLL_SECOND_ONLY = 1, COLL_UNIT_HIGHER = 2 };
+
+template <int ST, int BC, bool FORCE, bool MAXWELL, int COLL = COLL_GENERAL>
 __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>::S* __restrict__ src,
                                                         typename Stor<ST>::S* __restrict__ dst,
                                                         StepArgs<typename Stor<ST>::R> A) {
+  constexpr bool UNIT_HIGHER = COLL == COLL_SECOND_ONLY;
   static_assert(!UNIT_HIGHER || (!FORCE && !MAXWELL), "the unit-rate collision has no force and FPC attractors");
+  static_assert(COLL != COLL_UNIT_HIGHER || !MAXWELL, "the unit-rate form takes the Markovian attractors");
   using T = typename Stor<ST>::R;
   // FP16/BF16: arithmetic on the stored numbers (storage units), which drops
   // the multiply of every loaded value by its scale.  Not in the periodic
@@ -45,7 +54,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename Stor<ST>:
       const T k2[6] = {v[0][0][2], v[0][2][0], v[2][0][0], v[0][1][1], v[1][0][1], v[1][1][0]};
       les_rates<SU>(k2, rho, A.box, A.r, y, A.g.ny, ws, cs);
     }
-    relax<T, FORCE, MAXWELL, SU>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy, uz);
+    relax<T, FORCE, MAXWELL, SU, COLL == COLL_UNIT_HIGHER>(v, A.r, ws, cs, A.F[0], A.F[1], A.F[2], rhop, rho, ux, uy,
+                                                          uz);
   }
   push<ST, SU>(dst, A.g, x, y, z, v, A.step);
 }

@@ -108,6 +108,58 @@ extern "C" void host_collide_unit_units_f32(const float* dev, const double* omeg
   run_unit_dev<true>(dev, omega, out);
 }
 
+// The collision the step kernels take when every rate of orders 3-6 is 1 and
+// there is a body force (or a bulk rate other than 1): relax<..., UH = true>,
+// which drops the pre-collision values of orders 3-6 from their relaxation.
+template <typename T>
+static void run_uh(const double* f, const double* omega, const double* F, double* out) {
+  T v[3][3][3];
+  for (int a = 0; a < Q; ++a) v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] = (T)(f[a] - weight(a));
+  Rates<T> R;
+  for (int j = 0; j < Q; ++j) {
+    R.w[j] = (T)omega[j];
+    R.c[j] = (T)(1.0 - omega[j]);
+    R.h[j] = (T)(1.0 - 0.5 * omega[j]);
+  }
+  const T ws[6] = {R.w[4], R.w[5], R.w[6], R.w[7], R.w[8], R.w[9]};
+  const T cs[6] = {R.c[4], R.c[5], R.c[6], R.c[7], R.c[8], R.c[9]};
+  T rho, ux, uy, uz;
+  if (F[0] != 0.0 || F[1] != 0.0 || F[2] != 0.0)
+    collide<T, true, false, false, true>(v, R, ws, cs, (T)F[0], (T)F[1], (T)F[2], rho, ux, uy, uz);
+  else
+    collide<T, false, false, false, true>(v, R, ws, cs, T(0), T(0), T(0), rho, ux, uy, uz);
+  for (int a = 0; a < Q; ++a) out[a] = weight(a) + (double)(v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] * (T)inv_factor(a));
+}
+extern "C" void host_collide_uh_f64(const double* f, const double* omega, const double* F, double* out) {
+  run_uh<double>(f, omega, F, out);
+}
+extern "C" void host_collide_uh_f32(const double* f, const double* omega, const double* F, double* out) {
+  run_uh<float>(f, omega, F, out);
+}
+// the same in storage units and on plain deviations (FP32, with a force), for a bitwise comparison
+template <bool SU>
+static void run_uh_dev(const float* dev, const double* omega, const double* F, float* out) {
+  float v[3][3][3];
+  for (int a = 0; a < Q; ++a) v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] = SU ? dev[a] * dev_scale(a) : dev[a];
+  Rates<float> R;
+  for (int j = 0; j < Q; ++j) {
+    R.w[j] = (float)omega[j];
+    R.c[j] = (float)(1.0 - omega[j]);
+    R.h[j] = (float)(1.0 - 0.5 * omega[j]);
+  }
+  const float ws[6] = {R.w[4], R.w[5], R.w[6], R.w[7], R.w[8], R.w[9]};
+  const float cs[6] = {R.c[4], R.c[5], R.c[6], R.c[7], R.c[8], R.c[9]};
+  float rho, ux, uy, uz;
+  collide<float, true, false, SU, true>(v, R, ws, cs, (float)F[0], (float)F[1], (float)F[2], rho, ux, uy, uz);
+  for (int a = 0; a < Q; ++a) out[a] = v[EZ[a] + 1][EY[a] + 1][EX[a] + 1] * (float)(1.0 / Units<SU>::U);
+}
+extern "C" void host_collide_uh_dev_f32(const float* dev, const double* omega, const double* F, float* out) {
+  run_uh_dev<false>(dev, omega, F, out);
+}
+extern "C" void host_collide_uh_units_f32(const float* dev, const double* omega, const double* F, float* out) {
+  run_uh_dev<true>(dev, omega, F, out);
+}
+
 // f^eq(rho, u) through the kernels' inverse sweeps (what lbm_init stores)
 extern "C" void host_feq_f64(double rho, const double* u, double* out) {
   double v[3][3][3];

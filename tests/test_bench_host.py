@@ -45,7 +45,7 @@ def test_kernel_trace_summary_covers_the_timed_kernel():
     text = open(TRACE).read()
     assert "rocprofv3 --kernel-trace --stats" in text
     # FP32, periodic, no force, unit higher-order rates: the benchmark's kernel
-    assert "k_stream_collide<1, 0, false, false, true>" in text
+    assert "k_stream_collide<1, 0, false, false, 1>" in text
     assert "512x512x512" in text
 
 

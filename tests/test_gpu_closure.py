@@ -33,6 +33,26 @@ def _params(seed, bias=0.1):
     return C.pack(W1, b1, W2, b2, W3, b3).astype(np.float32).astype(np.float64)
 
 
+def _bf16_alternatives(X, xtol, max_flips=4):
+    """Nodes with features within xtol of a bf16 rounding boundary, and for each
+    the feature vectors with every combination of those features rounded to the
+    other side (at most 2^max_flips per node)."""
+    q = C.round_bf16(X)
+    lo, hi = C.round_bf16(X - xtol), C.round_bf16(X + xtol)
+    out = {}
+    for i in np.flatnonzero(np.any((lo != q) | (hi != q), axis=1)):
+        cols = np.flatnonzero((lo[i] != q[i]) | (hi[i] != q[i]))[:max_flips]
+        cands = []
+        for m in range(1, 1 << len(cols)):
+            x = q[i].copy()
+            for b, k in enumerate(cols):
+                if m >> b & 1:
+                    x[k] = lo[i, k] if lo[i, k] != q[i, k] else hi[i, k]
+            cands.append(x)
+        out[int(i)] = cands
+    return out
+
+
 def _dev(a):
     """Device copy of a host array; the caller keeps the tensor alive while the
     library uses its pointer (the library runs on its own stream)."""
@@ -260,19 +280,39 @@ def test_fused_closure_step_matches_oracle(storage, tol, shape):
     X = C.features(kap, rho).reshape(-1, 27)
     nu_t = C.forward_bf16(p, X)
     om = O.omega_table(nu)
-    wf = C.closure_rates(nu_t, om)
     ff = f.reshape(27, -1)
-    ref = np.zeros_like(ff)
-    for i in range(ff.shape[1]):
+
+    def collide_node_with(i, nut):
         w = om.copy()
-        w[4:10] = wf[i]
-        ref[:, i] = O.collide_node(ff[:, i], w, F)
+        w[4:10] = C.closure_rates(nut[None], om)[0]
+        return O.collide_node(ff[:, i], w, F)
+
+    ref = np.stack([collide_node_with(i, nu_t[i]) for i in range(ff.shape[1])], axis=1)
     # 16-bit storage: one unit in the last place of the stored deviation on top
     # (the stored value is rounded once, stochastically, after the collision)
     ulp = {"f16dev": 2.0 ** -10, "bf16dev": 2.0 ** -7}.get(storage, 0.0)
     bound = tol * W_ALPHA[:, None] + ulp * np.abs(ref - W_ALPHA[:, None]).max()
     err = np.abs(got.reshape(27, -1) - ref)
-    assert np.all(err <= bound), float((err / bound).max())
+    ok = np.all(err <= bound, axis=0)
+    # A feature that lies next to a bf16 rounding boundary may be rounded the
+    # other way by the kernel, whose features carry the rounding of their own
+    # arithmetic: either rounding is then a correct input to the network, and
+    # at such nodes the step must match the oracle's with one of them.  "Next
+    # to": within two FP32 units in the last place (the fp32 value itself may
+    # sit on a bf16 tie), or, for the FP32 arithmetic of the reduced forms,
+    # within 1e-7 of the feature's range (FP32 moments of order-0.1 values).
+    eps = 1e-13 if storage == "f64" else 1e-7
+    xtol = np.maximum(eps * np.abs(X).max(0), 2.0 * np.spacing(np.abs(X).astype(np.float32)))
+    alts = _bf16_alternatives(X, np.where(X == 0.0, 0.0, xtol))
+    g27 = got.reshape(27, -1)
+    for i in np.flatnonzero(~ok):
+        for Xi in alts.get(i, []):
+            r = collide_node_with(i, C.forward_bf16(p, Xi[None])[0])
+            if np.all(np.abs(g27[:, i] - r) <= bound[:, 0]):
+                ok[i] = True
+                break
+    assert np.all(ok), (np.flatnonzero(~ok)[:10], float((err / bound).max()))
+    assert len(alts) <= 0.05 * X.shape[0]  # near-boundary features are rare (measured: 0.2-2.6 %)
     assert np.any(np.clip(nu_t, 0, None) > 1e-3)  # the closure was active
 
 

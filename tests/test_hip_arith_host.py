@@ -31,6 +31,10 @@ def host():
         getattr(lib, n).argtypes = [_dp, _dp, _dp]
     for n in ("host_collide_unit_dev_f32", "host_collide_unit_units_f32"):
         getattr(lib, n).argtypes = [_fp, _dp, _fp]
+    for n in ("host_collide_uh_f64", "host_collide_uh_f32"):
+        getattr(lib, n).argtypes = [_dp, _dp, _dp, _dp]
+    for n in ("host_collide_uh_dev_f32", "host_collide_uh_units_f32"):
+        getattr(lib, n).argtypes = [_fp, _dp, _dp, _fp]
     lib.host_launch_cover.argtypes = [ctypes.c_int] * 4 + [ctypes.POINTER(ctypes.c_int),
                                                            ctypes.POINTER(ctypes.c_longlong)]
     lib.host_launch_cover.restype = ctypes.c_longlong
@@ -149,6 +153,53 @@ def test_unit_rate_collision_in_storage_units_is_bitwise_the_deviation_one(host,
     for fn in (host.host_collide_unit_dev_f32, host.host_collide_unit_units_f32):
         o = np.zeros(27, dtype=np.float32)
         fn(dev.ctypes.data_as(fp), om.ctypes.data_as(_dp), o.ctypes.data_as(fp))
+        outs.append(o)
+    assert np.all(np.isfinite(outs[0]))
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_host_unit_higher_collision_with_force_matches_oracle(host, seed):
+    """The collision the step and closure kernels take when every rate of
+    orders 3-6 is 1 (the paper's runs) under a body force, or with a bulk rate
+    other than 1: each moment of orders 3-6 lands on its attractor plus half
+    its source, without its pre-collision value.  It must equal the oracle's
+    full Appendix D collision to the bounds of the general path, for forces up
+    to 1e-3, bulk rates 0.5-1.9 and shear viscosities 1e-5-0.3, and the general
+    path (every moment relaxed at rate 1) must agree with it."""
+    rng = np.random.default_rng(1200 + seed)
+    u = 0.15 * rng.uniform(-1, 1, 3)
+    f = O.feq(1 + 0.08 * rng.uniform(-1, 1), u) * W.random_factors(27, seed + 90, 0.3)
+    om = O.omega_table(10 ** rng.uniform(-5, -0.5), omega_bulk=(1.0 if seed % 4 == 0 else rng.uniform(0.5, 1.9)))
+    assert np.all(om[10:] == 1.0)
+    F = 10 ** rng.uniform(-7, -3) * rng.uniform(-1, 1, 3) if seed % 4 != 1 else np.zeros(3)
+    ref = O.collide_node(f, om, F)
+    got = _call(host.host_collide_uh_f64, f, om, F)
+    err = np.max(np.abs(got - ref) / np.maximum(np.abs(ref), WA))
+    assert err <= 1e-13, err
+    got32 = _call(host.host_collide_uh_f32, f, om, F)
+    assert np.all(np.abs(got32 - ref) <= 4e-7 * WA), np.max(np.abs(got32 - ref) / WA)
+    gen = _call(host.host_collide_f64, f, om, F)
+    assert np.max(np.abs(gen - got) / np.maximum(np.abs(ref), WA)) <= 1e-13
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_unit_higher_collision_in_storage_units_is_bitwise_the_deviation_one(host, seed):
+    """The storage-unit form of the unit-higher collision with a force (the
+    16-bit kernels' arithmetic) is bitwise the FP32 arithmetic on plain
+    deviations, for deviations from 1e-9 w to w."""
+    fp = ctypes.POINTER(ctypes.c_float)
+    rng = np.random.default_rng(1300 + seed)
+    u = 0.1 * rng.uniform(-1, 1, 3)
+    f = O.feq(1 + 0.05 * rng.uniform(-1, 1), u) * W.random_factors(27, seed + 110, 0.2)
+    amp = 10.0 ** rng.uniform(-9, 0)
+    dev = ((f - WA) * amp).astype(np.float32)
+    om = np.ascontiguousarray(O.omega_table(10 ** rng.uniform(-5, -0.5), omega_bulk=rng.uniform(0.5, 1.9)))
+    F = np.ascontiguousarray(1e-4 * rng.uniform(-1, 1, 3) * amp)
+    outs = []
+    for fn in (host.host_collide_uh_dev_f32, host.host_collide_uh_units_f32):
+        o = np.zeros(27, dtype=np.float32)
+        fn(dev.ctypes.data_as(fp), om.ctypes.data_as(_dp), F.ctypes.data_as(_dp), o.ctypes.data_as(fp))
         outs.append(o)
     assert np.all(np.isfinite(outs[0]))
     assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
