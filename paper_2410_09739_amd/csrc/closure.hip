@@ -66,12 +66,21 @@ static void pack_params(const float* p, std::vector<char>& out) {
 
 // ===========================================================================
 // kernels
+// 1 / x for the per-node rates: FP32 takes the hardware reciprocal alone
+// (within one unit in the last place: a relative error below 1e-7 in a node's
+// rate, far inside the network's own), FP64 divides.
+template <typename T>
+__device__ __forceinline__ T rate_recip(T x) {
+  if constexpr (sizeof(T) == sizeof(float)) return __builtin_amdgcn_rcpf(x);
+  else return T(1) / x;
+}
+
 template <typename T>
 __device__ __forceinline__ void closure_rates(const float (&nu)[NOUT], const float (&inv_w)[6], T (&ws)[6], T (&cs)[6]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const float nt = fminf(fmaxf(nu[k], 0.0f), 1.0f / 3.0f);  // NaN -> 0
-    const T w = recip(T(inv_w[k]) + T(3) * T(nt));
+    const T w = rate_recip(T(inv_w[k]) + T(3) * T(nt));
     ws[k] = w;
     cs[k] = T(1) - w;
   }

@@ -61,14 +61,15 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // x_abc = (kappa'_abc - rho' E_abc) / rho * 3^((a+b+c)/2), in the paper's
 // moment order.
 // The factor 3^(order/2) / rho is formed once per order, so each feature takes
-// one multiply.
+// one multiply; 1 / rho is the collision's own (recip_rho), computed once.
 template <typename T>
 __device__ __forceinline__ void features(const T (&v)[3][3][3], T rhop, T rho, float (&x)[NIN]) {
   constexpr int MM[NIN][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1},
                               {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 2, 0}, {1, 0, 2}, {2, 1, 0}, {0, 1, 2},
                               {2, 0, 1}, {0, 2, 1}, {1, 1, 1}, {2, 2, 0}, {2, 0, 2}, {0, 2, 2}, {2, 1, 1},
                               {1, 2, 1}, {1, 1, 2}, {1, 2, 2}, {2, 1, 2}, {2, 2, 1}, {2, 2, 2}};
-  const T ir = recip(rho);
+  (void)rho;
+  const T ir = recip_rho<T>(rhop);
   T irn[7];
 #pragma unroll
   for (int o = 2; o < 7; ++o) irn[o] = ir * T(order_norm(o));

@@ -88,9 +88,12 @@ def test_f64_matches_oracle_other_rate_sets(mode):
 
 # The step kernel takes a collision that computes only the second-order
 # moments when the bulk rate and every rate of orders 3-6 are 1 and there is no
-# force (the paper's rate set; relax_unit_higher), and the general one
-# otherwise.  Both against the oracle on every boundary kind: periodic, y walls,
-# walls on all faces with a moving lid, the half channel with LES.
+# force (the paper's rate set; relax_unit_higher); one that drops the
+# pre-collision values of orders 3-6 from their relaxation when those rates are
+# 1 under a force or with another bulk rate (relax with UH); and the general
+# one otherwise.  All three against the oracle on every boundary kind:
+# periodic, y walls, walls on all faces with a moving lid, the half channel
+# with LES.
 UNIT_CASES = {
     "periodic": dict(shape=(70, 9, 6), walls=0, lid=None, les=None, cfg={}),
     "y walls": dict(shape=(13, 10, 9), walls="y", lid=None, les=None, cfg=dict(walls_y=True)),
@@ -101,12 +104,14 @@ UNIT_CASES = {
 }
 
 
+@pytest.mark.parametrize("force", [(0.0, 0.0, 0.0), (2e-5, -1e-5, 5e-6)])
 @pytest.mark.parametrize("rates", ["paper", "bulk 0.8", "higher 1.3"])
 @pytest.mark.parametrize("case", sorted(UNIT_CASES))
-def test_unit_rate_and_general_collisions_match_oracle(case, rates):
-    """Without a force: the paper's rates take the unit-rate collision, a bulk
-    rate of 0.8 or higher-order rates of 1.3 the general one.  FP64 to 1e-12,
-    FP32 and the 16-bit forms to the per-step bound, after 1 and 6 steps."""
+def test_unit_rate_and_general_collisions_match_oracle(case, rates, force):
+    """Without a force the paper's rates take the second-order-only collision;
+    with a force, or a bulk rate of 0.8, the unit-rate form of orders 3-6;
+    higher-order rates of 1.3 the general one.  FP64 to 1e-12, FP32 and the
+    16-bit forms to the per-step bound, after 1 and 6 steps."""
     c = UNIT_CASES[case]
     nx, ny, nz = c["shape"]
     nu = 0.01
@@ -115,10 +120,10 @@ def test_unit_rate_and_general_collisions_match_oracle(case, rates):
     om = O.omega_table(nu, omega_bulk=ob, omega_higher=oh)
     g0 = _state(c["shape"], seed=200 + nx, amp=0.08)
     for steps in (1, 6):
-        ref = O.run(g0, om, walls=c["walls"], lid=c["lid"], les=c["les"], steps=steps)
+        ref = O.run(g0, om, force, walls=c["walls"], lid=c["lid"], les=c["les"], steps=steps)
         for storage in ("f64", "f32", "f16dev", "bf16dev"):
             with L.Lattice(L.Config(nx, ny, nz, storage=storage, nu=nu, omega_bulk=ob, omega_higher=oh,
-                                    **c["cfg"])) as lat:
+                                    force=force, **c["cfg"])) as lat:
                 lat.set_f(g0)
                 lat.step(steps)
                 got = lat.get_f()
