@@ -1,12 +1,16 @@
 """Turn rocprofv3 CSV output into the short text summaries kept with the
 measurements.
 
-Two commands:
+Three commands:
 
 ``kernel-stats STATS_CSV OUT.md --title T --cmd C [--trace TRACE_CSV]``
     Table of the ``*_kernel_stats.csv`` written by
     ``rocprofv3 --kernel-trace --stats --output-format csv`` (with the trace
     CSV: one row per kernel and launch grid).
+
+``counters DIR OUT.md --title T --cmd C [--match NAME]``
+    Mean of every counter per dispatch of a ``rocprofv3 --pmc`` run, one row
+    per kernel and grid size.
 
 ``traffic --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --out OUT.md --cmd C ...``
     HBM bytes per launch of the stream-collide kernel of every storage form,
@@ -167,6 +171,30 @@ def kernel_stats(args) -> None:
             fo.write(f"| `{n}` | {grid} | {calls} | {tot:.1f} | {avg:.3f} | {pct:.2f} |\n")
 
 
+def counters(args) -> None:
+    """Mean of every counter per dispatch, one row per kernel and grid size,
+    from the ``*_counter_collection.csv`` of a ``rocprofv3 --pmc`` run."""
+    path = next(os.path.join(args.dir, f) for f in sorted(os.listdir(args.dir)) if f.endswith("counter_collection.csv"))
+    vals: dict[tuple, dict[str, list[float]]] = defaultdict(lambda: defaultdict(list))
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if args.match and args.match not in r["Kernel_Name"]:
+                continue
+            vals[(r["Kernel_Name"], r["Grid_Size"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for v in vals.values() for c in v})
+    with open(args.out, "w") as fo:
+        fo.write(f"# {args.title}\n\nCommand (run from the repository root):\n\n```\n{args.cmd}\n```\n\n")
+        if args.note:
+            fo.write(args.note + "\n\n")
+        fo.write("| kernel | grid (threads) | dispatches | " + " | ".join(names) + " |\n")
+        fo.write("|---|---|---|" + "---|" * len(names) + "\n")
+        for (name, grid), v in sorted(vals.items()):
+            k = name.split("(")[0].replace("void ", "")
+            n = max(len(x) for x in v.values())
+            cells = [f"{sum(v[c]) / len(v[c]):.0f}" if v.get(c) else "" for c in names]
+            fo.write(f"| `{k}` | {grid} | {n} | " + " | ".join(cells) + " |\n")
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -187,9 +215,18 @@ def main() -> None:
     t.add_argument("--nz", type=int, default=128)
     t.add_argument("--workload", default="channel 256x128x128 (walls, body force)")
     t.add_argument("--cmd", action="append", default=[])
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("out")
+    c.add_argument("--title", required=True)
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--note", default="")
+    c.add_argument("--match", default="", help="keep kernels whose name contains this")
     a = ap.parse_args()
     if a.cmd_name == "kernel-stats":
         kernel_stats(a)
+    elif a.cmd_name == "counters":
+        counters(a)
     else:
         res = traffic(a)
         write_traffic_md(res, a.out, a.cmd)

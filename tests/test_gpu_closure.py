@@ -72,8 +72,18 @@ def test_mfma_inference_matches_bf16_oracle(n):
     got = nud.cpu().numpy().astype(np.float64)
     ref = C.forward_bf16(p, X.astype(np.float64))
     scale = np.sqrt(np.mean(ref ** 2))
-    err = np.abs(got - ref).max()
-    assert err <= 2e-2 * scale + 1e-6, (err, scale)
+    e = np.abs(got - ref)
+    err = e.max()
+    # The same bf16 roundings give the same network up to the order of the FP32
+    # sums (~1e-7 relative); a hidden activation next to a bf16 rounding
+    # boundary may round the other way on either side and move a node's outputs
+    # by about one bf16 unit of that hidden unit times |W3| (measured: 1e-5 of
+    # the rms at one of 4,099 nodes).  So 99 % of the outputs agree to the FP32
+    # level (measured 1.2e-7 of the rms) and all to 1e-3.
+    q = np.quantile(e, [0.5, 0.9, 0.99]) / scale
+    print(f"inference vs bf16 oracle / rms: median {q[0]:.1e}, 90% {q[1]:.1e}, 99% {q[2]:.1e}, max {err / scale:.1e}")
+    assert q[2] <= 1e-6, q
+    assert err <= 1e-3 * scale, (err, scale)
     # and close to the exact network as well (BF16 quantisation only)
     exact, _ = C.forward(p, X)
     assert np.sqrt(np.mean((got - exact) ** 2)) <= 3e-2 * scale
