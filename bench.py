@@ -19,8 +19,9 @@ on the same GPU: that is the error at which the form's throughput is stated.
 Printed (one JSON line): MLUPS of the FP32-storage form as ``value``, the HBM
 roofline of its stream-collide kernel (algorithmic bytes per launch over the
 measured launch time), every storage form's MLUPS, roofline fraction and error
-against FP64, the learned-closure kernel on the coarse channel 192x96x96 for
-context, and the FP64 CPU oracle timed on a bounded slab of the same field.
+against FP64, the learned-closure kernel beside the plain step on the coarse
+channel 192x96x96 and on the turbulent-channel grid 384x192x192 for context,
+and the FP64 CPU oracle timed on a bounded slab of the same field.
 """
 from __future__ import annotations
 
@@ -215,20 +216,31 @@ def main():
     del u64, rd, ud
     torch.cuda.empty_cache()
 
-    # learned-closure forms on the coarse channel 192 x 96 x 96 (context: the
-    # closure workload, nu and force of the fine channel under 2x coarsening)
+    # learned-closure forms (context): the coarse channel 192 x 96 x 96 of the
+    # closure workload (nu and force of the fine channel under 2x coarsening,
+    # 2 x 191 MB of 16-bit state: held in the 256 MB last-level cache), and the
+    # turbulent-channel grid 384 x 192 x 192 at Re_tau = 180 (u_tau = 0.0025,
+    # h = 96), whose state does not fit in that cache.  Each form's plain
+    # step beside it; "vs_f32_plain" = MLUPS over the plain FP32 step's.
     closure = {}
     if args.closure_steps > 0:
-        cshape = (192, 96, 96)
-        cnu, F = 0.005, 2 * 8 * 0.01 * 0.05 / 128 ** 2
         params = closure_params()
-        for st, use in [("f32", False), ("f16dev", False), ("bf16dev", False), ("f32", True), ("f16dev", True),
-                        ("bf16dev", True)]:
-            key = st + ("+closure" if use else "")
-            closure[key] = run_closure_form(L, torch, st, cshape, cnu, F, args.closure_steps, 200,
-                                            params if use else None)
-            closure[key] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in closure[key].items()}
-            print(f"# coarse {key}: {closure[key]['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        ut = 0.0025
+        grids = [("channel_192x96x96", (192, 96, 96), 0.005, 2 * 8 * 0.01 * 0.05 / 128 ** 2, args.closure_steps),
+                 ("channel_384x192x192", (384, 192, 192), ut * 96 / 180, ut * ut / 96,
+                  max(1, args.closure_steps // 5))]
+        for gname, cshape, cnu, F, csteps in grids:
+            cg = {}
+            for st, use in [("f32", False), ("f16dev", False), ("bf16dev", False), ("f32", True),
+                            ("f16dev", True), ("bf16dev", True)]:
+                key = st + ("+closure" if use else "")
+                cg[key] = run_closure_form(L, torch, st, cshape, cnu, F, csteps, 200, params if use else None)
+                print(f"# {gname} {key}: {cg[key]['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+            for key in cg:
+                cg[key]["vs_f32_plain"] = cg[key]["mlups"] / cg["f32"]["mlups"]
+                cg[key] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cg[key].items()}
+            cg["steps"] = csteps
+            closure[gname] = cg
 
     main_form = results["f32"]
     roof = {"bound": "hbm", "achieved": round(main_form["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
@@ -260,7 +272,7 @@ def main():
         "roofline": roof,
         "forms": {k: {kk: (float(f"{vv:.6g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in results.items()},
-        "closure_forms_channel_192x96x96": closure,
+        "closure_forms": closure,
     }
     if not args.no_cpu_baseline:
         mlups, dt, cores = cpu_baseline(n, nu, args.cpu_planes, args.cpu_steps)
