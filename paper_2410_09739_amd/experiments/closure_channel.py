@@ -8,6 +8,7 @@ plain coarse run, the closure run and the filtered fine run, the wall friction
 velocity of each, the wall time of each, and the trained parameters (.npy).
 
     python -m paper_2410_09739_amd.experiments.closure_channel [--tstar-transient 6] [--tstar-stats 6]
+        [--shape 256,128,128] [--seeds 3] [--gains 1,3] [--coarse-storage f32,f16dev]
 
 Time unit T* = h / u_tau (38,400 fine steps).  The fine run gives a snapshot
 every T*/2 of its statistics window (the last one held out of training).  The
@@ -123,6 +124,8 @@ def main():
     ap.add_argument("--seeds", type=int, default=1, help="networks trained from different initialisations")
     ap.add_argument("--gains", default="1", help="comma list: multipliers of the network output (a-posteriori scale)")
     ap.add_argument("--save-params", default="closure_params.npy")
+    ap.add_argument("--coarse-storage", default="f32",
+                    help="comma list of storage forms for the coarse runs (plain and closure in each)")
     args = ap.parse_args()
     import torch
 
@@ -229,9 +232,14 @@ def main():
     c_settle = int((args.coarse_run - args.coarse_stats) * ctstar)
     c_stats = int(args.coarse_stats * ctstar)
     res = {}
-    runs = [("plain", None)] + [(f"closure_s{k}_g{g:g}", scaled_output(p, g)) for g in gains for k, p in enumerate(nets)]
-    for name, p in runs:
-        with L.Lattice(ccfg) as c:
+    cforms = [s for s in args.coarse_storage.split(",") if s]
+    runs = []
+    for st in cforms:
+        pre = "" if len(cforms) == 1 else f"{st}_"
+        runs += [(pre + "plain", st, None)]
+        runs += [(f"{pre}closure_s{k}_g{g:g}", st, scaled_output(p, g)) for g in gains for k, p in enumerate(nets)]
+    for name, st, p in runs:
+        with L.Lattice(L.Config(*cshape, storage=st, walls_y=True, nu=nu_f / 2, force=(2 * F_f, 0, 0))) as c:
             L.lbm_init_device(c.ctx, rc0.data_ptr(), uc0.data_ptr())
             if p is not None:
                 L.lbm_set_closure(c.ctx, p)
@@ -259,13 +267,16 @@ def main():
             f"U rel L2 {res[name]['rel_l2_U_vs_filtered_fine']:.4f}, "
             f"u_rms {res[name]['rel_l2_u_rms_vs_filtered_fine']:.4f}, v_rms {res[name]['rel_l2_v_rms_vs_filtered_fine']:.4f}")
     summary = {}
-    for g in gains:
-        names = [f"closure_s{k}_g{g:g}" for k in range(args.seeds)]
-        summary[f"gain {g:g}"] = {q: [float(np.mean([res[n][q] for n in names])), float(np.std([res[n][q] for n in names]))]
-                                  for q in ("u_bulk_over_u_tau", "u_bulk_rel_err_vs_fine", "rel_l2_U_vs_filtered_fine",
-                                            "rel_l2_u_rms_vs_filtered_fine", "rel_l2_v_rms_vs_filtered_fine",
-                                            "rel_l2_w_rms_vs_filtered_fine")}
-        log(f"gain {g:g} over {args.seeds} networks (mean, std): {summary[f'gain {g:g}']}")
+    for st in cforms:
+        pre = "" if len(cforms) == 1 else f"{st}_"
+        for g in gains:
+            names = [f"{pre}closure_s{k}_g{g:g}" for k in range(args.seeds)]
+            key = f"{pre}gain {g:g}"
+            summary[key] = {q: [float(np.mean([res[n][q] for n in names])), float(np.std([res[n][q] for n in names]))]
+                            for q in ("u_bulk_over_u_tau", "u_bulk_rel_err_vs_fine", "rel_l2_U_vs_filtered_fine",
+                                      "rel_l2_u_rms_vs_filtered_fine", "rel_l2_v_rms_vs_filtered_fine",
+                                      "rel_l2_w_rms_vs_filtered_fine")}
+            log(f"{key} over {args.seeds} networks (mean, std): {summary[key]}")
     out["coarse"] = res
     out["closure_summary"] = summary
     out["coarse_start_after_fine_steps"] = n_trans
