@@ -103,7 +103,31 @@ def scaled_output(params: np.ndarray, gain: float) -> np.ndarray:
     return p
 
 
-def main():
+def balance_eddy_viscosity(prof_c: dict, filt: dict, u_tau: float, nu: float, cap: float) -> np.ndarray:
+    """Eddy viscosity per coarse row that makes the coarse run's total shear
+    stress carry the filtered fine mean profile: in a statistically steady
+    channel (nu + nu_t) dU/dy - <u'v'> = u_tau^2 (1 - y/h) with y from the lower
+    wall (halfway bounce-back: row j at y = j + 1/2), so with the coarse run's
+    resolved <u'v'> and the filtered fine dU/dy,
+    nu_t = (u_tau^2 (1 - y/h) + <u'v'>_c) / dU_f/dy - nu, clipped to [0, cap].
+    The two halves are averaged as mirror images."""
+    U, uv = filt["U"], prof_c["uv"]
+    ny = len(U)
+    h = ny / 2.0
+    y = np.arange(ny) + 0.5
+    dU = np.empty(ny)
+    dU[1:-1] = 0.5 * (U[2:] - U[:-2])
+    dU[0] = 0.5 * (U[1] + U[0])  # ghost row below the wall: -U[0] (no slip half a link below row 0)
+    dU[-1] = -0.5 * (U[-1] + U[-2])
+    tau = u_tau * u_tau * (1.0 - y / h)
+    nut = np.zeros(ny)
+    ok = np.abs(dU) > 1e-3 * np.abs(dU).max()
+    nut[ok] = (tau[ok] + uv[ok]) / dU[ok] - nu
+    nut = 0.5 * (nut + nut[::-1])
+    return np.clip(nut, 0.0, cap)
+
+
+def main(argv=None) -> dict:
     ap = argparse.ArgumentParser()
     ap.add_argument("--shape", default="384,192,192")
     ap.add_argument("--u-tau", type=float, default=0.0025)
@@ -126,7 +150,13 @@ def main():
     ap.add_argument("--save-params", default="closure_params.npy")
     ap.add_argument("--coarse-storage", default="f32",
                     help="comma list of storage forms for the coarse runs (plain and closure in each)")
-    args = ap.parse_args()
+    ap.add_argument("--refine", type=int, default=0,
+                    help="a-posteriori passes: coarse run with the network, targets from the mean momentum "
+                         "balance of that run, retraining (first network only)")
+    ap.add_argument("--refine-relax", type=float, default=0.5, help="under-relaxation of the refined targets")
+    ap.add_argument("--load-params", default=None,
+                    help="closure parameters (.npy) to evaluate instead of training: a network from another start")
+    args = ap.parse_args(argv)
     import torch
 
     from paper_2410_09739_amd import lbm as L
@@ -205,7 +235,10 @@ def main():
     gains = [float(g) for g in args.gains.split(",")]
     nets = []
     out["training"] = []
-    for k in range(args.seeds):
+    if args.load_params:
+        nets.append(np.load(args.load_params).astype(np.float32))
+        log(f"closure parameters from {args.load_params} (no training)")
+    for k in range(0 if args.load_params else args.seeds):
         m = L.MLP(seed=11 + k)
         m.fit_normalisation(X.data_ptr(), Y.data_ptr(), ntr)
         l0, _ = m.loss_grad(X.data_ptr(), Y.data_ptr(), ntr)
@@ -223,32 +256,67 @@ def main():
                                 "loss_heldout_after": lh1, "wall_s": t_train, "steps": args.train_steps,
                                 "batch": args.batch, "loss_history_every_100": [float(v) for v in hist[::100]]})
         log(f"training {k}: loss {l0:.4e} -> {l1:.4e}, held-out {lh0:.4e} -> {lh1:.4e}, {t_train:.1f} s")
-    np.save(args.save_params, scaled_output(nets[0], gains[0]))
-    del X, Y, xs, ys
-
     # ---- coarse runs from the filtered fine state
+    cforms = [s for s in args.coarse_storage.split(",") if s]
     ctstar = tstar // 2  # dt_c = 2 dt_f
     cevery = max(1, every // 2)
     c_settle = int((args.coarse_run - args.coarse_stats) * ctstar)
     c_stats = int(args.coarse_stats * ctstar)
+
+    def coarse_run(st, p, tag):
+        with L.Lattice(L.Config(*cshape, storage=st, walls_y=True, nu=nu_f / 2, force=(2 * F_f, 0, 0))) as c:
+            L.lbm_init_device(c.ctx, rc0.data_ptr(), uc0.data_ptr())
+            if p is not None:
+                L.lbm_set_closure(c.ctx, p)
+            t_c = run_window(L, torch, c, c_settle, cevery, None, tag)
+            cs = ProfileStats(torch, cshape[1])
+            c_ub = []
+            t_c += run_window(L, torch, c, c_stats, cevery, cs, tag, None, c_ub)
+            dc = c.diagnostics()
+        return cs.result(), c_ub, dc, t_c
+
+    # ---- a-posteriori refinement of the first network: its coarse run's
+    # resolved shear stress and the filtered fine profile give, through the
+    # mean momentum balance, the eddy viscosity per row that the coarse grid
+    # lacks; every training sample of that row takes it as the target of the
+    # three off-diagonal groups, and a network is trained on them
+    out["refine"] = []
+    if args.refine > 0 and not args.load_params:
+        cy = cshape[1]
+        rows = torch.arange(X.shape[0], device="cuda") % nc // cshape[0] % cy
+        nut_prev = None
+        for it in range(args.refine):
+            prof_c, c_ub, _, _ = coarse_run(cforms[0], nets[0], f"refine {it}")
+            nut = balance_eddy_viscosity(prof_c, filt, ut, nu_f / 2, cap=4.0 * nu_f / 2)
+            if nut_prev is not None:
+                nut = args.refine_relax * nut + (1.0 - args.refine_relax) * nut_prev
+            nut_prev = nut
+            err = float(np.sqrt(np.sum((prof_c["U"] - filt["U"]) ** 2) / np.sum(filt["U"] ** 2)))
+            log(f"refine {it}: U rel L2 of the run {err:.4f}, U_b/u_tau {np.mean(c_ub) / ut:.3f}; "
+                f"target nu_t / nu_c by row {np.round(nut[: cy // 2] / (nu_f / 2), 3).tolist()}")
+            Yr = torch.zeros_like(Y)
+            tn = torch.tensor(nut, dtype=torch.float32, device="cuda")[rows]
+            for j in range(3):
+                Yr[:, j] = tn
+            m = L.MLP(seed=11)
+            m.fit_normalisation(X.data_ptr(), Yr.data_ptr(), ntr)
+            hist = m.train(X.data_ptr(), Yr.data_ptr(), ntr, args.batch, args.train_steps, args.lr, 5)
+            l1, _ = m.loss_grad(X.data_ptr(), Yr.data_ptr(), ntr)
+            nets[0] = m.export()
+            m.close()
+            out["refine"].append({"pass": it, "run_rel_l2_U": err, "run_u_bulk_over_u_tau": float(np.mean(c_ub) / ut),
+                                  "target_nu_t_over_nu_c": [round(float(v), 4) for v in nut / (nu_f / 2)],
+                                  "loss_after": l1})
+    np.save(args.save_params, scaled_output(nets[0], gains[0]))
+    del X, Y, xs, ys
     res = {}
-    cforms = [s for s in args.coarse_storage.split(",") if s]
     runs = []
     for st in cforms:
         pre = "" if len(cforms) == 1 else f"{st}_"
         runs += [(pre + "plain", st, None)]
         runs += [(f"{pre}closure_s{k}_g{g:g}", st, scaled_output(p, g)) for g in gains for k, p in enumerate(nets)]
     for name, st, p in runs:
-        with L.Lattice(L.Config(*cshape, storage=st, walls_y=True, nu=nu_f / 2, force=(2 * F_f, 0, 0))) as c:
-            L.lbm_init_device(c.ctx, rc0.data_ptr(), uc0.data_ptr())
-            if p is not None:
-                L.lbm_set_closure(c.ctx, p)
-            t_c = run_window(L, torch, c, c_settle, cevery, None, f"coarse {name}")
-            cs = ProfileStats(torch, cshape[1])
-            c_ub = []
-            t_c += run_window(L, torch, c, c_stats, cevery, cs, f"coarse {name}", None, c_ub)
-            dc = c.diagnostics()
-        pr = cs.result()
+        pr, c_ub, dc, t_c = coarse_run(st, p, f"coarse {name}")
         res[name] = {"wall_s": t_c, "steps": c_settle + c_stats, "stats_steps": c_stats,
                      "u_tau_end": friction_velocity(dc, cshape[0], cshape[2]),
                      "u_bulk_over_u_tau": float(np.mean(c_ub) / ut), "u_bulk_std_over_u_tau": float(np.std(c_ub) / ut),
@@ -270,13 +338,13 @@ def main():
     for st in cforms:
         pre = "" if len(cforms) == 1 else f"{st}_"
         for g in gains:
-            names = [f"{pre}closure_s{k}_g{g:g}" for k in range(args.seeds)]
+            names = [f"{pre}closure_s{k}_g{g:g}" for k in range(len(nets))]
             key = f"{pre}gain {g:g}"
             summary[key] = {q: [float(np.mean([res[n][q] for n in names])), float(np.std([res[n][q] for n in names]))]
                             for q in ("u_bulk_over_u_tau", "u_bulk_rel_err_vs_fine", "rel_l2_U_vs_filtered_fine",
                                       "rel_l2_u_rms_vs_filtered_fine", "rel_l2_v_rms_vs_filtered_fine",
                                       "rel_l2_w_rms_vs_filtered_fine")}
-            log(f"{key} over {args.seeds} networks (mean, std): {summary[key]}")
+            log(f"{key} over {len(nets)} networks (mean, std): {summary[key]}")
     out["coarse"] = res
     out["closure_summary"] = summary
     out["coarse_start_after_fine_steps"] = n_trans
@@ -284,6 +352,7 @@ def main():
     out["filtered_fine_rms_over_u_tau"] = {q: [round(float(v) / ut, 4) for v in filt[q][: cshape[1] // 2]]
                                            for q in ("u_rms", "v_rms", "w_rms")}
     print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -85,6 +85,16 @@ def _counter_means(d: str) -> dict[str, list[float]]:
     return vals
 
 
+def _counter_means_by_name(d: str) -> dict[str, dict[str, list[float]]]:
+    """kernel -> counter -> values per dispatch (a run collecting several counters)."""
+    path = next(os.path.join(d, f) for f in sorted(os.listdir(d)) if f.endswith("counter_collection.csv"))
+    vals: dict[str, dict[str, list[float]]] = defaultdict(lambda: defaultdict(list))
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            vals[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return vals
+
+
 def _copy_factor(d: str, nbytes: int) -> float:
     """Bytes that one KiB of the counter stands for, from a copy of ``nbytes``."""
     v = _counter_means(d)[COPY_KERNEL]
@@ -97,6 +107,7 @@ def traffic(args) -> dict:
     cf = _copy_factor(args.copy_fetch, args.copy_bytes)
     cw = _copy_factor(args.copy_write, args.copy_bytes)
     fetch, write = _counter_means(args.fetch), _counter_means(args.write)
+    dram = _counter_means_by_name(args.dram) if getattr(args, "dram", None) else {}
     forms = {}
     for name in fetch:
         m = re.match(r"void k_stream_collide<(\d+),", name)
@@ -110,6 +121,16 @@ def traffic(args) -> dict:
         forms[form] = {"kernel": name, "launches": len(fetch[name]), "fetch_kib": round(fk, 3),
                        "write_kib": round(wk, 3), "hbm_bytes_per_launch": round(hbm),
                        "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": round(hbm / alg, 5)}
+        if name in dram:
+            # DRAM requests counted in 32-byte units (a 64- or 128-byte request counts 2 or 4):
+            # bytes with no calibration
+            rd = dram[name].get("TCC_EA0_RDREQ_DRAM_32B_sum", [])
+            wr = dram[name].get("TCC_EA0_WRREQ_WRITE_DRAM_32B_sum", [])
+            if rd and wr:
+                b = 32.0 * (sum(rd) / len(rd) + sum(wr) / len(wr))
+                forms[form]["dram_32b_read_bytes"] = round(32.0 * sum(rd) / len(rd))
+                forms[form]["dram_32b_write_bytes"] = round(32.0 * sum(wr) / len(wr))
+                forms[form]["dram_32b_over_algorithmic"] = round(b / alg, 5)
     return {"kernel_source_sha": kernel_source_hash(), "workload": args.workload,
             "shape": [args.nx, args.ny, args.nz], "nodes": nodes,
             "copy_factor_fetch_bytes_per_kib": round(cf, 3), "copy_factor_write_bytes_per_kib": round(cw, 3),
@@ -125,11 +146,18 @@ def write_traffic_md(res: dict, out: str, cmds: list[str]) -> None:
                  f"write {res['copy_factor_write_bytes_per_kib']} B/KiB).  Algorithmic bytes per "
                  "launch: 27 reads + 27 writes of the stored population per node.\n\n")
         fo.write("Commands (run from the repository root):\n\n```\n" + "\n".join(cmds) + "\n```\n\n")
-        fo.write("| form | fetch KiB | write KiB | HBM bytes / launch | algorithmic | ratio |\n"
-                 "|---|---|---|---|---|---|\n")
+        dram = all("dram_32b_over_algorithmic" in r for r in res["forms"].values())
+        if dram:
+            fo.write("Cross-check without a calibration: the DRAM read and write requests in 32-byte units "
+                     "(TCC_EA0_RDREQ_DRAM_32B_sum, TCC_EA0_WRREQ_WRITE_DRAM_32B_sum, one further run) "
+                     "times 32 bytes.\n\n")
+        fo.write("| form | fetch KiB | write KiB | HBM bytes / launch | algorithmic | ratio |"
+                 + (" DRAM 32-B units x 32 / algorithmic |" if dram else "") + "\n"
+                 "|---|---|---|---|---|---|" + ("---|" if dram else "") + "\n")
         for f, r in res["forms"].items():
             fo.write(f"| {f} | {r['fetch_kib']:.1f} | {r['write_kib']:.1f} | {r['hbm_bytes_per_launch']} | "
-                     f"{r['algorithmic_bytes_per_launch']} | {r['traffic_over_algorithmic']:.4f} |\n")
+                     f"{r['algorithmic_bytes_per_launch']} | {r['traffic_over_algorithmic']:.4f} |"
+                     + (f" {r['dram_32b_over_algorithmic']:.4f} |" if dram else "") + "\n")
         fo.write("\n```json\n" + json.dumps(res, indent=1) + "\n```\n")
 
 
@@ -215,6 +243,8 @@ def main() -> None:
     t.add_argument("--nz", type=int, default=128)
     t.add_argument("--workload", default="channel 256x128x128 (walls, body force)")
     t.add_argument("--cmd", action="append", default=[])
+    t.add_argument("--dram", default=None, help="a --pmc run of TCC_EA0_RDREQ_DRAM_32B_sum and "
+                   "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum (cross-check)")
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("out")
