@@ -154,6 +154,9 @@ def main(argv=None) -> dict:
                     help="a-posteriori passes: coarse run with the network, targets from the mean momentum "
                          "balance of that run, retraining (first network only)")
     ap.add_argument("--refine-relax", type=float, default=0.5, help="under-relaxation of the refined targets")
+    ap.add_argument("--refine-groups", default="110,101,011",
+                    help="off-diagonal groups that take the refined target, the others 0 (the mean momentum "
+                         "balance fixes the x-y shear viscosity only; 110 alone is the variant)")
     ap.add_argument("--load-params", default=None,
                     help="closure parameters (.npy) to evaluate instead of training: a network from another start")
     args = ap.parse_args(argv)
@@ -279,7 +282,8 @@ def main(argv=None) -> dict:
     # resolved shear stress and the filtered fine profile give, through the
     # mean momentum balance, the eddy viscosity per row that the coarse grid
     # lacks; every training sample of that row takes it as the target of the
-    # three off-diagonal groups, and a network is trained on them
+    # off-diagonal groups named by --refine-groups (the others 0), and a
+    # network is trained on them
     out["refine"] = []
     if args.refine > 0 and not args.load_params:
         cy = cshape[1]
@@ -296,8 +300,9 @@ def main(argv=None) -> dict:
                 f"target nu_t / nu_c by row {np.round(nut[: cy // 2] / (nu_f / 2), 3).tolist()}")
             Yr = torch.zeros_like(Y)
             tn = torch.tensor(nut, dtype=torch.float32, device="cuda")[rows]
-            for j in range(3):
-                Yr[:, j] = tn
+            for j, grp in enumerate(("110", "101", "011")):
+                if grp in args.refine_groups.split(","):
+                    Yr[:, j] = tn
             m = L.MLP(seed=11)
             m.fit_normalisation(X.data_ptr(), Yr.data_ptr(), ntr)
             hist = m.train(X.data_ptr(), Yr.data_ptr(), ntr, args.batch, args.train_steps, args.lr, 5)
