@@ -71,7 +71,7 @@ def test_omega_table_matches_oracle_mapping(nu, mode):
 
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(ny=-1), dict(nu=0.0), dict(nu=-0.1), dict(omega_bulk=2.0), dict(omega_higher=0.0),
-    dict(storage=7), dict(walls_y=2), dict(nx=2048, ny=2048, nz=1024), dict(attractor=2), dict(attractor=-1), dict(walls_x=2), dict(walls_z=-1),
+    dict(storage=7), dict(walls_y=2), dict(nx=2048, ny=2048, nz=1024), dict(nx=2048, ny=1024, nz=1024),dict(attractor=2), dict(attractor=-1), dict(walls_x=2), dict(walls_z=-1),
 ])
 def test_create_rejects_invalid_configs_before_touching_the_device(bad):
     c = L.Config(8, 8, 8, nu=0.01).to_c()
