@@ -5,7 +5,6 @@ UndefinedBehaviorSanitizer and driven, without a GPU, by a plain C++ program
 access, use after free, leak or undefined behaviour on those paths aborts it.
 The device code is compiled unoptimised (it is never launched here)."""
 import os
-import shutil
 import subprocess
 
 import pytest
