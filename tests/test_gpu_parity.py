@@ -567,10 +567,10 @@ def test_get_f_nodes_equals_get_f(storage):
             assert ei.value.code == L.LBM_EINVAL
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
 def test_taylor_green_512_sampled_nodes(storage):
     """The 512^3 Taylor-Green vortex (Re 1600, u0 0.05) at full size, in the
-    storage forms its precision study compares: a few steps from the initial
+    storage forms the benchmark times: a few steps from the initial
     state, then one more; at sampled nodes (random, periodic seams, segment
     edges) the update equals the oracle's pull and collision of the GPU's own
     previous populations, read back through lbm_get_f_nodes."""
@@ -602,9 +602,9 @@ def test_taylor_green_512_sampled_nodes(storage):
     om = O.omega_table(nu)
     ref = np.stack([O.collide_node(f[:, k], om, (0.0, 0.0, 0.0)) for k in range(sel.size)], axis=1)
     w = W_ALPHA.reshape(27, 1)
-    tol = 8e-7 * w
-    if storage == "f16dev":
-        tol = tol + 2.0 ** -10 * np.abs(ref - w).max() * 2
+    tol = (1e-12 if storage == "f64" else 8e-7) * w
+    ulp = {"f16dev": 2.0 ** -10, "bf16dev": 2.0 ** -7}.get(storage, 0.0)
+    tol = tol + ulp * np.abs(ref - w).max() * 2
     assert np.all(np.abs(got - ref) <= tol), float((np.abs(got - ref) / tol).max())
 
 
