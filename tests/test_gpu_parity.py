@@ -22,7 +22,7 @@ from paper_2410_09739_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 W_ALPHA = O.feq(1.0, [0, 0, 0])[:, None, None, None]
-SHAPES = [(13, 10, 9), (32, 8, 5), (1, 16, 1), (65, 3, 7), (7, 1, 4)]
+SHAPES = [(13, 10, 9), (32, 8, 5), (1, 16, 1), (65, 3, 7), (7, 1, 4), (1, 1, 1)]
 
 
 def _state(shape, seed, amp=0.05, u_amp=0.05):
