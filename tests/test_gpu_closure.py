@@ -233,6 +233,52 @@ def test_coarsen_and_targets_match_oracle(walls, shape, storage):
     np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max() + 1e-30)
 
 
+def test_coarsen_full_size_sampled_blocks():
+    """The box filter at the size the closure study runs it: the fine channel
+    384 x 192 x 192 in FP32 storage onto 192 x 96 x 96.  At sampled coarse
+    nodes (walls, row ends, random) the filtered density, Favre velocity and
+    sub-filter stress equal the oracle's filter of the GPU's own eight fine
+    populations, read back through lbm_get_f_nodes."""
+    nx, ny, nz = 384, 192, 192
+    ut, h = 0.0025, 96.0
+    F = (ut * ut / h, 0.0, 0.0)
+    rho0, u0 = W.channel_turbulent_start(nx, ny, nz, u_bulk=15.7 * ut, amp=0.3, seed=77)
+    cx, cy, cz = nx // 2, ny // 2, nz // 2
+    nc = cx * cy * cz
+    rng = np.random.default_rng(9)
+    sel = np.unique(np.concatenate([
+        rng.integers(0, nc, 2000),
+        np.array([(z * cy + y) * cx + x for x in (0, 31, 32, cx - 1) for y in (0, cy - 1) for z in (0, cz - 1)]),
+    ]))
+    X, Y, Z = sel % cx, (sel // cx) % cy, sel // (cx * cy)
+    m = sel.size
+    # fine node of (k, j, i) in block b, laid out as a (2, 2, 2m) pseudo-lattice
+    kk, jj, ii = np.meshgrid(np.arange(2), np.arange(2), np.arange(2), indexing="ij")
+    fine_idx = (((2 * Z[None, None, None] + kk[..., None]) * ny + 2 * Y[None, None, None] + jj[..., None]) * nx
+                + 2 * X[None, None, None] + ii[..., None])  # [k, j, i, b]
+    with L.Lattice(L.Config(nx, ny, nz, storage="f32", walls_y=True, nu=ut * h / 180.0, force=F)) as fine:
+        fine.init(rho0, u0)
+        del rho0, u0
+        fine.step(3)
+        g = fine.get_f_nodes(np.moveaxis(fine_idx, -1, 2).ravel())  # order [k, j, b, i]
+        rd = torch.zeros(nc, dtype=torch.float64, device="cuda")
+        ud = torch.zeros(3 * nc, dtype=torch.float64, device="cuda")
+        td = torch.zeros(6 * nc, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        L.lbm_coarsen(fine.ctx, rd.data_ptr(), ud.data_ptr(), td.data_ptr())
+        fine.synchronize()
+    gs = g.reshape(27, 2, 2, 2 * m)
+    rho, u = O.macroscopic(gs, F)
+    rb, utl, tau = C.box_filter(rho, u)
+    got_r = rd.cpu().numpy()[sel]
+    got_u = ud.cpu().numpy().reshape(3, nc)[:, sel]
+    got_t = td.cpu().numpy().reshape(6, nc)[:, sel]
+    np.testing.assert_allclose(got_r, rb.reshape(m), rtol=1e-13)
+    np.testing.assert_allclose(got_u, utl.reshape(3, m), rtol=1e-11, atol=1e-15)
+    np.testing.assert_allclose(got_t, tau.reshape(6, m), rtol=1e-9, atol=1e-15)
+    assert np.abs(tau[3]).max() > 1e-8  # resolved velocity differences inside the blocks
+
+
 def _oracle_pre_collision(g, F, walls):
     """Streamed populations, Step 7 fields and central moments about u (FP64)."""
     e, _, _ = O.lattice()
