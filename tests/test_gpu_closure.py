@@ -89,9 +89,9 @@ def test_mfma_inference_matches_bf16_oracle(n):
     assert np.sqrt(np.mean((got - exact) ** 2)) <= 3e-2 * scale
 
 
-def test_mlp_loss_and_gradient_match_oracle():
+@pytest.mark.parametrize("n", [1000, 2_000_003])  # not multiples of the 32-sample chunk; the second of
+def test_mlp_loss_and_gradient_match_oracle(n):     # the size of a closure study's training set
     rng = np.random.default_rng(3)
-    n = 1000  # not a multiple of the 32-sample chunk
     X = rng.standard_normal((n, 27)).astype(np.float32)
     Y = rng.standard_normal((n, 6)).astype(np.float32)
     p = _params(4)
@@ -103,6 +103,25 @@ def test_mlp_loss_and_gradient_match_oracle():
     lref, gref = C.loss_and_grad(p, X.astype(np.float64), Y.astype(np.float64))
     assert loss == pytest.approx(lref, rel=1e-5)
     assert np.abs(g - gref).max() <= 1e-4 * np.abs(gref).max()
+    m.close()
+
+
+def test_mlp_normalisation_statistics_at_training_set_size():
+    """Column means and standard deviations of 2,000,003 feature rows with a
+    large common offset (the features' own scale: 1e-3 +- 3e-4), and the rms
+    target scale, against numpy in FP64."""
+    rng = np.random.default_rng(12)
+    n = 2_000_003
+    X = (3e-4 * rng.standard_normal((n, 27)) + 1e-3 * (1 + np.arange(27))).astype(np.float32)
+    Y = (2e-3 * rng.standard_normal((n, 6))).astype(np.float32)
+    xd, yd = _dev(X), _dev(Y)
+    m = L.MLP(seed=0)
+    m.fit_normalisation(xd.data_ptr(), yd.data_ptr(), n)
+    mu, sg, sy = m.get_normalisation()
+    X64 = X.astype(np.float64)
+    np.testing.assert_allclose(mu, X64.mean(0), rtol=1e-6)
+    np.testing.assert_allclose(sg, X64.std(0), rtol=1e-5)
+    assert sy == pytest.approx(np.sqrt(np.mean(Y.astype(np.float64) ** 2)), rel=1e-6)
     m.close()
 
 
