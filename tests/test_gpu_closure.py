@@ -53,6 +53,45 @@ def _bf16_alternatives(X, xtol, max_flips=4):
     return out
 
 
+def _explained_by_one_hidden_flip(p, x, got, tol):
+    """True if some network that differs from the oracle's bf16 forward only in
+    one hidden activation rounded to its other bf16 neighbour gives got (within
+    tol).  A unit is a candidate when its pre-activation, known to FP32
+    accumulation accuracy, may lie on either side of a bf16 rounding boundary."""
+    W1, b1, W2, b2, W3, b3 = C.unpack(p)
+    W1q, W2q, W3q = C.round_bf16(W1), C.round_bf16(W2), C.round_bf16(W3)
+    b1f, b2f, b3f = (b.astype(np.float32).astype(np.float64) for b in (b1, b2, b3))
+    xq = C.round_bf16(x)
+
+    def other(z, mag):
+        d = 64 * 2.0 ** -24 * mag  # FP32 accumulation of up to 64 products
+        r = lambda v: C.round_bf16(np.maximum(v, 0.0))  # noqa: E731  (ReLU, then bf16)
+        lo, hi, q = r(z - d), r(z + d), r(z)
+        return np.where(lo != q, lo, np.where(hi != q, hi, np.nan))
+
+    def layer2_on(h1):
+        z2 = h1 @ W2q.T + b2f
+        return z2, C.round_bf16(np.maximum(z2, 0.0)), np.abs(h1) @ np.abs(W2q).T + np.abs(b2f)
+
+    z1 = xq @ W1q.T + b1f
+    h1 = C.round_bf16(np.maximum(z1, 0.0))
+    z2, h2, m2 = layer2_on(h1)
+    alt1 = other(z1, np.abs(xq) @ np.abs(W1q).T + np.abs(b1f))
+    alt2 = other(z2, m2)
+    for k in np.flatnonzero(~np.isnan(alt2)):
+        h = h2.copy()
+        h[k] = alt2[k]
+        if np.all(np.abs(h @ W3q.T + b3f - got) <= tol):
+            return True
+    for k in np.flatnonzero(~np.isnan(alt1)):
+        h = h1.copy()
+        h[k] = alt1[k]
+        _, hh2, _ = layer2_on(h)
+        if np.all(np.abs(hh2 @ W3q.T + b3f - got) <= tol):
+            return True
+    return False
+
+
 def _dev(a):
     """Device copy of a host array; the caller keeps the tensor alive while the
     library uses its pointer (the library runs on its own stream)."""
@@ -61,7 +100,7 @@ def _dev(a):
     return t
 
 
-@pytest.mark.parametrize("n", [64, 1000, 4099])
+@pytest.mark.parametrize("n", [64, 1000, 4099, 1_000_003])
 def test_mfma_inference_matches_bf16_oracle(n):
     p = _params(1)
     X = np.random.default_rng(2).standard_normal((n, 27)).astype(np.float32)
@@ -79,11 +118,19 @@ def test_mfma_inference_matches_bf16_oracle(n):
     # boundary may round the other way on either side and move a node's outputs
     # by about one bf16 unit of that hidden unit times |W3| (measured: 1e-5 of
     # the rms at one of 4,099 nodes).  So 99 % of the outputs agree to the FP32
-    # level (measured 1.2e-7 of the rms) and all to 1e-3.
+    # level (measured 1.2e-7 of the rms).
     q = np.quantile(e, [0.5, 0.9, 0.99]) / scale
     print(f"inference vs bf16 oracle / rms: median {q[0]:.1e}, 90% {q[1]:.1e}, 99% {q[2]:.1e}, max {err / scale:.1e}")
     assert q[2] <= 1e-6, q
-    assert err <= 1e-3 * scale, (err, scale)
+    # Every node beyond the FP32 sums' reach (which tops out near 1e-5 of the
+    # rms: 64-term sums of outputs up to several times the rms) is the oracle's
+    # network with one hidden activation rounded to its other bf16 neighbour
+    # (measured on 1,000,003 nodes: 947, all explained so).
+    off = np.flatnonzero(np.any(e > 1e-5 * scale, axis=1))
+    print(f"{off.size} of {n} nodes beyond the FP32 level")
+    assert off.size <= 0.01 * n
+    for i in off:
+        assert _explained_by_one_hidden_flip(p, X[i].astype(np.float64), got[i], 1e-5 * scale), i
     # and close to the exact network as well (BF16 quantisation only)
     exact, _ = C.forward(p, X)
     assert np.sqrt(np.mean((got - exact) ** 2)) <= 3e-2 * scale
