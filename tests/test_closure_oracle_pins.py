@@ -318,3 +318,75 @@ def test_minibatch_indices_follow_their_definition_and_are_uniform():
     chi2 = float(((counts - expect) ** 2 / expect).sum())
     from scipy.stats import chi2 as chi2dist
     assert chi2dist.sf(chi2, n - 1) > 1e-4
+
+
+def _hidden(p, x):
+    """Pre-activations and bf16 activations of the oracle's quantised network."""
+    W1, b1, W2, b2, W3, b3 = C.unpack(p)
+    xq = C.round_bf16(x)
+    z1 = xq @ C.round_bf16(W1).T + b1.astype(np.float32)
+    h1 = C.round_bf16(np.maximum(z1, 0.0))
+    z2 = h1 @ C.round_bf16(W2).T + b2.astype(np.float32)
+    return z1, h1, z2, C.round_bf16(np.maximum(z2, 0.0))
+
+
+def test_acceptance_of_one_hidden_rounding_flip_rejects_planted_mistakes():
+    """The GPU inference check accepts a node's outputs when they are the
+    oracle's network with one hidden activation rounded to its other bf16
+    neighbour, where that activation may sit on a rounding boundary.  Planted
+    on the CPU: such a flip next to a boundary is accepted; the same flip on a
+    unit far from any boundary, an output offset by 1e-4, the outputs of another
+    node, or the outputs with W3's rows swapped are rejected."""
+    from closure_checks import explained_by_one_hidden_flip as ok
+    rng = np.random.default_rng(4)
+    W1, b1, W2, b2, W3, b3 = C.unpack(C.init_params(2))
+    p = C.pack(W1, b1 + 0.1 * rng.standard_normal(64), W2, b2 + 0.1 * rng.standard_normal(64), W3,
+               b3 + 0.1 * rng.standard_normal(6)).astype(np.float32).astype(np.float64)
+    W3q, b3f = C.round_bf16(C.unpack(p)[4]), C.unpack(p)[5].astype(np.float32).astype(np.float64)
+    X = rng.standard_normal((3000, 27)).astype(np.float32).astype(np.float64)
+    ref = C.forward_bf16(p, X)
+    tol = 1e-6
+    near = far = None
+    for n in range(X.shape[0]):
+        z1, h1, z2, h2 = _hidden(p, X[n])
+        up = C.round_bf16(np.maximum(z2, 0.0) * (1 + 2.0 ** -8))  # the next bf16 value up (positive units)
+        rel = np.abs(np.maximum(z2, 0.0) - 0.5 * (h2 + up)) / np.maximum(np.abs(z2), 1e-30)
+        k_near, k_far = int(np.argmin(np.where(z2 > 0, rel, np.inf))), int(np.argmax(np.where(z2 > 1.0, rel, -1)))
+        if near is None and z2[k_near] > 0 and rel[k_near] < 1e-7:
+            h = h2.copy()
+            h[k_near] = C.round_bf16([2 * z2[k_near] - h2[k_near]])[0]  # the other neighbour
+            near = (n, h @ W3q.T + b3f)
+        if far is None and z2[k_far] > 1.0 and rel[k_far] > 1e-3:
+            h = h2.copy()
+            h[k_far] = C.round_bf16([2 * z2[k_far] - h2[k_far]])[0]
+            if np.abs(h @ W3q.T + b3f - ref[n]).max() > 10 * tol:
+                far = (n, h @ W3q.T + b3f)
+        if near and far:
+            break
+    assert near is not None and far is not None
+    n, got = near
+    assert np.abs(got - ref[n]).max() > 10 * tol  # the flip is visible
+    assert ok(p, X[n], got, tol)
+    n, got = far
+    assert not ok(p, X[n], got, tol)
+    assert not ok(p, X[0], ref[0] + 1e-4, tol)
+    assert not ok(p, X[0], ref[1], tol)
+    assert not ok(p, X[0], ref[0][[1, 0, 2, 3, 4, 5]], tol) or np.allclose(ref[0][0], ref[0][1])
+
+
+def test_feature_rounding_alternatives_cover_exactly_the_near_boundary_features():
+    """The fused-step check may take a feature rounded to its other bf16
+    neighbour only where the feature lies within the stated distance of a
+    rounding boundary: a feature planted on a boundary gets the alternative,
+    features far from any boundary get none."""
+    from closure_checks import bf16_alternatives
+    X = np.full((3, 27), 1.0 + 2.0 ** -8)  # 1 + half a bf16 ulp (2^-7 in [1, 2)): a tie
+    X[1] = 1.0 + 2.0 ** -9                 # a quarter ulp from 1: far from the boundaries
+    X[2] = 1.0 + 2.0 ** -9
+    X[2, 5] = 1.0 + 2.0 ** -8 + 1e-9      # just above the tie
+    alts = bf16_alternatives(X, np.full(X.shape, 1e-7))
+    assert set(alts) == {0, 2}
+    assert all(len(a) == 2 ** 4 - 1 for a in [alts[0]])  # ties in every column: the first four flipped
+    (only,) = alts[2]
+    assert np.flatnonzero(only != C.round_bf16(X[2])).tolist() == [5]
+    assert {C.round_bf16(X[2])[5], only[5]} == {1.0, 1.0 + 2.0 ** -7}

@@ -17,6 +17,7 @@ import oracle as O
 from oracle import closure_oracle as C
 from paper_2410_09739_amd import lbm as L
 from paper_2410_09739_amd import workloads as W
+from closure_checks import bf16_alternatives, explained_by_one_hidden_flip
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -31,65 +32,6 @@ def _params(seed, bias=0.1):
     b2 += bias * rng.standard_normal(64)
     b3 += bias * rng.standard_normal(6)
     return C.pack(W1, b1, W2, b2, W3, b3).astype(np.float32).astype(np.float64)
-
-
-def _bf16_alternatives(X, xtol, max_flips=4):
-    """Nodes with features within xtol of a bf16 rounding boundary, and for each
-    the feature vectors with every combination of those features rounded to the
-    other side (at most 2^max_flips per node)."""
-    q = C.round_bf16(X)
-    lo, hi = C.round_bf16(X - xtol), C.round_bf16(X + xtol)
-    out = {}
-    for i in np.flatnonzero(np.any((lo != q) | (hi != q), axis=1)):
-        cols = np.flatnonzero((lo[i] != q[i]) | (hi[i] != q[i]))[:max_flips]
-        cands = []
-        for m in range(1, 1 << len(cols)):
-            x = q[i].copy()
-            for b, k in enumerate(cols):
-                if m >> b & 1:
-                    x[k] = lo[i, k] if lo[i, k] != q[i, k] else hi[i, k]
-            cands.append(x)
-        out[int(i)] = cands
-    return out
-
-
-def _explained_by_one_hidden_flip(p, x, got, tol):
-    """True if some network that differs from the oracle's bf16 forward only in
-    one hidden activation rounded to its other bf16 neighbour gives got (within
-    tol).  A unit is a candidate when its pre-activation, known to FP32
-    accumulation accuracy, may lie on either side of a bf16 rounding boundary."""
-    W1, b1, W2, b2, W3, b3 = C.unpack(p)
-    W1q, W2q, W3q = C.round_bf16(W1), C.round_bf16(W2), C.round_bf16(W3)
-    b1f, b2f, b3f = (b.astype(np.float32).astype(np.float64) for b in (b1, b2, b3))
-    xq = C.round_bf16(x)
-
-    def other(z, mag):
-        d = 64 * 2.0 ** -24 * mag  # FP32 accumulation of up to 64 products
-        r = lambda v: C.round_bf16(np.maximum(v, 0.0))  # noqa: E731  (ReLU, then bf16)
-        lo, hi, q = r(z - d), r(z + d), r(z)
-        return np.where(lo != q, lo, np.where(hi != q, hi, np.nan))
-
-    def layer2_on(h1):
-        z2 = h1 @ W2q.T + b2f
-        return z2, C.round_bf16(np.maximum(z2, 0.0)), np.abs(h1) @ np.abs(W2q).T + np.abs(b2f)
-
-    z1 = xq @ W1q.T + b1f
-    h1 = C.round_bf16(np.maximum(z1, 0.0))
-    z2, h2, m2 = layer2_on(h1)
-    alt1 = other(z1, np.abs(xq) @ np.abs(W1q).T + np.abs(b1f))
-    alt2 = other(z2, m2)
-    for k in np.flatnonzero(~np.isnan(alt2)):
-        h = h2.copy()
-        h[k] = alt2[k]
-        if np.all(np.abs(h @ W3q.T + b3f - got) <= tol):
-            return True
-    for k in np.flatnonzero(~np.isnan(alt1)):
-        h = h1.copy()
-        h[k] = alt1[k]
-        _, hh2, _ = layer2_on(h)
-        if np.all(np.abs(hh2 @ W3q.T + b3f - got) <= tol):
-            return True
-    return False
 
 
 def _dev(a):
@@ -130,7 +72,7 @@ def test_mfma_inference_matches_bf16_oracle(n):
     print(f"{off.size} of {n} nodes beyond the FP32 level")
     assert off.size <= 0.01 * n
     for i in off:
-        assert _explained_by_one_hidden_flip(p, X[i].astype(np.float64), got[i], 1e-5 * scale), i
+        assert explained_by_one_hidden_flip(p, X[i].astype(np.float64), got[i], 1e-5 * scale), i
     # and close to the exact network as well (BF16 quantisation only)
     exact, _ = C.forward(p, X)
     assert np.sqrt(np.mean((got - exact) ** 2)) <= 3e-2 * scale
@@ -428,7 +370,7 @@ def test_fused_closure_step_matches_oracle(storage, tol, shape, oh):
     # within 1e-7 of the feature's range (FP32 moments of order-0.1 values).
     eps = 1e-13 if storage == "f64" else 1e-7
     xtol = np.maximum(eps * np.abs(X).max(0), 2.0 * np.spacing(np.abs(X).astype(np.float32)))
-    alts = _bf16_alternatives(X, np.where(X == 0.0, 0.0, xtol))
+    alts = bf16_alternatives(X, np.where(X == 0.0, 0.0, xtol))
     g27 = got.reshape(27, -1)
     for i in np.flatnonzero(~ok):
         for Xi in alts.get(i, []):
