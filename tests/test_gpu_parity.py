@@ -511,6 +511,56 @@ def test_channel_sampled_nodes_f32(shape):
     assert ratio <= 1.0, ratio
 
 
+@pytest.mark.parametrize("case,storage", [("cavity", "f64"), ("cavity", "f32"), ("half_channel", "f32")])
+def test_cavity_and_half_channel_full_size_sampled_nodes(case, storage):
+    """The Sec. 4 configurations at the sizes their studies run: the lid-driven
+    cubic cavity 150^3 at Re 1000 (walls on every face, the lid moving in x:
+    three segments per row, the last one ragged) and the half channel
+    628 x 100 x 314 at Re_tau 180 (wall, specular symmetry plane, body force,
+    Smagorinsky rates with van Driest damping).  A few steps from a random
+    (cavity) or perturbed laminar (channel) state, then one more: at sampled
+    nodes (faces, edges, corners, interior) the update matches the oracle's
+    single-node step from the GPU's own previous state."""
+    if case == "cavity":
+        n, U = 150, 0.05
+        nx = ny = nz = n
+        nu, F, les = U * n / 1000.0, (0.0, 0.0, 0.0), None
+        rho, u = W.random_fields(n, n, n, seed=150, u_amp=0.02)
+        cfg = L.Config(n, n, n, storage=storage, nu=nu, walls_x=True, walls_y=True, walls_z=True,
+                       lid_velocity=(U, 0.0, 0.0))
+        walls, lid = "xyz", (U, 0.0, 0.0)
+    else:
+        H, ut = 100, 0.0075
+        nx, ny, nz = 628, H, 314
+        nu, F = ut * H / 180.0, (ut * ut / H, 0.0, 0.0)
+        les = (0.1, ut / nu, 26.0)
+        rho, u = W.channel_turbulent_start(nx, ny, nz, u_bulk=15.7 * ut, amp=0.3, seed=1234, kmax=3)
+        cfg = L.Config(nx, ny, nz, storage=storage, walls_y=True, sym_top=True, nu=nu, force=F,
+                       les_cs=les[0], les_wall_units=les[1], les_aplus=les[2])
+        walls, lid = "ys", None
+    rng = np.random.default_rng(3)
+    sel = np.unique(np.concatenate([
+        rng.integers(0, nx * ny * nz, 3000),
+        np.array([(z * ny + y) * nx + x for x in (0, 1, 63, 64, nx - 1) for y in (0, 1, ny - 1) for z in (0, nz - 1)]),
+    ]))
+    om = O.omega_table(nu)
+    with L.Lattice(cfg) as lat:
+        lat.init(rho, u)
+        del rho, u
+        lat.step(4)
+        g_prev = lat.get_f()
+        lat.step(1)
+        g_next = lat.get_f().reshape(27, -1)[:, sel]
+    ref = O.step_nodes(g_prev, sel, om, F, walls=walls, lid=lid, les=les)
+    del g_prev
+    if storage == "f64":
+        err = float((np.abs(g_next - ref) / np.maximum(np.abs(ref), W_ALPHA.reshape(27, 1))).max())
+        assert err <= 1e-12, err
+    else:
+        ratio = float((np.abs(g_next - ref) / (8e-7 * W_ALPHA.reshape(27, 1))).max())
+        assert ratio <= 1.0, ratio
+
+
 @pytest.mark.parametrize("storage,mant", [("f16dev", 10), ("bf16dev", 7)])
 def test_channel_sampled_nodes_16bit(storage, mant):
     """The benchmark channel 256 x 128 x 128 in FP16 / BF16 deviation storage
