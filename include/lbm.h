@@ -264,7 +264,8 @@ void lbm_destroy(lbm_ctx* c);
 const char* lbm_last_error(const lbm_ctx* c);
 
 /* ---------------------------------------------------------------------------
- * Learned second-order closure (not part of the paper; see the design notes).
+ * Learned second-order closure (not part of the paper: a learned eddy
+ * viscosity on top of its second-order relaxation).
  * A per-node network 27 -> 64 -> 64 -> 6 (ReLU hidden layers) maps features of
  * the node's pre-collision central moments (Appendix D Step 2) to eddy
  * viscosities nu_t,j of the six second-order groups relaxed with omega_4..9

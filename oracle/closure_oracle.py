@@ -2,8 +2,8 @@
 
 Only tests/, the smoke check and the benchmark's cpu_baseline leg may import
 this module; it never imports the product path.  The paper has no learned
-closure: every function here states the reading the library implements (the
-design notes list the same readings), in plain numpy, one definition at a time.
+closure: every function here states the reading the library implements, in
+plain numpy, one definition at a time.
 
 Network (per node): x in R^27 -> h1 = relu(W1 x + b1) (64) -> h2 = relu(W2 h1 + b2)
 (64) -> o = W3 h2 + b3 (6).  Parameters are one flat vector in the order

@@ -662,7 +662,8 @@ def test_taylor_green_512_sampled_nodes(storage):
 def test_small_force_momentum_is_kept_by_stochastic_rounding(storage, tol):
     """A body force far below half an ulp of the stored deviations: with
     stochastic rounding the total momentum still grows by N F per step on
-    average (round-to-nearest loses most of it; see the design notes)."""
+    average (round-to-nearest loses most of it: an increment below half an ulp
+    of the stored deviation rounds away at every step)."""
     shape = (64, 16, 16)
     F = (2e-7, 0.0, 0.0)
     with L.Lattice(L.Config(*shape, storage=storage, nu=0.05, force=F)) as lat:
