@@ -22,12 +22,19 @@
  * the binomial theorem, and the collision follows Appendix D Step 3 in the
  * paper's order and notation.  No blocking, fusion or factorisation.
  *
- * Readings where the paper is garbled or silent (each also listed in the design
- * notes of the repository):
+ * Readings where the paper is garbled or silent (the tests and the Python side
+ * cite them by these labels):
+ *   R2  the equilibrium (initial state, not defined in the paper) is the set of
+ *       populations whose central moments are the attractors at rest in the
+ *       moving frame, kappa_abc = rho c_a c_b c_c with c = (1, 0, c_s^2): the
+ *       discrete Maxwellian, equal to the product form rho prod_d phi(e_d, u_d).
  *   R3  kappa^Mv_122 is evaluated from the general attractor formula, which
  *       yields the product kappa~_110 kappa~_012 (the printed closed form shows
  *       kappa~_011 kappa~_012 there; the continuous form in Sec. 3.4 agrees with
  *       the general formula).
+ *   R6  P^-1 is the exact inverse of P; the printed Step 5 row of f~_4
+ *       (e_4 = (0, -1, 0)) carries +kappa~'_010 where the exact inverse has
+ *       -kappa~'_010 (all other printed rows agree with it).
  *   R7  the third-order decomposition assigns (3s3 - 3m3)/2 to kappa~_021.
  *   R8  sources use the pre-collision central moments with kappa_000 = rho and
  *       the first-order central moments taken as zero (as the 2D source list in
