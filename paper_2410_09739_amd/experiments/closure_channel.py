@@ -9,6 +9,7 @@ velocity of each, the wall time of each, and the trained parameters (.npy).
 
     python -m paper_2410_09739_amd.experiments.closure_channel [--tstar-transient 6] [--tstar-stats 6]
         [--shape 256,128,128] [--seeds 3] [--gains 1,3] [--coarse-storage f32,f16dev]
+        [--refine 1 --calibrate] [--load-params trained.npy --flow-seed 4321]
 
 Time unit T* = h / u_tau (38,400 fine steps).  The fine run gives a snapshot
 every T*/2 of its statistics window (the last one held out of training).  The
@@ -154,9 +155,12 @@ def main(argv=None) -> dict:
                     help="a-posteriori passes: coarse run with the network, targets from the mean momentum "
                          "balance of that run, retraining (first network only)")
     ap.add_argument("--refine-relax", type=float, default=0.5, help="under-relaxation of the refined targets")
-    ap.add_argument("--refine-groups", default="110,101,011",
+    ap.add_argument("--refine-groups", default="110",
                     help="off-diagonal groups that take the refined target, the others 0 (the mean momentum "
-                         "balance fixes the x-y shear viscosity only; 110 alone is the variant)")
+                         "balance fixes the x-y shear viscosity only; 110,101,011 gives it to all three)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="scale the first network's output so that the coarse run on the training start has the "
+                         "filtered fine bulk velocity (linear between the plain run and the unscaled network)")
     ap.add_argument("--load-params", default=None,
                     help="closure parameters (.npy) to evaluate instead of training: a network from another start")
     args = ap.parse_args(argv)
@@ -312,6 +316,19 @@ def main(argv=None) -> dict:
             out["refine"].append({"pass": it, "run_rel_l2_U": err, "run_u_bulk_over_u_tau": float(np.mean(c_ub) / ut),
                                   "target_nu_t_over_nu_c": [round(float(v), 4) for v in nut / (nu_f / 2)],
                                   "loss_after": l1})
+    # ---- output gain of the first network: on the training start, the scale g
+    # that brings the coarse run's bulk velocity to the filtered fine run's,
+    # interpolated linearly between the plain run (g = 0) and the network (g = 1)
+    out["calibration"] = None
+    if args.calibrate and not args.load_params:
+        _, ub0, _, _ = coarse_run(cforms[0], None, "calibrate g=0")
+        _, ub1, _, _ = coarse_run(cforms[0], nets[0], "calibrate g=1")
+        u0, u1, uf = float(np.mean(ub0)), float(np.mean(ub1)), float(np.mean(f_ub))
+        g = float(np.clip((u0 - uf) / (u0 - u1), 0.1, 2.0)) if u0 != u1 else 1.0
+        nets[0] = scaled_output(nets[0], g)
+        out["calibration"] = {"gain": g, "u_bulk_over_u_tau_plain": u0 / ut, "u_bulk_over_u_tau_g1": u1 / ut,
+                              "u_bulk_over_u_tau_fine": uf / ut}
+        log(f"calibration: U_b/u_tau plain {u0 / ut:.3f}, network {u1 / ut:.3f}, fine {uf / ut:.3f} -> gain {g:.3f}")
     np.save(args.save_params, scaled_output(nets[0], gains[0]))
     del X, Y, xs, ys
     res = {}

@@ -636,15 +636,16 @@ def test_refined_closure_lowers_the_mean_profile_error_on_a_held_out_start(tmp_p
     """What the trained network gains, a posteriori.  The network kept in the
     repository was trained on a turbulent channel started from one random
     perturbation (seed 1234): a-priori targets from the filtered fine run, then
-    one pass of mean-momentum-balance targets from its own coarse run (the
-    closure study's --refine 1).  Here it runs on a channel it has never seen
-    (seed 4321): fine 256 x 128 x 128 at Re_tau = 180 for 12 T*, coarse
-    128 x 64 x 64 in FP16 deviation storage for 40 T* with statistics over the
-    last 32, plain and with the fused closure, both against the box-filtered
-    fine run.  Measured in the study: U(y) relative L2 error 0.134 (plain) and
-    0.039 (closure), bulk velocity 18.17 and 15.65 u_tau against 16.06; the
-    velocity fluctuations get worse (rms errors 0.10-0.13 -> 0.25-0.27), which
-    is printed, not asserted."""
+    one pass of mean-momentum-balance targets for the x-y shear group from its
+    own coarse run, and an output gain that gives that coarse run the filtered
+    fine bulk velocity (the closure study's --refine 1 --calibrate).  Here it
+    runs on a channel it has never seen (seed 4321): fine 256 x 128 x 128 at
+    Re_tau = 180 for 12 T*, coarse 128 x 64 x 64 in FP16 deviation storage for
+    40 T* with statistics over the last 32, plain and with the fused closure,
+    both against the box-filtered fine run.  Measured in the study: U(y)
+    relative L2 error 0.134 (plain) and 0.020 (closure), bulk velocity 18.17 and
+    15.94 u_tau against 16.06, rms error of u 0.130 and 0.100; those of v and w
+    0.100/0.090 and 0.125/0.106 (printed, not asserted)."""
     import os
     from paper_2410_09739_amd.experiments import closure_channel as CC
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2410_09739_amd",
@@ -658,5 +659,6 @@ def test_refined_closure_lowers_the_mean_profile_error_on_a_held_out_start(tmp_p
           f"U_b/u_tau: fine {ub_f:.3f}, plain {plain['u_bulk_over_u_tau']:.3f}, closure {cl['u_bulk_over_u_tau']:.3f}; "
           f"rms errors plain {[round(plain[f'rel_l2_{q}_rms_vs_filtered_fine'], 3) for q in 'uvw']}, "
           f"closure {[round(cl[f'rel_l2_{q}_rms_vs_filtered_fine'], 3) for q in 'uvw']}")
-    assert cl["rel_l2_U_vs_filtered_fine"] <= 0.6 * plain["rel_l2_U_vs_filtered_fine"]
+    assert cl["rel_l2_U_vs_filtered_fine"] <= 0.4 * plain["rel_l2_U_vs_filtered_fine"]
     assert abs(cl["u_bulk_over_u_tau"] - ub_f) < abs(plain["u_bulk_over_u_tau"] - ub_f)
+    assert cl["rel_l2_u_rms_vs_filtered_fine"] <= 1.1 * plain["rel_l2_u_rms_vs_filtered_fine"]
