@@ -113,6 +113,30 @@ def run_closure_form(L, torch, storage, shape, nu, F, steps, warmup, params):
     return {"mlups": n / (ms * 1e-3) / 1e6, "ms_per_step": ms, "finite": d["n_nonfinite"] == 0}
 
 
+def closure_cost_at_equal_error(cg: dict, form: str = "f16dev+closure"):
+    """Cost of plain FP32 at the closure form's mean-flow error, over the
+    closure form's cost, on the coarse channel 192 x 96 x 96.  The errors are
+    those the closure study measured on held-out starts (data file, with the
+    command that produced them); the rates are this run's.  Plain runs' error
+    goes as dx^p between the two coarse grids, so plain FP32 reaches the
+    closure's error on a grid r = (e_plain / e_closure)^(1/p) times finer per
+    direction; at equal physical time that costs r^4 (nodes r^3, acoustic steps
+    r) at the plain FP32 rate, against the closure form at its own rate."""
+    path = os.path.join(ROOT, "paper_2410_09739_amd", "data", "closure_channel_errors.json")
+    if not os.path.exists(path) or "f32" not in cg or form not in cg:
+        return None
+    d = json.load(open(path))
+    g1, g0 = d["grids"]["192x96x96"], d["grids"]["128x64x64"]
+    e_plain, e_cl = float(np.mean(g1["plain_f32"])), float(np.mean(g1["closure_f16dev"]))
+    p = float(np.log(np.mean(g0["plain_f32"]) / e_plain) / np.log(1.5))
+    r = (e_plain / e_cl) ** (1.0 / p)
+    return {"grid": "channel_192x96x96", "form": form, "U_error_closure": round(e_cl, 4),
+            "U_error_plain_f32": round(e_plain, 4), "plain_error_order": round(p, 3),
+            "plain_refinement_for_equal_error": round(r, 3),
+            "plain_f32_cost_over_closure_cost": round(r ** 4 * cg[form]["mlups"] / cg["f32"]["mlups"], 2),
+            "errors_from": d["command"]}
+
+
 def copy_calibration(torch, nbytes: int = 1 << 31, reps: int = 5):
     """A plain device copy of known size, to scale the HBM byte counters."""
     x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -241,6 +265,11 @@ def main():
                 cg[key] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cg[key].items()}
             cg["steps"] = csteps
             closure[gname] = cg
+        cost = closure_cost_at_equal_error(closure["channel_192x96x96"])
+        if cost is not None:
+            closure["cost_at_equal_error"] = cost
+            print(f"# closure cost at equal mean-flow error: plain FP32 / {cost['form']} = "
+                  f"{cost['plain_f32_cost_over_closure_cost']}", file=sys.stderr, flush=True)
 
     main_form = results["f32"]
     roof = {"bound": "hbm", "achieved": round(main_form["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,

@@ -54,3 +54,10 @@ def test_bench_prints_one_json_line_with_roofline_and_cpu_baseline():
         cf = d["closure_forms"][g]
         assert cf["f32"]["vs_f32_plain"] == 1.0
         assert all(cf[k]["finite"] for k in cf if k != "steps")
+    # cost of plain FP32 at the closure's mean-flow error over the closure form's
+    cost = d["closure_forms"]["cost_at_equal_error"]
+    r = cost["plain_refinement_for_equal_error"]
+    assert r > 1.0 and cost["U_error_closure"] < cost["U_error_plain_f32"]
+    mlups = d["closure_forms"]["channel_192x96x96"]
+    assert cost["plain_f32_cost_over_closure_cost"] == pytest.approx(
+        r ** 4 * mlups["f16dev+closure"]["mlups"] / mlups["f32"]["mlups"], rel=1e-2)
