@@ -159,8 +159,9 @@ def main(argv=None) -> dict:
                     help="off-diagonal groups that take the refined target, the others 0 (the mean momentum "
                          "balance fixes the x-y shear viscosity only; 110,101,011 gives it to all three)")
     ap.add_argument("--calibrate", action="store_true",
-                    help="scale the first network's output so that the coarse run on the training start has the "
-                         "filtered fine bulk velocity (linear between the plain run and the unscaled network)")
+                    help="scale the first network's output (first network only) so that the coarse run on the "
+                         "training start has the filtered fine bulk velocity (linear between the plain run and the "
+                         "unscaled network)")
     ap.add_argument("--load-params", default=None,
                     help="closure parameters (.npy) to evaluate instead of training: a network from another start")
     args = ap.parse_args(argv)
