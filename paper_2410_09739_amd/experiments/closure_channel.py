@@ -128,6 +128,16 @@ def balance_eddy_viscosity(prof_c: dict, filt: dict, u_tau: float, nu: float, ca
     return np.clip(nut, 0.0, cap)
 
 
+def output_gain(u_plain: float, u_net: float, u_fine: float, lo: float = 0.1, hi: float = 2.0) -> float:
+    """Scale g of the network output that gives the coarse run the fine bulk
+    velocity, with the bulk velocity taken linear in g between the plain run
+    (g = 0) and the unscaled network (g = 1); clipped to [lo, hi], 1 when the
+    network does not move the bulk velocity."""
+    if u_plain == u_net:
+        return 1.0
+    return float(np.clip((u_plain - u_fine) / (u_plain - u_net), lo, hi))
+
+
 def main(argv=None) -> dict:
     ap = argparse.ArgumentParser()
     ap.add_argument("--shape", default="384,192,192")
@@ -325,7 +335,7 @@ def main(argv=None) -> dict:
         _, ub0, _, _ = coarse_run(cforms[0], None, "calibrate g=0")
         _, ub1, _, _ = coarse_run(cforms[0], nets[0], "calibrate g=1")
         u0, u1, uf = float(np.mean(ub0)), float(np.mean(ub1)), float(np.mean(f_ub))
-        g = float(np.clip((u0 - uf) / (u0 - u1), 0.1, 2.0)) if u0 != u1 else 1.0
+        g = output_gain(u0, u1, uf)
         nets[0] = scaled_output(nets[0], g)
         out["calibration"] = {"gain": g, "u_bulk_over_u_tau_plain": u0 / ut, "u_bulk_over_u_tau_g1": u1 / ut,
                               "u_bulk_over_u_tau_fine": uf / ut}

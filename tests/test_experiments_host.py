@@ -32,3 +32,18 @@ def test_balance_eddy_viscosity_recovers_a_prescribed_profile(ny):
     assert np.all(steep == 0.0)
     capped = CC.balance_eddy_viscosity({"uv": np.zeros(ny)}, {"U": 0.01 * U}, ut, nu, cap=2 * nu)
     assert np.all(capped[1:-1] == 2 * nu)
+
+
+def test_output_gain_interpolates_the_bulk_velocity_linearly():
+    """The closure study's output gain: with U_b(g) = U_plain + g (U_net - U_plain),
+    the g that gives the fine U_b; the measured case of the 192 x 96 x 96 grid
+    (plain 16.671, network 13.764, fine 15.729 u_tau) gives 0.324; outside
+    [0.1, 2] it is clipped, and a network that leaves U_b unchanged keeps g = 1."""
+    from paper_2410_09739_amd.experiments.closure_channel import output_gain
+    for up, un, uf in [(18.0, 16.0, 16.5), (16.671, 13.764, 15.729), (10.0, 12.0, 11.0)]:
+        g = output_gain(up, un, uf)
+        assert up + g * (un - up) == pytest.approx(uf, rel=1e-12)
+    assert output_gain(16.671, 13.764, 15.729) == pytest.approx(0.324, abs=5e-4)
+    assert output_gain(18.0, 17.9, 10.0) == 2.0
+    assert output_gain(18.0, 16.0, 18.5) == 0.1
+    assert output_gain(18.0, 18.0, 16.0) == 1.0
