@@ -122,10 +122,17 @@ def closure_cost_at_equal_error(cg: dict, form: str = "f16dev+closure"):
     closure's error on a grid r = (e_plain / e_closure)^(1/p) times finer per
     direction; at equal physical time that costs r^4 (nodes r^3, acoustic steps
     r) at the plain FP32 rate, against the closure form at its own rate."""
-    path = os.path.join(ROOT, "paper_2410_09739_amd", "data", "closure_channel_errors.json")
+    import hashlib
+    data = os.path.join(ROOT, "paper_2410_09739_amd", "data")
+    path = os.path.join(data, "closure_channel_errors.json")
     if not os.path.exists(path) or "f32" not in cg or form not in cg:
         return None
     d = json.load(open(path))
+    # the errors hold for the networks they were measured with
+    for name, sha in d.get("networks_sha256", {}).items():
+        f = os.path.join(data, name)
+        if not os.path.exists(f) or hashlib.sha256(open(f, "rb").read()).hexdigest() != sha:
+            return None
     g1, g0 = d["grids"]["192x96x96"], d["grids"]["128x64x64"]
     e_plain, e_cl = float(np.mean(g1["plain_f32"])), float(np.mean(g1["closure_f16dev"]))
     p = float(np.log(np.mean(g0["plain_f32"]) / e_plain) / np.log(1.5))

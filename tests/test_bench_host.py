@@ -56,3 +56,16 @@ def test_source_hash_ignores_comments_but_not_code():
     assert P._code_only(a) == P._code_only(b)
     assert P._code_only(a) != P._code_only(c)
     assert '"// kept /* too */"' in P._code_only(a)
+
+
+def test_closure_errors_file_matches_the_kept_networks():
+    """The benchmark's closure cost at equal error uses the study's held-out
+    errors only while the kept networks are the ones they were measured with
+    (else it reports nothing): a retrained network must come with new errors."""
+    import hashlib
+    import json
+    data = os.path.join(ROOT, "paper_2410_09739_amd", "data")
+    d = json.load(open(os.path.join(data, "closure_channel_errors.json")))
+    assert set(d["networks_sha256"]) == {"closure_channel_192x96x96.npy", "closure_channel_128x64x64_refined.npy"}
+    for name, sha in d["networks_sha256"].items():
+        assert hashlib.sha256(open(os.path.join(data, name), "rb").read()).hexdigest() == sha, name
