@@ -4,6 +4,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -69,3 +70,34 @@ def test_closure_errors_file_matches_the_kept_networks():
     assert set(d["networks_sha256"]) == {"closure_channel_192x96x96.npy", "closure_channel_128x64x64_refined.npy"}
     for name, sha in d["networks_sha256"].items():
         assert hashlib.sha256(open(os.path.join(data, name), "rb").read()).hexdigest() == sha, name
+
+
+def test_closure_cost_at_equal_error_follows_its_definition(tmp_path, monkeypatch):
+    """cost = r^4 x (closure MLUPS / plain FP32 MLUPS) with r = (e_plain /
+    e_closure)^(1/p), p from the plain errors of the two coarse grids (spacing
+    ratio 1.5); nothing when a network's hash does not match its errors."""
+    import importlib.util
+    import json
+    import shutil
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    data = tmp_path / "paper_2410_09739_amd" / "data"
+    data.mkdir(parents=True)
+    src = os.path.join(ROOT, "paper_2410_09739_amd", "data")
+    for name in ("closure_channel_192x96x96.npy", "closure_channel_128x64x64_refined.npy"):
+        shutil.copy(os.path.join(src, name), data / name)
+    d = json.load(open(os.path.join(src, "closure_channel_errors.json")))
+    d["grids"] = {"192x96x96": {"plain_f32": [0.06, 0.06], "closure_f16dev": [0.02, 0.02]},
+                  "128x64x64": {"plain_f32": [0.135, 0.135], "closure_f16dev": [0.03, 0.03]}}
+    (data / "closure_channel_errors.json").write_text(json.dumps(d))
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    cg = {"f32": {"mlups": 26000.0}, "f16dev+closure": {"mlups": 13000.0}}
+    c = b.closure_cost_at_equal_error(cg)
+    p = np.log(0.135 / 0.06) / np.log(1.5)  # = 2 exactly: errors go as dx^2
+    assert c["plain_error_order"] == pytest.approx(p, abs=1e-3) and p == pytest.approx(2.0)
+    assert c["plain_refinement_for_equal_error"] == pytest.approx(3.0 ** 0.5, abs=1e-3)
+    assert c["plain_f32_cost_over_closure_cost"] == pytest.approx(9.0 * 0.5, rel=1e-3)
+    d["networks_sha256"]["closure_channel_192x96x96.npy"] = "0" * 64
+    (data / "closure_channel_errors.json").write_text(json.dumps(d))
+    assert b.closure_cost_at_equal_error(cg) is None
