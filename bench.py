@@ -154,6 +154,26 @@ def copy_calibration(torch, nbytes: int = 1 << 31, reps: int = 5):
     print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}), flush=True)
 
 
+def copy_bandwidth(torch, nbytes: int = 1 << 31, reps: int = 10) -> float:
+    """GB/s of a plain device-to-device copy (torch, nbytes read and nbytes
+    written per copy), timed with events after two untimed copies: the rate a
+    simple streaming kernel reaches on this GPU, beside the published peak."""
+    x = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        y.copy_(x)
+    end.record()
+    end.synchronize()
+    gbs = 2.0 * nbytes * reps / (start.elapsed_time(end) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_baseline(n, nu, planes, steps):
     """The FP64 oracle on the first ``planes`` z-planes of the same n^3 field
     (periodic in z over the slab): the work per node is that of the full box."""
@@ -310,6 +330,11 @@ def main():
                   for k, v in results.items()},
         "closure_forms": closure,
     }
+    cgbs = copy_bandwidth(torch)
+    line["copy_reference"] = {"copy_GBs": round(cgbs, 1), "f32_achieved_over_copy": round(roof["achieved"] / cgbs, 4),
+                              "what": "torch device-to-device copy of 2 GiB (read + write counted), 10 timed copies"}
+    print(f"# plain device copy: {cgbs:.0f} GB/s; FP32 step at {roof['achieved'] / cgbs:.3f} of it",
+          file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         mlups, dt, cores = cpu_baseline(n, nu, args.cpu_planes, args.cpu_steps)
         line["cpu_baseline"] = {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",

@@ -54,6 +54,9 @@ def test_bench_prints_one_json_line_with_roofline_and_cpu_baseline():
         cf = d["closure_forms"][g]
         assert cf["f32"]["vs_f32_plain"] == 1.0
         assert all(cf[k]["finite"] for k in cf if k != "steps")
+    cr = d["copy_reference"]
+    assert 1000 < cr["copy_GBs"] < 8000
+    assert cr["f32_achieved_over_copy"] == pytest.approx(roof["achieved"] / cr["copy_GBs"], rel=1e-3)
     # cost of plain FP32 at the closure's mean-flow error over the closure form's
     cost = d["closure_forms"]["cost_at_equal_error"]
     r = cost["plain_refinement_for_equal_error"]
